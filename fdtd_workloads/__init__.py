@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the oracle tests, the HIP parity tests and bench.py.
+
+This module holds no arithmetic of the method: only the problem descriptions
+(grid sizes, spacings, material constants, box positions, band edges) and the
+seeded density generator.  Every derived quantity (time step, absorber
+profiles, incident-field tables, DFT phasors, weights, update coefficients) is
+computed separately by each implementation.
+
+Workloads follow the problem statement of the paper (Sec. 2, eqs. (1)-(5)):
+a Yee grid, a per-cell density rho in [0,1] on a design box that interpolates
+between the background dielectric and a Drude metal, a gap region where the
+field is observed, a plane-wave pulse and an objective on the DFT of the gap
+field over a band.  The paper's own geometries need its optimized designs; the
+densities here are seeded box-smoothed uniform noise of the same shape.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+# Drude and dielectric constants of the synthetic workloads.
+DRUDE = dict(eps_inf=1.0, omega_p=1.37e16, gamma_p=4.08e13)
+# The paper's silver fit over 350-1000 nm (Sec. 2): eps_inf, omega_p, gamma_p.
+SILVER_PAPER = dict(eps_inf=4.469, omega_p=1.426e16, gamma_p=4.571e13)
+
+_COMMON = dict(
+    courant=0.5,
+    pml_order=3.0,
+    pml_sigma_scale=1.0,
+    pml_kappa_max=1.0,
+    pml_alpha_max=0.0,
+    eps_s=2.25,
+    eps_g=2.25,
+    gamma_mult=1.0,
+    sigma_max=0.0,
+    psi_s_ratio=0.01,
+    source="gauss",
+    t0_over_tau=4.0,
+    amplitude=1.0,
+    objective="dft",
+    weights="enhancement",
+    freqs_hz=None,
+    periodic_x=False,
+    **DRUDE,
+)
+
+
+def _centered(n, m):
+    return (n - m) // 2
+
+
+def c1():
+    """2D TMz FP64 200x200, dx=5 nm, 20-cell CPML, 60x60 design, point gap, 2000 steps, K=8."""
+    w = dict(_COMMON)
+    w.update(name="tmz2d_200_fp64", dims=2, precision=64, n=(200, 200, 1), dx=5e-9,
+             n_steps=2000, pml_cells=20, tfsf_margin=5,
+             design_lo=(70, 70, 0), design_n=(60, 60, 1),
+             gap_lo=(100, 100, 0), gap_n=(1, 1, 1),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=8)
+    return w
+
+
+def c2(gamma_mult=1.0):
+    """2D TMz FP32 2048x2048, dx=2 nm, 32-cell CPML, 512x512 design, 5x5 gap, 20000 steps, K=16."""
+    w = dict(_COMMON)
+    w.update(name="tmz2d_2048_fp32", dims=2, precision=32, n=(2048, 2048, 1), dx=2e-9,
+             n_steps=20000, pml_cells=32, tfsf_margin=8,
+             design_lo=(768, 768, 0), design_n=(512, 512, 1),
+             gap_lo=(1022, 1022, 0), gap_n=(5, 5, 1),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=16, gamma_mult=gamma_mult)
+    return w
+
+
+def c3():
+    """3D FP32 256^3, dx=2 nm, 16-cell CPML, 128x128x32 slab, 4^3 gap, x-pol along +z, 8000 steps, K=16."""
+    w = dict(_COMMON)
+    w.update(name="yee3d_256_fp32", dims=3, precision=32, n=(256, 256, 256), dx=2e-9,
+             n_steps=8000, pml_cells=16, tfsf_margin=6,
+             design_lo=(64, 64, 112), design_n=(128, 128, 32),
+             gap_lo=(126, 126, 126), gap_n=(4, 4, 4),
+             lambda_lo=600e-9, lambda_hi=900e-9, n_freq=16)
+    return w
+
+
+def tiny2d(**over):
+    """Small 2D TMz case exercising every feature: CPML, plane wave, Drude design, gap."""
+    w = dict(_COMMON)
+    w.update(name="tmz2d_tiny", dims=2, precision=64, n=(40, 44, 1), dx=5e-9,
+             n_steps=1100, pml_cells=6, tfsf_margin=2, t0_over_tau=3.0,
+             design_lo=(14, 16, 0), design_n=(12, 12, 1),
+             gap_lo=(19, 21, 0), gap_n=(2, 2, 1),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=4,
+             sigma_max=5e5, gamma_mult=4.0)
+    w.update(over)
+    return w
+
+
+def tiny3d(**over):
+    """Small 3D case exercising every feature."""
+    w = dict(_COMMON)
+    w.update(name="yee3d_tiny", dims=3, precision=64, n=(22, 22, 26), dx=5e-9,
+             n_steps=900, pml_cells=5, tfsf_margin=2, t0_over_tau=3.0,
+             design_lo=(7, 7, 10), design_n=(8, 8, 6),
+             gap_lo=(10, 10, 12), gap_n=(2, 2, 2),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=4,
+             sigma_max=5e5, gamma_mult=4.0)
+    w.update(over)
+    return w
+
+
+PRESETS = {"c1": c1, "c2": c2, "c3": c3, "tiny2d": tiny2d, "tiny3d": tiny3d}
+
+
+def with_(w, **over):
+    """Copy of workload ``w`` with fields replaced."""
+    x = copy.deepcopy(w)
+    x.update(over)
+    return x
+
+
+def design_shape(w):
+    """Array shape of the density over the design box: [z][y][x] in 3D, [y][x] in 2D."""
+    nx, ny, nz = w["design_n"]
+    return (nz, ny, nx) if w["dims"] == 3 else (ny, nx)
+
+
+def box_smooth(a):
+    """Mean over a 3-wide box along every axis with edge-replicate padding."""
+    p = np.pad(a, 1, mode="edge")
+    out = np.zeros_like(a)
+    if a.ndim == 2:
+        for dy in range(3):
+            for dx in range(3):
+                out += p[dy:dy + a.shape[0], dx:dx + a.shape[1]]
+        return out / 9.0
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                out += p[dz:dz + a.shape[0], dy:dy + a.shape[1], dx:dx + a.shape[2]]
+    return out / 27.0
+
+
+def seeded_rho(w, seed, kind="smooth"):
+    """Seeded density over the design box, float64.
+
+    kind: "smooth"  U[0,1) from ``numpy.random.default_rng(seed)``, box-smoothed, clipped;
+          "half"    rho = 0.5 everywhere (the paper's initial design);
+          "binary"  the smooth field thresholded at 0.5;
+          "zero"/"one" constant fields.
+    """
+    shape = design_shape(w)
+    if kind == "half":
+        return np.full(shape, 0.5)
+    if kind == "zero":
+        return np.zeros(shape)
+    if kind == "one":
+        return np.ones(shape)
+    r = np.random.default_rng(seed).random(shape)
+    r = np.clip(box_smooth(r), 0.0, 1.0)
+    if kind == "binary":
+        return (r >= 0.5).astype(np.float64)
+    if kind != "smooth":
+        raise ValueError(f"unknown density kind {kind!r}")
+    return r
+
+
+def cell_updates(w, include_adjoint=True):
+    """Cells x steps (x2 with the adjoint solve): the unit of the throughput metric."""
+    nx, ny, nz = w["n"]
+    cells = nx * ny * (nz if w["dims"] == 3 else 1)
+    return cells * w["n_steps"] * (2 if include_adjoint else 1)
