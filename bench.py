@@ -1,0 +1,173 @@
+"""Throughput benchmark of the Drude-FDTD forward + adjoint + gradient hot path.
+
+One step = set_density (device tensor) + forward solve + adjoint solve +
+gradient (device tensor) of one seeded density, i.e. one topology-optimization
+iteration.  The default workload is the 2D TMz FP32 case: 2048 x 2048 grid,
+dx = 2 nm, 32-cell CPML, 512 x 512 design box, 5 x 5 gap, 20000 steps, 16 DFT
+frequencies over 500-1000 nm; successive steps cycle the collision-rate
+multiplier through {1, 4, 16} (damping continuation).
+
+Prints ONE JSON line: the metric in Gcell-updates/s (grid cells x time steps x
+2 solves / wall time of the step), the roofline of the time-step kernel
+(algorithmic HBM bytes per launch / average launch time from HIP events on the
+library stream), and the CPU oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import fdtd_workloads as W  # noqa: E402
+
+METRIC = "Drude-FDTD fwd+adjoint Gcell-updates/s, % HBM roofline; time-to-design vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(w, adjoint):
+    """HBM bytes one launch of the fused step kernel must move at minimum:
+    every field array read once and written once; absorber memories over the
+    CPML strips; density, Drude current and history (forward: write;
+    adjoint: read, plus the FP64 sensitivity sum) over the design box."""
+    esz = 4 if w["precision"] == 32 else 8
+    nx, ny, nz = w["n"]
+    P = w["pml_cells"]
+    dnx, dny, dnz = w["design_n"]
+    if w["dims"] == 2:
+        cells = nx * ny
+        fields = 3
+        pml_cells = 2 * (2 * P) * (nx + ny)  # psi_E and psi_H per strip direction
+        design = dnx * dny
+        ncomp = 1
+    else:
+        cells = nx * ny * nz
+        fields = 6
+        pml_cells = 4 * (2 * P) * (ny * nz + nx * nz + nx * ny)
+        design = dnx * dny * dnz
+        ncomp = 3
+    b = cells * fields * 2 * esz + pml_cells * 2 * esz
+    if not adjoint:
+        b += design * (esz + ncomp * (2 * esz + esz))            # rho; J r/w + history write
+    else:
+        b += design * (esz + ncomp * (2 * esz + esz + 16))       # rho; J r/w + history read + FP64 sum r/w
+    return b
+
+
+def cpu_baseline(w, steps):
+    """The oracle as it stands, on the first `steps` steps of the workload."""
+    import oracle
+    ws = W.with_(w, n_steps=steps, precision=64)
+    o = oracle.Oracle(ws)
+    rho = W.seeded_rho(ws, 0)
+    t0 = time.perf_counter()
+    o.set_density(rho)
+    o.forward()
+    o.adjoint()
+    o.gradient()
+    dt = time.perf_counter() - t0
+    nx, ny, nz = w["n"]
+    cells = nx * ny * (nz if w["dims"] == 3 else 1)
+    o.close()
+    return {"value": cells * steps * 2 / dt / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{w['name']} grid, first {steps} of {w['n_steps']} steps, forward+adjoint+gradient, "
+                      f"FP64, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
+    ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path runs on a single device); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2203_01462_amd as P
+
+    torch.cuda.set_device(0)
+    base = W.PRESETS[args.workload]()
+    if args.n_steps:
+        base = W.with_(base, n_steps=args.n_steps)
+    gmults = [1.0, 4.0, 16.0] if args.workload == "c2" else [1.0]
+    stream = torch.cuda.Stream()
+    ctxs = [P.FDTD(W.with_(base, gamma_mult=g), stream=stream.cuda_stream) for g in gmults]
+    dt_np = np.float32 if base["precision"] == 32 else np.float64
+    rho_host = W.seeded_rho(base, 0).astype(dt_np)
+    with torch.cuda.stream(stream):
+        rho = torch.from_numpy(rho_host).to("cuda")
+        grad = torch.empty_like(rho)
+    stream.synchronize()
+
+    def step(i):
+        c = ctxs[i % len(ctxs)]
+        c.set_density(rho)
+        c.forward()
+        c.adjoint()
+        c.gradient(grad)
+        return c
+
+    for i in range(args.warmup):
+        step(i)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    fwd_ms = adj_ms = 0.0
+    launches_f = launches_a = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        c = step(args.warmup + i)
+        stream.synchronize()
+        t = c.timing()
+        fwd_ms += t["forward_ms"]
+        adj_ms += t["adjoint_ms"]
+        launches_f += t["forward_launches"]
+        launches_a += t["adjoint_launches"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    cells_steps = W.cell_updates(base)  # cells x N x 2
+    value = cells_steps / (wall / args.steps) / 1e9
+
+    bf = algorithmic_bytes(base, False)
+    ba = algorithmic_bytes(base, True)
+    achieved = (bf * launches_f + ba * launches_a) / ((fwd_ms + adj_ms) * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "step2d_kernel", "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
+                "avg_launch_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
+                "avg_launch_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}
+    nx, ny, nz = base["n"]
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if base["precision"] == 32 else "f64", "data": "synthetic",
+        "config": {"workload": base["name"], "grid": [nx, ny] if base["dims"] == 2 else [nx, ny, nz],
+                   "dx_nm": base["dx"] * 1e9, "time_steps": base["n_steps"], "pml_cells": base["pml_cells"],
+                   "design_box": list(base["design_n"][:base["dims"]]), "gap_box": list(base["gap_n"][:base["dims"]]),
+                   "n_freq": base["n_freq"], "gamma_mult_cycle": gmults, "density": "seeded smoothed U[0,1), seed 0",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+    for c in ctxs:
+        c.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(base, min(args.cpu_steps, base["n_steps"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,6 +83,20 @@ def c3():
     return w
 
 
+def medium2d(**over):
+    """512x512 2D TMz FP32 with the 2048^2 workload's physics (dx = 2 nm,
+    32-cell CPML, 5x5 gap, K = 16) and a 96x96 design box, run long enough
+    for the pulse to reach the gap; sized for the oracle to finish in seconds."""
+    w = dict(_COMMON)
+    w.update(name="tmz2d_512_fp32", dims=2, precision=32, n=(512, 512, 1), dx=2e-9,
+             n_steps=3600, pml_cells=32, tfsf_margin=8, t0_over_tau=3.0,
+             design_lo=(208, 120, 0), design_n=(96, 96, 1),
+             gap_lo=(254, 166, 0), gap_n=(5, 5, 1),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=16)
+    w.update(over)
+    return w
+
+
 def tiny2d(**over):
     """Small 2D TMz case exercising every feature: CPML, plane wave, Drude design, gap."""
     w = dict(_COMMON)
@@ -109,7 +123,7 @@ def tiny3d(**over):
     return w
 
 
-PRESETS = {"c1": c1, "c2": c2, "c3": c3, "tiny2d": tiny2d, "tiny3d": tiny3d}
+PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "tiny2d": tiny2d, "tiny3d": tiny3d}
 
 
 def with_(w, **over):

@@ -1,0 +1,174 @@
+/*
+ * fdtd.h -- C ABI of the MI355X Drude-FDTD topology-optimization hot path.
+ *
+ * One optimization iteration of time-domain topology optimization for
+ * dispersive (Drude) nanostructures, after Hassan & Cala Lesina, "Topology
+ * optimization of dispersive plasmonic nanostructures in the time-domain"
+ * (arXiv 2203.01462):
+ *
+ *   fdtd_set_density   rho over the design box                  (eqs. (4)-(5))
+ *   fdtd_forward       Drude-ADE FDTD forward solve, gap DFT, F (eqs. (10a-c), (3)/(24))
+ *   fdtd_adjoint       adjoint FDTD solve, sensitivity sums      (eq. (20), eq. (25))
+ *   fdtd_gradient      dF/drho per design cell                   (eq. (27), filter = identity)
+ *
+ * The conceptual problem is eq. (2) / its discrete form eq. (28): maximize an
+ * electric-field objective in a gap region by choosing, per design cell, a
+ * density rho in [0,1] that interpolates between a dielectric (eps_s) and a
+ * Drude metal (eps_inf, omega_p, gamma_p; eq. (1)), with the artificial
+ * damping of eq. (5c) (sigma_max) and/or a collision-rate multiplier
+ * (gamma = gamma_mult * gamma_p).
+ *
+ * Conventions
+ *   * Units are SI.  Grid nodes are indexed (x, y, z); arrays are row-major
+ *     with x fastest: [y][x] in 2D, [z][y][x] in 3D.
+ *   * dims = 2 is the TMz polarization: E along z (one E per cell, at the
+ *     node), H in the plane; the plane wave travels along +y.
+ *     dims = 3 is the full Yee cell; the plane wave travels along +z with E
+ *     along x.  Each cell owns its three index-aligned E edges.
+ *   * The outermost nodes are PEC walls; a convolutional PML of pml_cells
+ *     lines the walls; a total-field/scattered-field box tfsf_margin cells
+ *     inside the PML injects the plane wave.  Design and gap boxes must lie
+ *     strictly inside the total-field box.
+ *   * Gap cells are non-dispersive (eps_g) and carry no design variable even
+ *     when they lie inside the design box; their gradient entry is 0.
+ *   * Objective (objective_kind = DFT): F = sum_k w_k sum_{g,c} |Ehat_{g,c}(w_k)|^2,
+ *     Ehat(w) = dt sum_{n=1..N} E^n exp(-j w n dt); w_k = 1/|Ghat(w_k)|^2
+ *     (ENHANCEMENT: Ghat is the same DFT of the excitation waveform) or 1 (UNIT).
+ *     objective_kind = TIME_ENERGY is eq. (24).
+ *
+ * Ownership and threading
+ *   * The caller owns every buffer passed in or out; the library copies what
+ *     it keeps (rho, freqs_hz).  A context owns all of its device memory and
+ *     frees it in fdtd_destroy.
+ *   * All device work of a context runs in order on its stream (config.stream,
+ *     a hipStream_t the caller keeps alive; NULL: the library creates one).
+ *     Calls on one context must not overlap; distinct contexts are
+ *     independent.
+ *   * Functions never abort or exit; they return an fdtd_status and leave a
+ *     message readable with fdtd_last_error.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDTD_ABI_VERSION 1
+
+typedef enum {
+  FDTD_OK = 0,
+  FDTD_EINVAL = 1,    /* invalid argument or configuration */
+  FDTD_ESTATE = 2,    /* call out of order (e.g. adjoint before forward) */
+  FDTD_ENOMEM = 3,    /* device memory or history budget exhausted */
+  FDTD_EDEVICE = 4,   /* HIP runtime error (no device, launch failure) */
+  FDTD_EUNSTABLE = 5  /* non-finite fields after a solve */
+} fdtd_status;
+
+enum { FDTD_SRC_GAUSS = 0, FDTD_SRC_SINC_HANN = 1 };
+enum { FDTD_OBJ_DFT = 0, FDTD_OBJ_TIME_ENERGY = 1 };
+enum { FDTD_W_ENHANCEMENT = 0, FDTD_W_UNIT = 1 };
+
+typedef struct fdtd_ctx fdtd_ctx; /* opaque */
+
+typedef struct {
+  int32_t abi_version;   /* must be FDTD_ABI_VERSION */
+  int32_t dims;          /* 2 (TMz) or 3 */
+  int32_t precision;     /* 32 or 64: field arithmetic and storage; DFT and sensitivity sums are always FP64 */
+  int32_t n[3];          /* nodes along x, y, z (n[2] ignored in 2D) */
+  int32_t n_steps;       /* N time steps of each solve */
+  int32_t pml_cells;     /* CPML thickness (cells) next to each wall */
+  int32_t tfsf_margin;   /* cells between the PML and the total-field box */
+  int32_t design_lo[3], design_n[3]; /* design box, nodes [lo, lo+n) per axis */
+  int32_t gap_lo[3], gap_n[3];       /* gap (observation) box */
+  int32_t source_kind;   /* FDTD_SRC_*: Gaussian-modulated carrier, or the paper's Hann-windowed 4-lobe sinc */
+  int32_t objective_kind;/* FDTD_OBJ_* */
+  int32_t weight_kind;   /* FDTD_W_* */
+  int32_t n_freq;        /* K >= 1 band frequencies */
+  double dx;             /* cell size (m), equal along all axes */
+  double courant;        /* c0 dt / dx, in (0, 1/sqrt(dims)) */
+  double pml_order, pml_sigma_scale, pml_kappa_max, pml_alpha_max; /* CPML grading: order m, sigma_max/(0.8(m+1)/(eta_s dx)), kappa_max, alpha_max (S/m) */
+  double eps_s;          /* background / rho = 0 relative permittivity */
+  double eps_g;          /* gap relative permittivity */
+  double eps_inf, omega_p, gamma_p; /* Drude metal (eq. (1)) at rho = 1 */
+  double gamma_mult;     /* collision-rate multiplier (damping continuation) */
+  double sigma_max;      /* artificial conductivity peak of eq. (5c), S/m */
+  double psi_s_ratio;    /* psi_s / omega_p^2 (the paper uses 1/100) */
+  double f_lo, f_hi;     /* band edges (Hz) of the excitation */
+  double t0_over_tau;    /* Gaussian delay in units of its width */
+  double amplitude;      /* incident amplitude (V/m) */
+  const double *freqs_hz;/* K frequencies, or NULL for K uniform over [f_lo, f_hi]; copied */
+  int64_t history_budget_bytes; /* cap on the stored forward history; 0 = device limit */
+  void *stream;          /* hipStream_t or NULL */
+} fdtd_config;
+
+/* Per-solve timing of the time-stepping kernel, from HIP events recorded on
+ * the context stream right before the first and right after the last step
+ * launch of the most recent forward and adjoint solves. */
+typedef struct {
+  double forward_ms, adjoint_ms;   /* event time over the step-kernel launches */
+  int64_t forward_launches, adjoint_launches;
+  int64_t cells;                   /* nodes of the grid */
+  int64_t design_cells;            /* cells of the design box (Drude or gap) */
+} fdtd_timing;
+
+/* Version of this header the library was built from. */
+int32_t fdtd_abi_version(void);
+
+/* Validate `cfg`, allocate the context and all device memory, and compute the
+ * ρ-independent tables (absorber grading, incident-field line, phasors,
+ * weights).  Fails with EINVAL on: precision not 32/64, dims not 2/3,
+ * Courant outside (0, 1/sqrt(dims)), n_steps < 1, n_freq < 1, non-positive
+ * permittivities or negative material parameters, boxes outside the
+ * total-field region; ENOMEM if the forward history does not fit the budget;
+ * EDEVICE without a usable HIP device.  *out is NULL on failure. */
+fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out);
+
+/* Set the density over the design box (eqs. (4)-(5)): `count` =
+ * prod(design_n) values of the context precision (float or double), layout
+ * [z][y][x] / [y][x].  on_device != 0: `rho` is a device pointer read in
+ * stream order; else a host pointer copied before return.  Entries must lie
+ * in [0,1] (NaN rejected) -> EINVAL.  Invalidates forward/adjoint results. */
+fdtd_status fdtd_set_density(fdtd_ctx *ctx, const void *rho, int64_t count, int32_t on_device);
+
+/* Forward FDTD solve over n_steps (eqs. (10a-c)) with the gap monitor;
+ * writes the objective F to *objective_out (host; may be NULL) and returns
+ * after the solve has finished.  Requires a density (ESTATE). */
+fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out);
+
+/* Adjoint FDTD solve (eq. (20)): time-reversed, driven by dF/dE at the gap,
+ * accumulating the sensitivity sums of eq. (25) on every Drude design edge.
+ * Requires a forward solve on the current density (ESTATE).  Asynchronous
+ * on the context stream. */
+fdtd_status fdtd_adjoint(fdtd_ctx *ctx);
+
+/* dF/drho per design cell (eq. (27), filter = identity; in 3D the sum over the
+ * cell's three edges), `count` = prod(design_n) values of the context
+ * precision, same layout as the density.  on_device != 0: device pointer,
+ * written in stream order; else host pointer, filled before return.
+ * Requires an adjoint solve on the current density (ESTATE). */
+fdtd_status fdtd_gradient(fdtd_ctx *ctx, void *grad_out, int64_t count, int32_t on_device);
+
+/* Gap DFT after a forward solve: host array of count = K * n_gap_cells *
+ * n_comp * 2 doubles, layout [k][gap cell][component][re, im]; n_comp = 1 in
+ * 2D, 3 (Ex, Ey, Ez) in 3D. */
+fdtd_status fdtd_get_dft(fdtd_ctx *ctx, double *re_im, int64_t count);
+
+/* Timing of the most recent solves (see fdtd_timing). */
+fdtd_status fdtd_get_timing(fdtd_ctx *ctx, fdtd_timing *out);
+
+/* Release the context and its device memory.  NULL is accepted. */
+fdtd_status fdtd_destroy(fdtd_ctx *ctx);
+
+/* Message of the last failing call on `ctx` (or of the last failing
+ * fdtd_create when ctx is NULL).  Owned by the library; valid until the next
+ * call on the same context. */
+const char *fdtd_last_error(const fdtd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

@@ -1,0 +1,45 @@
+// fdtd_2d.hpp -- parameters of the 2D TMz step kernel.
+#pragma once
+
+#include "fdtd_internal.hpp"
+
+namespace fdtd {
+
+// Everything one launch of the fused 2D step reads.  Field, absorber-memory
+// and H arrays come in two copies (index par = read copy, par^1 = write copy)
+// because a tile recomputes its halo of H from the previous step's values
+// while neighbouring tiles are already writing theirs.
+template <typename T>
+struct Step2D {
+  int nx, ny, pitch, P;
+  int dx0, dy0, dnx, dny;  // design box
+  int gx0, gy0, gnx, gny;  // gap box
+  int ia, ib, ja, jb, jref, L, tf_on;
+  int K, ng;
+  T *ez[2], *hx[2], *hy[2];
+  T *pex[2], *pey[2], *phx[2], *phy[2];  // absorber memories (forward psi*dx; adjoint nu)
+  T *J;                                  // Drude current over the design box [dny][dnx]
+  const T *rho;                          // density over the design box
+  T *hist;                               // forward E over the design box, [N][dny][dnx]
+  double *grad;                          // sensitivity sums over the design box (adjoint)
+  double *dft;                           // gap DFT [K][ng][2]
+  const double *phasor;                  // [N+1][K][cos, sin]
+  double *gapE;                          // gap time series [N+1][ng]
+  const T *asrc;                         // adjoint source table [N+1][ng] (scaled by dx and S')
+  const T *einc, *hinc;                  // incident line [N+1][L], [N][L]
+  const T *bxe, *axe, *ikxe, *bxh, *axh, *ikxh;  // x grading at nodes / half nodes
+  const T *bye, *aye, *ikye, *byh, *ayh, *ikyh;  // y grading
+  T chx;          // dt / (mu0 dx)
+  T ce_s, ce_g;   // dt / (eps0 eps dx): background, gap
+  T A0, A1;       // 2 eps0 eps_inf_i = A0 + rho A1
+  T B0, B1;       // beta_i = B0 + rho B1
+  T Sg;           // sigma_i dt = Sg rho (1 - rho)
+  T dt_, dtdx, dthJ, kp;
+  T ga, gsm, rs;  // sensitivity: ga = -(eps0/dt)(eps_inf - eps_s); gsm = -sigma_max/2; rs = psi_s/psi
+  double dt;
+};
+
+template <typename T>
+void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s);
+
+}  // namespace fdtd

@@ -1,0 +1,423 @@
+// fdtd_api.hip -- the C ABI of include/fdtd.h: context creation, validation,
+// buffer management and the solve drivers.  The time loops only enqueue
+// kernels on the context stream; all arithmetic of a solve runs on the GPU.
+#include <algorithm>
+#include <memory>
+
+#include "fdtd_2d.hpp"
+
+using namespace fdtd;
+
+struct fdtd_ctx {
+  fdtd_config cfg{};
+  std::vector<double> freqs;
+  int dims = 2, prec = 64;
+  size_t esz = 8;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int nx = 0, ny = 0, nz = 1, pitch = 0;
+  int N = 0, K = 0, nd = 0, ng = 0, ncomp = 1, nmon = 0;
+  double dt = 0;
+  int ia = 0, ib = 0, ja = 0, jb = 0, jref = 0, L = 0;
+  // device memory
+  DevBuf fld[2][3], pml[2][4], J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
+  DevBuf axis[12], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
+  Step2D<float> p2f{};
+  Step2D<double> p2d{};
+  int state = 0;  // 0 created, 1 density, 2 forward, 3 adjoint
+  double F = 0;
+  std::string err;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  fdtd_timing timing{};
+};
+
+namespace {
+
+std::string g_create_error;
+
+Error einval(const std::string &m) { return Error{FDTD_EINVAL, m}; }
+
+bool box_inside(int lo, int n, int a, int b) { return n >= 1 && lo >= a && lo + n - 1 <= b; }
+
+void validate(const fdtd_config &c) {
+  if (c.abi_version != FDTD_ABI_VERSION) throw einval("abi_version mismatch");
+  if (c.dims != 2 && c.dims != 3) throw einval("dims must be 2 or 3");
+  if (c.precision != 32 && c.precision != 64) throw einval("precision must be 32 or 64");
+  if (c.n_steps < 1) throw einval("n_steps < 1");
+  if (c.n_freq < 1) throw einval("n_freq < 1");
+  if (!(c.dx > 0)) throw einval("dx <= 0");
+  const double lim = 1.0 / std::sqrt((double)c.dims);
+  if (!(c.courant > 0) || !(c.courant < lim)) throw einval("Courant number outside (0, 1/sqrt(dims))");
+  if (!(c.eps_s > 0) || !(c.eps_g > 0) || !(c.eps_inf > 0)) throw einval("permittivity <= 0");
+  if (c.psi_s_ratio < 0 || c.sigma_max < 0 || c.gamma_mult < 0 || c.gamma_p < 0 || c.omega_p < 0 ||
+      !(c.psi_s_ratio > 0 || c.omega_p == 0))
+    throw einval("invalid Drude parameters (psi_s_ratio must be > 0)");
+  if (c.pml_cells < 0 || c.tfsf_margin < 0) throw einval("negative pml_cells / tfsf_margin");
+  if (c.source_kind != FDTD_SRC_GAUSS && c.source_kind != FDTD_SRC_SINC_HANN) throw einval("unknown source_kind");
+  if (c.objective_kind != FDTD_OBJ_DFT && c.objective_kind != FDTD_OBJ_TIME_ENERGY) throw einval("unknown objective_kind");
+  if (c.weight_kind != FDTD_W_ENHANCEMENT && c.weight_kind != FDTD_W_UNIT) throw einval("unknown weight_kind");
+  if (!(c.f_hi > c.f_lo) || !(c.f_lo > 0)) throw einval("band edges must satisfy 0 < f_lo < f_hi");
+  for (int a = 0; a < c.dims; ++a)
+    if (c.n[a] < 8) throw einval("grid too small");
+}
+
+template <typename T>
+void upload(hipStream_t s, DevBuf &b, const std::vector<T> &v) {
+  b.alloc(v.size() * sizeof(T));
+  FDTD_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+template <typename T>
+void build_axis_tables(fdtd_ctx *c) {
+  AxisTables<T> ax, ay;
+  ax.build(c->cfg, c->dt, c->nx, c->cfg.pml_cells);
+  ay.build(c->cfg, c->dt, c->ny, c->cfg.pml_cells);
+  const std::vector<T> *v[12] = {&ax.be, &ax.ae, &ax.ike, &ax.bh, &ax.ah, &ax.ikh,
+                                 &ay.be, &ay.ae, &ay.ike, &ay.bh, &ay.ah, &ay.ikh};
+  for (int k = 0; k < 12; ++k) upload(c->stream, c->axis[k], *v[k]);
+}
+
+template <typename T>
+void fill_params2d(fdtd_ctx *c, Step2D<T> &p) {
+  const fdtd_config &g = c->cfg;
+  p.nx = c->nx; p.ny = c->ny; p.pitch = c->pitch; p.P = g.pml_cells;
+  p.dx0 = g.design_lo[0]; p.dy0 = g.design_lo[1]; p.dnx = g.design_n[0]; p.dny = g.design_n[1];
+  p.gx0 = g.gap_lo[0]; p.gy0 = g.gap_lo[1]; p.gnx = g.gap_n[0]; p.gny = g.gap_n[1];
+  p.ia = c->ia; p.ib = c->ib; p.ja = c->ja; p.jb = c->jb; p.jref = c->jref; p.L = c->L; p.tf_on = 1;
+  p.K = c->K; p.ng = c->ng;
+  for (int b = 0; b < 2; ++b) {
+    p.ez[b] = c->fld[b][0].as<T>(); p.hx[b] = c->fld[b][1].as<T>(); p.hy[b] = c->fld[b][2].as<T>();
+    p.pex[b] = c->pml[b][0].as<T>(); p.pey[b] = c->pml[b][1].as<T>();
+    p.phx[b] = c->pml[b][2].as<T>(); p.phy[b] = c->pml[b][3].as<T>();
+  }
+  p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
+  p.dft = c->dft.as<double>(); p.phasor = c->phasor.as<double>(); p.gapE = c->gapE.as<double>();
+  p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
+  const T **ax[12] = {&p.bxe, &p.axe, &p.ikxe, &p.bxh, &p.axh, &p.ikxh, &p.bye, &p.aye, &p.ikye, &p.byh, &p.ayh, &p.ikyh};
+  for (int k = 0; k < 12; ++k) *ax[k] = c->axis[k].as<T>();
+  const double dt = c->dt, dx = g.dx;
+  const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
+  const double gam = g.gamma_mult * g.gamma_p;
+  const double den = 1.0 + gam * dt / 2.0;
+  p.chx = T(dt / (kMu0 * dx));
+  p.ce_s = T(dt / (kEps0 * g.eps_s * dx));
+  p.ce_g = T(dt / (kEps0 * g.eps_g * dx));
+  p.A0 = T(2.0 * kEps0 * g.eps_s);
+  p.A1 = T(2.0 * kEps0 * (g.eps_inf - g.eps_s));
+  p.B0 = T(kEps0 * psi_s * dt / 2.0 / den);
+  p.B1 = T(kEps0 * (psi - psi_s) * dt / 2.0 / den);
+  p.Sg = T(g.sigma_max * dt);
+  p.dt_ = T(dt);
+  p.dtdx = T(dt / dx);
+  p.kp = T((1.0 - gam * dt / 2.0) / den);
+  p.dthJ = T(dt * 0.5 * (1.0 + (1.0 - gam * dt / 2.0) / den));
+  p.ga = T(-(kEps0 / dt) * (g.eps_inf - g.eps_s));
+  p.gsm = T(-0.5 * g.sigma_max);
+  p.rs = T(g.psi_s_ratio);
+  p.dt = dt;
+}
+
+void create_2d(fdtd_ctx *c) {
+  const fdtd_config &g = c->cfg;
+  const int P = g.pml_cells, m = g.tfsf_margin;
+  c->ia = P + m; c->ib = c->nx - 1 - P - m;
+  c->ja = P + m; c->jb = c->ny - 1 - P - m;
+  if (c->ia < 2 || c->ib - c->ia < 2 || c->ja < 3 || c->jb - c->ja < 2)
+    throw einval("total-field box does not fit inside the absorber");
+  if (!box_inside(g.design_lo[0], g.design_n[0], c->ia + 1, c->ib - 1) ||
+      !box_inside(g.design_lo[1], g.design_n[1], c->ja + 1, c->jb - 1) ||
+      !box_inside(g.gap_lo[0], g.gap_n[0], c->ia + 1, c->ib - 1) ||
+      !box_inside(g.gap_lo[1], g.gap_n[1], c->ja + 1, c->jb - 1))
+    throw einval("design/gap boxes must lie strictly inside the total-field box");
+  c->pitch = (c->nx + 63) & ~63;
+  c->nd = g.design_n[0] * g.design_n[1];
+  c->ng = g.gap_n[0] * g.gap_n[1];
+  c->ncomp = 1;
+  c->nmon = c->ng;
+  c->jref = c->ja - 2;
+  c->L = c->jb + 2 - c->jref + 1;
+  const size_t n2 = (size_t)c->pitch * c->ny * c->esz;
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 3; ++k) c->fld[b][k].alloc(n2);
+    for (int k = 0; k < 4; ++k) c->pml[b][k].alloc(n2);
+  }
+  if (c->prec == 32) build_axis_tables<float>(c); else build_axis_tables<double>(c);
+}
+
+void create_common(fdtd_ctx *c) {
+  const fdtd_config &g = c->cfg;
+  hipStream_t s = c->stream;
+  c->J.alloc((size_t)c->nd * c->ncomp * c->esz);
+  c->rho.alloc((size_t)c->nd * c->esz);
+  c->grad.alloc((size_t)c->nd * c->ncomp * sizeof(double));
+  const double hist_bytes = (double)c->N * c->nd * c->ncomp * c->esz;
+  if (g.history_budget_bytes > 0 && hist_bytes > (double)g.history_budget_bytes)
+    throw Error{FDTD_ENOMEM, "forward history (" + std::to_string(hist_bytes) + " bytes) exceeds history_budget_bytes"};
+  size_t fr = 0, tot = 0;
+  FDTD_HIP(hipMemGetInfo(&fr, &tot));
+  if (hist_bytes > 0.92 * (double)fr) throw Error{FDTD_ENOMEM, "forward history does not fit in device memory"};
+  c->hist.alloc((size_t)hist_bytes);
+  c->dft.alloc((size_t)c->K * c->nmon * 2 * sizeof(double));
+  c->gapE.alloc((size_t)(c->N + 1) * c->nmon * sizeof(double));
+  c->asrc.alloc((size_t)(c->N + 1) * c->nmon * c->esz);
+  c->scal.alloc(64);
+  c->bad.alloc(64);
+  c->Fdev.alloc(64);
+  c->gtmp.alloc((size_t)c->nd * c->esz);
+  // excitation samples, frequencies, phasors, weights
+  std::vector<double> wave(c->N + 2);
+  for (int n = 0; n <= c->N + 1; ++n) wave[n] = source_wave(g, n * c->dt);
+  upload(s, c->gwave, wave);
+  upload(s, c->dfreq, c->freqs);
+  c->phasor.alloc((size_t)(c->N + 1) * c->K * 2 * sizeof(double));
+  launch_phasors(s, c->dfreq.as<double>(), c->K, c->N, c->dt, c->phasor.as<double>());
+  c->wts.alloc((size_t)c->K * sizeof(double));
+  launch_weights(s, c->gwave.as<double>(), c->dfreq.as<double>(), c->K, c->N, c->dt,
+                 g.weight_kind == FDTD_W_UNIT, c->wts.as<double>());
+  // incident line: node p <-> main-grid index jref + p; far-end absorber of 20 cells
+  const int P1 = 20, n1 = c->L + P1 + 1;
+  std::vector<double> prof(6 * (size_t)n1);
+  for (int p = 0; p < n1; ++p) {
+    const double start = n1 - 1 - P1;
+    const double de = (p - start) / P1, dh = (p + 0.5 - start) / P1;
+    Grade ge{1, 0, 1}, gh{1, 0, 1};
+    if (de > 0) ge = pml_grade(g, c->dt, de);
+    if (dh > 0) gh = pml_grade(g, c->dt, dh);
+    prof[p] = ge.b; prof[n1 + p] = ge.a; prof[2 * n1 + p] = 1.0 / ge.kap;
+    prof[3 * n1 + p] = gh.b; prof[4 * n1 + p] = gh.a; prof[5 * n1 + p] = 1.0 / gh.kap;
+  }
+  upload(s, c->lineprof, prof);
+  c->linescr.alloc(4 * (size_t)n1 * sizeof(double));
+  c->einc.alloc((size_t)(c->N + 1) * c->L * c->esz);
+  c->hinc.alloc((size_t)c->N * c->L * c->esz);
+  launch_incident_line(s, c->prec, c->gwave.as<double>(), c->N, n1, c->L, c->lineprof.as<double>(),
+                       c->dt / (kMu0 * g.dx), c->dt / (kEps0 * g.eps_s * g.dx), 0.0, 0.0,
+                       c->linescr.as<double>(), c->einc.p, c->hinc.p);
+}
+
+void zero(fdtd_ctx *c, DevBuf &b) { launch_fill_zero(c->stream, b.p, b.bytes); }
+
+void zero_state(fdtd_ctx *c) {
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 3; ++k) zero(c, c->fld[b][k]);
+    for (int k = 0; k < 4; ++k) zero(c, c->pml[b][k]);
+  }
+  zero(c, c->J);
+}
+
+template <typename T>
+Step2D<T> &params2d(fdtd_ctx *c);
+template <>
+Step2D<float> &params2d<float>(fdtd_ctx *c) { return c->p2f; }
+template <>
+Step2D<double> &params2d<double>(fdtd_ctx *c) { return c->p2d; }
+
+template <typename T>
+void run_steps(fdtd_ctx *c, bool adjoint) {
+  Step2D<T> &p = params2d<T>(c);
+  FDTD_HIP(hipEventRecord(c->ev[adjoint ? 2 : 0], c->stream));
+  if (!adjoint) {
+    for (int n = 0; n < c->N; ++n) launch_step2d<T>(p, n, n & 1, false, c->stream);
+  } else {
+    for (int m = c->N; m >= 1; --m) launch_step2d<T>(p, m, (c->N - m) & 1, true, c->stream);
+  }
+  FDTD_HIP(hipGetLastError());
+  FDTD_HIP(hipEventRecord(c->ev[adjoint ? 3 : 1], c->stream));
+}
+
+template <typename F>
+fdtd_status guard(fdtd_ctx *c, F &&f) {
+  try {
+    f();
+    return FDTD_OK;
+  } catch (const Error &e) {
+    if (c) c->err = e.msg; else g_create_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (c) c->err = "host out of memory"; else g_create_error = "host out of memory";
+    return FDTD_ENOMEM;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fdtd_abi_version(void) { return FDTD_ABI_VERSION; }
+
+const char *fdtd_last_error(const fdtd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
+  if (!out) { g_create_error = "null out pointer"; return FDTD_EINVAL; }
+  *out = nullptr;
+  if (!cfg) { g_create_error = "null config"; return FDTD_EINVAL; }
+  std::unique_ptr<fdtd_ctx> c(new fdtd_ctx());
+  fdtd_status st = guard(nullptr, [&] {
+    validate(*cfg);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      (void)hipGetLastError();
+      throw Error{FDTD_EDEVICE, "no HIP device"};
+    }
+    FDTD_HIP(hipGetDevice(&c->device));
+    c->cfg = *cfg;
+    c->dims = cfg->dims;
+    c->prec = cfg->precision;
+    c->esz = c->prec == 32 ? 4 : 8;
+    c->nx = cfg->n[0]; c->ny = cfg->n[1]; c->nz = cfg->dims == 3 ? cfg->n[2] : 1;
+    c->N = cfg->n_steps; c->K = cfg->n_freq;
+    c->dt = cfg->courant * cfg->dx / kC0;
+    c->freqs.resize(c->K);
+    for (int k = 0; k < c->K; ++k)
+      c->freqs[k] = cfg->freqs_hz ? cfg->freqs_hz[k]
+                                  : (c->K == 1 ? 0.5 * (cfg->f_lo + cfg->f_hi)
+                                               : cfg->f_lo + (cfg->f_hi - cfg->f_lo) * k / (c->K - 1));
+    c->cfg.freqs_hz = nullptr;
+    if (cfg->stream) {
+      c->stream = (hipStream_t)cfg->stream;
+    } else {
+      FDTD_HIP(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    for (int k = 0; k < 4; ++k) FDTD_HIP(hipEventCreate(&c->ev[k]));
+    if (c->dims == 3) throw einval("dims = 3 is not available in this build");
+    create_2d(c.get());
+    create_common(c.get());
+    if (c->prec == 32) fill_params2d(c.get(), c->p2f); else fill_params2d(c.get(), c->p2d);
+    FDTD_HIP(hipStreamSynchronize(c->stream));
+    FDTD_HIP(hipGetLastError());
+  });
+  if (st != FDTD_OK) {
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    for (int k = 0; k < 4; ++k) if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    return st;
+  }
+  *out = c.release();
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_destroy(fdtd_ctx *ctx) {
+  if (!ctx) return FDTD_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < 4; ++k) if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_set_density(fdtd_ctx *ctx, const void *rho, int64_t count, int32_t on_device) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (!rho) throw einval("null density");
+    if (count != (int64_t)ctx->nd) throw einval("density count must equal the number of design cells");
+    if (!on_device) {
+      if (ctx->prec == 32) {
+        const float *r = (const float *)rho;
+        for (int64_t i = 0; i < count; ++i) if (!(r[i] >= 0.0f && r[i] <= 1.0f)) throw einval("density outside [0,1] or NaN");
+      } else {
+        const double *r = (const double *)rho;
+        for (int64_t i = 0; i < count; ++i) if (!(r[i] >= 0.0 && r[i] <= 1.0)) throw einval("density outside [0,1] or NaN");
+      }
+      FDTD_HIP(hipMemcpyAsync(ctx->rho.p, rho, (size_t)count * ctx->esz, hipMemcpyHostToDevice, ctx->stream));
+      FDTD_HIP(hipStreamSynchronize(ctx->stream));
+    } else {
+      launch_check_density(ctx->stream, ctx->prec, rho, count, ctx->bad.as<int>());
+      int bad = 0;
+      FDTD_HIP(hipMemcpyAsync(&bad, ctx->bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      FDTD_HIP(hipStreamSynchronize(ctx->stream));
+      if (bad) throw einval("density outside [0,1] or NaN");
+      launch_copy_density(ctx->stream, ctx->prec, rho, ctx->rho.p, count);
+    }
+    ctx->state = 1;
+  });
+}
+
+fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (ctx->state < 1) throw Error{FDTD_ESTATE, "forward before set_density"};
+    ctx->state = 1;
+    zero_state(ctx);
+    zero(ctx, ctx->dft);
+    zero(ctx, ctx->gapE);
+    if (ctx->prec == 32) run_steps<float>(ctx, false); else run_steps<double>(ctx, false);
+    const fdtd_config &g = ctx->cfg;
+    const double te_scale = 0.5 * g.eps_g * ctx->dt * g.dx * g.dx * g.dx;
+    launch_objective(ctx->stream, ctx->dft.as<double>(), ctx->wts.as<double>(), ctx->gapE.as<double>(), ctx->K,
+                     ctx->nmon, ctx->N, g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_scale, ctx->Fdev.as<double>());
+    double F = 0;
+    FDTD_HIP(hipMemcpyAsync(&F, ctx->Fdev.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FDTD_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0;
+    FDTD_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->timing.forward_ms = ms;
+    ctx->timing.forward_launches = ctx->N;
+    if (!std::isfinite(F)) throw Error{FDTD_EUNSTABLE, "non-finite objective"};
+    ctx->F = F;
+    if (objective_out) *objective_out = F;
+    ctx->state = 2;
+  });
+}
+
+fdtd_status fdtd_adjoint(fdtd_ctx *ctx) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (ctx->state < 2) throw Error{FDTD_ESTATE, "adjoint before forward"};
+    const fdtd_config &g = ctx->cfg;
+    const double te_coef = g.eps_g * ctx->dt * g.dx * g.dx * g.dx;
+    launch_adjoint_source(ctx->stream, ctx->prec, ctx->dft.as<double>(), ctx->wts.as<double>(),
+                          ctx->phasor.as<double>(), ctx->gapE.as<double>(), ctx->K, ctx->nmon, ctx->N,
+                          g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_coef, ctx->dt, g.dx, ctx->scal.as<double>(),
+                          ctx->asrc.p);
+    zero_state(ctx);
+    zero(ctx, ctx->grad);
+    if (ctx->prec == 32) run_steps<float>(ctx, true); else run_steps<double>(ctx, true);
+    ctx->timing.adjoint_launches = ctx->N;
+    ctx->state = 3;
+  });
+}
+
+fdtd_status fdtd_gradient(fdtd_ctx *ctx, void *grad_out, int64_t count, int32_t on_device) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (ctx->state < 3) throw Error{FDTD_ESTATE, "gradient before adjoint"};
+    if (!grad_out) throw einval("null gradient buffer");
+    if (count != (int64_t)ctx->nd) throw einval("gradient count must equal the number of design cells");
+    const fdtd_config &g = ctx->cfg;
+    void *dst = on_device ? grad_out : ctx->gtmp.p;
+    launch_grad_finalize(ctx->stream, ctx->prec, ctx->grad.as<double>(), ctx->scal.as<double>(), ctx->ncomp,
+                         g.design_n[0], g.design_n[1], ctx->dims == 3 ? g.design_n[2] : 1,
+                         g.gap_lo[0] - g.design_lo[0], g.gap_lo[1] - g.design_lo[1],
+                         ctx->dims == 3 ? g.gap_lo[2] - g.design_lo[2] : 0, g.gap_n[0], g.gap_n[1],
+                         ctx->dims == 3 ? g.gap_n[2] : 1, dst);
+    if (!on_device) {
+      FDTD_HIP(hipMemcpyAsync(grad_out, ctx->gtmp.p, (size_t)count * ctx->esz, hipMemcpyDeviceToHost, ctx->stream));
+      FDTD_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    float ms = 0;
+    FDTD_HIP(hipEventSynchronize(ctx->ev[3]));
+    FDTD_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+    ctx->timing.adjoint_ms = ms;
+  });
+}
+
+fdtd_status fdtd_get_dft(fdtd_ctx *ctx, double *re_im, int64_t count) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (ctx->state < 2) throw Error{FDTD_ESTATE, "get_dft before forward"};
+    if (!re_im || count != (int64_t)ctx->K * ctx->nmon * 2) throw einval("dft buffer size must be K * n_gap * n_comp * 2");
+    FDTD_HIP(hipMemcpyAsync(re_im, ctx->dft.p, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FDTD_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+fdtd_status fdtd_get_timing(fdtd_ctx *ctx, fdtd_timing *out) {
+  if (!ctx || !out) return FDTD_EINVAL;
+  *out = ctx->timing;
+  out->cells = (int64_t)ctx->nx * ctx->ny * ctx->nz;
+  out->design_cells = ctx->nd;
+  return FDTD_OK;
+}
+
+}  // extern "C"

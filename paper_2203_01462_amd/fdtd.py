@@ -1,0 +1,227 @@
+"""ctypes binding of the C ABI in ``include/fdtd.h`` (argument marshalling only).
+
+Every step of a solve runs in the HIP library: this module translates a
+workload description into ``fdtd_config``, passes host arrays or torch device
+pointers through, and raises on non-zero status codes.  There is no fallback:
+if the library is missing or no HIP device is usable, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
+ABI_VERSION = 1
+C0 = 299792458.0
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSTABLE"}
+SRC = {"gauss": 0, "sinc_hann": 1}
+OBJ = {"dft": 0, "time_energy": 1}
+WTS = {"enhancement": 0, "unit": 1}
+
+
+class FDTDError(RuntimeError):
+    def __init__(self, code, msg):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{self.name}: {msg}")
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("dims", C.c_int32), ("precision", C.c_int32),
+        ("n", C.c_int32 * 3), ("n_steps", C.c_int32), ("pml_cells", C.c_int32),
+        ("tfsf_margin", C.c_int32),
+        ("design_lo", C.c_int32 * 3), ("design_n", C.c_int32 * 3),
+        ("gap_lo", C.c_int32 * 3), ("gap_n", C.c_int32 * 3),
+        ("source_kind", C.c_int32), ("objective_kind", C.c_int32), ("weight_kind", C.c_int32),
+        ("n_freq", C.c_int32),
+        ("dx", C.c_double), ("courant", C.c_double),
+        ("pml_order", C.c_double), ("pml_sigma_scale", C.c_double),
+        ("pml_kappa_max", C.c_double), ("pml_alpha_max", C.c_double),
+        ("eps_s", C.c_double), ("eps_g", C.c_double), ("eps_inf", C.c_double),
+        ("omega_p", C.c_double), ("gamma_p", C.c_double), ("gamma_mult", C.c_double),
+        ("sigma_max", C.c_double), ("psi_s_ratio", C.c_double),
+        ("f_lo", C.c_double), ("f_hi", C.c_double), ("t0_over_tau", C.c_double),
+        ("amplitude", C.c_double),
+        ("freqs_hz", C.POINTER(C.c_double)),
+        ("history_budget_bytes", C.c_int64),
+        ("stream", C.c_void_p),
+    ]
+
+
+class Timing(C.Structure):
+    _fields_ = [("forward_ms", C.c_double), ("adjoint_ms", C.c_double),
+                ("forward_launches", C.c_int64), ("adjoint_launches", C.c_int64),
+                ("cells", C.c_int64), ("design_cells", C.c_int64)]
+
+
+# Every symbol the header declares (checked by the CPU tests).
+EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint",
+           "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libfdtd_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is missing: run __graft_entry__.build() first")
+    # torch provides device memory and streams; importing it first makes the
+    # library bind to the HIP runtime torch has already loaded (same SONAME),
+    # so one process never holds two HIP runtimes.
+    import torch  # noqa: F401
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.fdtd_abi_version.restype = C.c_int32
+    L.fdtd_create.argtypes = [C.POINTER(Config), C.POINTER(P)]
+    L.fdtd_set_density.argtypes = [P, P, C.c_int64, C.c_int32]
+    L.fdtd_forward.argtypes = [P, C.POINTER(C.c_double)]
+    L.fdtd_adjoint.argtypes = [P]
+    L.fdtd_gradient.argtypes = [P, P, C.c_int64, C.c_int32]
+    L.fdtd_get_dft.argtypes = [P, C.POINTER(C.c_double), C.c_int64]
+    L.fdtd_get_timing.argtypes = [P, C.POINTER(Timing)]
+    L.fdtd_destroy.argtypes = [P]
+    L.fdtd_last_error.argtypes = [P]
+    L.fdtd_last_error.restype = C.c_char_p
+    for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
+               "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy"):
+        getattr(L, fn).restype = C.c_int
+    if L.fdtd_abi_version() != ABI_VERSION:
+        raise ImportError("libfdtd_hip.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def make_config(w, stream=None, history_budget_bytes=0):
+    """Translate a workload dict into fdtd_config (pure marshalling)."""
+    c = Config()
+    c.abi_version = ABI_VERSION
+    c.dims = w["dims"]
+    c.precision = w["precision"]
+    for k in range(3):
+        c.n[k] = w["n"][k]
+        c.design_lo[k] = w["design_lo"][k]
+        c.design_n[k] = w["design_n"][k]
+        c.gap_lo[k] = w["gap_lo"][k]
+        c.gap_n[k] = w["gap_n"][k]
+    c.n_steps = w["n_steps"]
+    c.pml_cells = w["pml_cells"]
+    c.tfsf_margin = w["tfsf_margin"]
+    c.source_kind = SRC[w["source"]]
+    c.objective_kind = OBJ[w["objective"]]
+    c.weight_kind = WTS[w["weights"]]
+    c.dx = w["dx"]
+    c.courant = w["courant"]
+    for k in ("pml_order", "pml_sigma_scale", "pml_kappa_max", "pml_alpha_max", "eps_s", "eps_g",
+              "eps_inf", "omega_p", "gamma_p", "gamma_mult", "sigma_max", "psi_s_ratio",
+              "t0_over_tau", "amplitude"):
+        setattr(c, k, float(w[k]))
+    c.f_lo = C0 / w["lambda_hi"]
+    c.f_hi = C0 / w["lambda_lo"]
+    keep = None
+    if w.get("freqs_hz") is not None:
+        keep = np.ascontiguousarray(np.asarray(w["freqs_hz"], dtype=np.float64))
+        c.n_freq = len(keep)
+        c.freqs_hz = keep.ctypes.data_as(C.POINTER(C.c_double))
+    else:
+        c.n_freq = w["n_freq"]
+        c.freqs_hz = C.POINTER(C.c_double)()
+    c.history_budget_bytes = int(history_budget_bytes)
+    c.stream = stream
+    return c, keep
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class FDTD:
+    """One problem instance on the GPU (a context of the HIP library)."""
+
+    def __init__(self, w, stream=None, history_budget_bytes=0):
+        L = load_library()
+        self.w = dict(w)
+        self.dims = w["dims"]
+        self.dtype = np.float32 if w["precision"] == 32 else np.float64
+        cfg, keep = make_config(w, stream, history_budget_bytes)
+        h = C.c_void_p()
+        rc = L.fdtd_create(C.byref(cfg), C.byref(h))
+        if rc:
+            raise FDTDError(rc, L.fdtd_last_error(None).decode())
+        self.h = h
+        self.K = cfg.n_freq
+        dnx, dny, dnz = w["design_n"]
+        self.dshape = (dnz, dny, dnx) if self.dims == 3 else (dny, dnx)
+        self.nd = int(np.prod(self.dshape))
+        gx, gy, gz = w["gap_n"]
+        self.ng = gx * gy * (gz if self.dims == 3 else 1)
+        self.ncomp = 3 if self.dims == 3 else 1
+
+    def _check(self, rc):
+        if rc:
+            raise FDTDError(rc, load_library().fdtd_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().fdtd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_density(self, rho):
+        """rho: numpy array (host copy) or torch device tensor of the context dtype."""
+        L = load_library()
+        if _is_torch(rho) and rho.is_cuda:
+            if not rho.is_contiguous() or rho.numel() != self.nd:
+                raise ValueError("device density must be contiguous with one value per design cell")
+            self._check(L.fdtd_set_density(self.h, C.c_void_p(rho.data_ptr()), rho.numel(), 1))
+            return
+        r = np.ascontiguousarray(np.asarray(rho, dtype=self.dtype).reshape(-1))
+        self._check(L.fdtd_set_density(self.h, r.ctypes.data_as(C.c_void_p), r.size, 0))
+
+    def forward(self):
+        F = C.c_double()
+        self._check(load_library().fdtd_forward(self.h, C.byref(F)))
+        return F.value
+
+    def adjoint(self):
+        self._check(load_library().fdtd_adjoint(self.h))
+
+    def gradient(self, out=None):
+        """dF/drho per design cell: into ``out`` (torch device tensor) or a new numpy array."""
+        L = load_library()
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._check(L.fdtd_gradient(self.h, C.c_void_p(out.data_ptr()), out.numel(), 1))
+            return out
+        g = np.zeros(self.nd, dtype=self.dtype)
+        self._check(L.fdtd_gradient(self.h, g.ctypes.data_as(C.c_void_p), g.size, 0))
+        return g.reshape(self.dshape)
+
+    def run(self, rho):
+        self.set_density(rho)
+        F = self.forward()
+        self.adjoint()
+        return F, self.gradient()
+
+    def dft(self):
+        n = self.K * self.ng * self.ncomp * 2
+        out = np.zeros(n)
+        self._check(load_library().fdtd_get_dft(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n))
+        out = out.reshape(self.K, self.ng, self.ncomp, 2)
+        return out[..., 0] + 1j * out[..., 1]
+
+    def timing(self):
+        t = Timing()
+        self._check(load_library().fdtd_get_timing(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Timing._fields_}

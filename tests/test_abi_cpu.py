@@ -1,0 +1,76 @@
+"""CPU-side checks of the HIP library boundary: it builds, loads, exports every
+symbol that include/fdtd.h declares, and rejects invalid configurations before
+touching a device."""
+import os
+import re
+
+import pytest
+
+import fdtd_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2203_01462_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2203_01462_amd import build
+        build.build()
+    return P
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    syms = header_symbols()
+    for s in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = lib.load_library()
+    for s in header_symbols():
+        assert hasattr(L, s), s
+    assert sorted(lib.fdtd.EXPORTS) == header_symbols()
+    assert L.fdtd_abi_version() == 1
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(courant=0.71), "Courant"),
+    (dict(precision=16), "precision"),
+    (dict(n_steps=0), "n_steps"),
+    (dict(n_freq=0), "n_freq"),
+    (dict(eps_s=-1.0), "permittivity"),
+    (dict(psi_s_ratio=0.0), "psi_s_ratio"),
+])
+def test_invalid_configs_rejected_before_device(lib, over, msg):
+    w = W.tiny2d(**over)
+    with pytest.raises(lib.FDTDError) as e:
+        lib.FDTD(w)
+    assert e.value.name == "EINVAL" and msg in str(e.value)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2203_01462_amd import fdtd as F
+    saved = F._lib
+    try:
+        F._lib = None
+        with pytest.raises(ImportError):
+            F.load_library(str(tmp_path / "absent.so"))
+    finally:
+        F._lib = saved
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2203_01462_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                for bad in ("import oracle", "from oracle", "liboracle", "or2d_", "or3d_"):
+                    assert bad not in txt, (f, bad)
