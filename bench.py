@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 5 device copies of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path runs on a single device); "
@@ -99,6 +101,15 @@ def main():
     import paper_2203_01462_amd as P
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_dispatch": src.numel() * 4,
+                          "copy_probe_bytes_written_per_dispatch": dst.numel() * 4}), flush=True)
+        return
     base = W.PRESETS[args.workload]()
     if args.n_steps:
         base = W.with_(base, n_steps=args.n_steps)

@@ -14,224 +14,477 @@
 // chain rule of eq. (27) into one FP64 sum per design edge:
 //   g_i += E_i^m [ga dE*_i + gb (E*_i^{m-1/2} + E*_i^{m+1/2}) + gc (J*_i^{m-1/2} + J*_i^{m+1/2})].
 //
-// Layout: a workgroup owns a 64 x 16 tile of E nodes.  It stages E (or the
-// graded E*) of the tile plus a one-node halo in LDS, computes H for the tile
-// plus the low-side halo row/column (so no other tile's new H is needed),
-// writes the tile's own H, then updates E.  All arrays that a halo reads come
-// in two copies so the step needs no grid-wide synchronisation.
+// Layout: a wavefront owns a 64 x 2 tile of E nodes (four wavefronts stacked
+// along y form a workgroup); each thread owns one column segment of 2 nodes.
+// Wavefronts whose tile (with its halo) touches only the plain background take
+// a lean path with the dielectric update alone.  It issues all of its loads at once (E over the
+// segment plus one node above/below/left/right, the old H it needs), computes
+// H for its segment plus the low-side halo (H_x one row below, H_y one column
+// to the left) from those values, writes its own H, then updates E.  No LDS
+// and no barrier: neighbour values come through the caches.  All arrays that
+// a halo reads come in two copies (read copy par, write copy par^1), so the
+// step needs no grid-wide synchronisation.
 #include "fdtd_2d.hpp"
 
 namespace fdtd {
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int NT = 256;
+#ifndef FDTD2D_ROWS
+#define FDTD2D_ROWS 2
+#endif
+#ifndef FDTD2D_MIN_WAVES
+#define FDTD2D_MIN_WAVES 1
+#endif
+#ifndef FDTD2D_XCD_REMAP
+#define FDTD2D_XCD_REMAP 2
+#endif
+constexpr int WAVES = 4;          // wavefronts per workgroup, stacked along y
+constexpr int NT = 64 * WAVES;    // threads per workgroup
+constexpr int TXW = 64;           // tile width (nodes along x): one wavefront
+constexpr int R = FDTD2D_ROWS;    // rows per thread; a wavefront covers 64 x R nodes
+constexpr int TYB = WAVES * R;    // workgroup tile height
 
 __device__ __forceinline__ bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
 __device__ __forceinline__ bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
 
-template <typename T, bool ADJ>
-__global__ void __launch_bounds__(NT) step2d_kernel(Step2D<T> p, int n, int par) {
-  __shared__ T sEx[TY + 2][TX + 2];             // E (forward) / x-graded E* (adjoint)
-  __shared__ T sEy[ADJ ? TY + 2 : 1][TX + 2];   // y-graded E* (adjoint)
-  __shared__ T sHx[TY + 1][TX];                 // new Hx (forward) / graded Hx* (adjoint), rows j0-1 ..
-  __shared__ T sHy[TY][TX + 1];                 // new Hy / graded Hy*, columns i0-1 ..
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, tid = threadIdx.x;
-  const int nx = p.nx, ny = p.ny, P = p.P, pitch = p.pitch;
+// Workgroup -> tile map.  Consecutive dispatch slots go round-robin over the
+// 8 XCDs (each with its own L2).  Mode 2 (default) gives XCD x whole tile-rows
+// x, x+8, x+16, ...: horizontal neighbours share an L2, and the absorber,
+// design and gap rows (the slower wavefronts) spread evenly over the XCDs.
+// Mode 1 gives each XCD one contiguous band of tile-rows; mode 0 keeps the
+// plain order.
+__device__ __forceinline__ void tile_of(int bid, int nbx, int nby, int &tx, int &ty) {
+  int t = bid;
+  if (FDTD2D_XCD_REMAP == 1 && (nby * nbx) % 8 == 0) t = (bid & 7) * (nbx * nby / 8) + (bid >> 3);
+  if (FDTD2D_XCD_REMAP == 2 && nby % 8 == 0) {
+    const int k = bid >> 3;
+    tx = k % nbx;
+    ty = (bid & 7) + 8 * (k / nbx);
+    return;
+  }
+  tx = t % nbx;
+  ty = t / nbx;
+}
+
+// Branch-free predicated load: reads base[q] when `on`, else base[0] (always
+// a valid address) and returns 0.
+template <typename T>
+__device__ __forceinline__ T ldp(const T *__restrict__ base, size_t q, bool on) {
+  const T v = base[on ? q : 0];
+  return on ? v : T(0);
+}
+
+// The step kernel is latency-bound unless every global load of a column
+// segment is in flight before the first dependent use: all workgroups are
+// resident at once on this grid, so the slowest column (absorber, design or
+// gap) sets the launch time.  Hence three phases -- predicated loads, pure
+// register arithmetic, stores -- with restrict-qualified pointers.
+// A wavefront tile is an edge tile if it (or its one-node halo) touches an
+// absorber cell, a wall or a total-field line.
+__device__ __forceinline__ bool wave_is_edge(const int nx, const int ny, const int P, const int i0, const int jb,
+                                             const int ia, const int ib, const int ja, const int jbt) {
+  if (i0 < P + 2 || i0 + TXW > nx - 2 - P || jb < P + 2 || jb + R > ny - 2 - P) return true;
+  const int x0 = i0 - 1, x1 = i0 + TXW, y0 = jb - 1, y1 = jb + R;
+  auto hit = [](int lo, int hi, int v) { return v >= lo && v <= hi; };
+  if (hit(x0, x1, ia - 1) || hit(x0, x1, ia) || hit(x0, x1, ib) || hit(x0, x1, ib + 1)) return true;
+  return hit(y0, y1, ja - 1) || hit(y0, y1, ja) || hit(y0, y1, jbt) || hit(y0, y1, jbt + 1);
+}
+
+// Does the wavefront's 64 x R block of E nodes meet the box [x0,x0+nx) x [y0,y0+ny)?
+__device__ __forceinline__ bool wave_touches_box(const int i0, const int jb, const int x0, const int y0, const int bnx,
+                                                 const int bny) {
+  return i0 + TXW - 1 >= x0 && i0 < x0 + bnx && jb + R - 1 >= y0 && jb < y0 + bny;
+}
+
+// Tiles that are neither edge tiles nor touch the design or gap box need only
+// the plain dielectric update, identical in the forward and adjoint solves.
+template <typename T>
+__device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, const int i, const int jb) {
+  const int pitch = p.pitch;
+  const T *__restrict__ ez = p.ez[par];
+  const T *__restrict__ hxo = p.hx[par];
+  const T *__restrict__ hyo = p.hy[par];
+  T *__restrict__ ezw = p.ez[par ^ 1];
+  T *__restrict__ hxw = p.hx[par ^ 1];
+  T *__restrict__ hyw = p.hy[par ^ 1];
+  const size_t q0 = (size_t)jb * pitch + i;
+  T e[R + 2], er[R], el[R], hx[R + 1], hy[R], hyl[R];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) e[r] = ez[q0 + (size_t)(r - 1) * pitch];
+#pragma unroll
+  for (int r = 0; r < R + 1; ++r) hx[r] = hxo[q0 + (size_t)(r - 1) * pitch];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const size_t q = q0 + (size_t)r * pitch;
+    er[r] = ez[q + 1];
+    el[r] = ez[q - 1];
+    hy[r] = hyo[q];
+    hyl[r] = hyo[q - 1];
+  }
+  const T ch = p.chx, ce = p.ce_s;
+  T hxn[R + 1];
+#pragma unroll
+  for (int r = 0; r < R + 1; ++r) hxn[r] = hx[r] - ch * (e[r + 1] - e[r]);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const size_t q = q0 + (size_t)r * pitch;
+    const T h = hy[r] + ch * (er[r] - e[r + 1]);
+    const T hl = hyl[r] + ch * (e[r + 1] - el[r]);
+    hxw[q] = hxn[r + 1];
+    hyw[q] = h;
+    ezw[q] = e[r + 1] + ce * ((h - hl) - (hxn[r + 1] - hxn[r]));
+  }
+}
+
+// Absorber, wall, total-field, design and gap nodes.  EDGE = false compiles
+// the absorber and plane-wave terms out (interior design/gap wavefronts).
+template <typename T, bool ADJ, bool EDGE>
+__device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, const int par, const int i,
+                                             const int jb) {
+  const int nx = p.nx, ny = p.ny, pitch = p.pitch, P = EDGE ? p.P : 0;
+  if (i >= nx) return;
   const int wr = par ^ 1;
   const T *__restrict__ ez = p.ez[par];
+  const T *__restrict__ hxo = p.hx[par];
+  const T *__restrict__ hyo = p.hy[par];
+  const T *__restrict__ pexo = p.pex[par];
+  const T *__restrict__ peyo = p.pey[par];
+  const T *__restrict__ phxo = p.phx[par];
+  const T *__restrict__ phyo = p.phy[par];
+  T *__restrict__ ezw = p.ez[wr];
+  T *__restrict__ hxw = p.hx[wr];
+  T *__restrict__ hyw = p.hy[wr];
+  T *__restrict__ pexw = p.pex[wr];
+  T *__restrict__ peyw = p.pey[wr];
+  T *__restrict__ phxw = p.phx[wr];
+  T *__restrict__ phyw = p.phy[wr];
+  const T *__restrict__ rho = p.rho;
+  T *__restrict__ Jc = p.J;
+  T *__restrict__ hist = p.hist;
+  double *__restrict__ grad = p.grad;
 
-  // ---- stage E of the tile plus a one-node halo
-  for (int k = tid; k < (TY + 2) * (TX + 2); k += NT) {
-    const int ly = k / (TX + 2), lx = k - ly * (TX + 2);
-    const int i = i0 - 1 + lx, j = j0 - 1 + ly;
-    const bool in = i >= 0 && i < nx && j >= 0 && j < ny;
-    const size_t q = (size_t)j * pitch + i;
-    const T e = in ? ez[q] : T(0);
-    if (!ADJ) {
-      sEx[ly][lx] = e;
-    } else {
-      T gx = e, gy = e;
-      if (in) {
-        const bool own = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-        if (pml_e(i, nx, P)) {
-          const T nu = p.bxe[i] * p.pex[par][q] + p.axe[i] * e;
-          gx = e * p.ikxe[i] + nu;
-          if (own) p.pex[wr][q] = nu;
-        }
-        if (pml_e(j, ny, P)) {
-          const T nu = p.bye[j] * p.pey[par][q] + p.aye[j] * e;
-          gy = e * p.ikye[j] + nu;
-          if (own) p.pey[wr][q] = nu;
-        }
-      }
-      sEx[ly][lx] = gx;
-      sEy[ly][lx] = gy;
-    }
-  }
-  __syncthreads();
-
-  // ---- Hx at (i, j+1/2): rows j0-1 .. j0+TY-1 (row j0-1 is the halo)
-  for (int k = tid; k < (TY + 1) * TX; k += NT) {
-    const int ly = k / TX, lx = k - ly * TX;
-    const int i = i0 + lx, j = j0 - 1 + ly;
-    T v = T(0);
-    if (i >= 1 && i <= nx - 2 && j >= 0 && j <= ny - 2) {
-      const size_t q = (size_t)j * pitch + i;
-      const bool own = ly >= 1;
-      if (!ADJ) {
-        const T dE = sEx[ly + 1][lx + 1] - sEx[ly][lx + 1];
-        T h = p.hx[par][q];
-        if (pml_h(j, ny, P)) {
-          const T ps = p.byh[j] * p.phx[par][q] + p.ayh[j] * dE;
-          h -= p.chx * (dE * p.ikyh[j] + ps);
-          if (own) p.phx[wr][q] = ps;
-        } else {
-          h -= p.chx * dE;
-        }
-        if (p.tf_on && i >= p.ia && i <= p.ib) {
-          if (j == p.ja - 1) h += p.chx * p.einc[(size_t)n * p.L + (p.ja - p.jref)];
-          if (j == p.jb) h -= p.chx * p.einc[(size_t)n * p.L + (p.jb - p.jref)];
-        }
-        if (own) p.hx[wr][q] = h;
-        v = h;
-      } else {
-        const T dG = sEy[ly + 1][lx + 1] - sEy[ly][lx + 1];
-        const T h = p.hx[par][q] - p.chx * dG;
-        if (own) p.hx[wr][q] = h;
-        v = h;
-        if (pml_h(j, ny, P)) {
-          const T nu = p.byh[j] * p.phx[par][q] + p.ayh[j] * h;
-          v = h * p.ikyh[j] + nu;
-          if (own) p.phx[wr][q] = nu;
-        }
-      }
-    }
-    sHx[ly][lx] = v;
-  }
-
-  // ---- Hy at (i+1/2, j): columns i0-1 .. i0+TX-1 (column i0-1 is the halo)
-  for (int k = tid; k < TY * (TX + 1); k += NT) {
-    const int ly = k / (TX + 1), lx = k - ly * (TX + 1);
-    const int i = i0 - 1 + lx, j = j0 + ly;
-    T v = T(0);
-    if (i >= 0 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-      const size_t q = (size_t)j * pitch + i;
-      const bool own = lx >= 1;
-      if (!ADJ) {
-        const T dE = sEx[ly + 1][lx + 1] - sEx[ly + 1][lx];
-        T h = p.hy[par][q];
-        if (pml_h(i, nx, P)) {
-          const T ps = p.bxh[i] * p.phy[par][q] + p.axh[i] * dE;
-          h += p.chx * (dE * p.ikxh[i] + ps);
-          if (own) p.phy[wr][q] = ps;
-        } else {
-          h += p.chx * dE;
-        }
-        if (p.tf_on && j >= p.ja && j <= p.jb) {
-          if (i == p.ia - 1) h -= p.chx * p.einc[(size_t)n * p.L + (j - p.jref)];
-          if (i == p.ib) h += p.chx * p.einc[(size_t)n * p.L + (j - p.jref)];
-        }
-        if (own) p.hy[wr][q] = h;
-        v = h;
-      } else {
-        const T dG = sEx[ly + 1][lx + 1] - sEx[ly + 1][lx];
-        const T h = p.hy[par][q] + p.chx * dG;
-        if (own) p.hy[wr][q] = h;
-        v = h;
-        if (pml_h(i, nx, P)) {
-          const T nu = p.bxh[i] * p.phy[par][q] + p.axh[i] * h;
-          v = h * p.ikxh[i] + nu;
-          if (own) p.phy[wr][q] = nu;
-        }
-      }
-    }
-    sHy[ly][lx] = v;
-  }
-  __syncthreads();
-
-  // ---- E (and J) at the tile's nodes
+  const bool hasl = i >= 1, hasr = i + 1 < nx;
+  const bool colx = i >= 1 && i <= nx - 2;       // E node column / H_x column
+  const bool coly = i <= nx - 2;                  // H_y at (i+1/2)
+  const bool pxe = pml_e(i, nx, P), pxh = pml_h(i, nx, P);
+  const bool pxhl = hasl && pml_h(i - 1, nx, P);
+  const bool pxel = hasl && pml_e(i - 1, nx, P), pxer = hasr && pml_e(i + 1, nx, P);
   const int nd = p.dnx * p.dny;
-  for (int k = tid; k < TY * TX; k += NT) {
-    const int ly = k / TX, lx = k - ly * TX;
-    const int i = i0 + lx, j = j0 + ly;
-    if (i < 1 || i > nx - 2 || j < 1 || j > ny - 2) continue;
-    const size_t q = (size_t)j * pitch + i;
-    const T dHy = sHy[ly][lx + 1] - sHy[ly][lx];
-    const T dHx = sHx[ly + 1][lx] - sHx[ly][lx];
+  const int di = i - p.dx0, gi = i - p.gx0;
+  const bool dcol = colx && di >= 0 && di < p.dnx, gcol = colx && gi >= 0 && gi < p.gnx;
+  const bool tfx = (EDGE && p.tf_on) && i >= p.ia && i <= p.ib;
+  const bool tfy = (EDGE && p.tf_on) && (i == p.ia - 1 || i == p.ia || i == p.ib || i == p.ib + 1);
+
+  // ---------------------------------------------------------------- loads
+  // Every load is unconditional: a predicated-off load reads element 0 of its
+  // array (one cache line for the whole wavefront) and its value is dropped.
+  // Branch-free loads stay in flight together; branches around them would
+  // make the compiler wait at every join.
+  T e[R + 2], er[R], el[R], hx[R + 1], hy[R], hyl[R];
+  T phx[R + 1], phy[R], phyl[R], pex[R], pey[R + 2], pexr[R], pexl[R];
+  T rr[R], Jo[R], Em[R], src[R], einc_r[R];
+  double gacc[R];
+#pragma unroll
+  for (int r = 0; r < R + 2; ++r) {
+    const int j = jb - 1 + r;
+    const bool ok = j >= 0 && j < ny;
+    const size_t q = (size_t)(ok ? j : 0) * pitch + i;
+    e[r] = ldp(ez, q, ok);
+    const bool wpe = ADJ ? (ok && pml_e(j, ny, P)) : (r >= 1 && r <= R && colx && j <= ny - 2 && ok && pml_e(j, ny, P));
+    pey[r] = ldp(peyo, q, wpe);
+    if (r <= R) {
+      hx[r] = ldp(hxo, q, ok);
+      phx[r] = ldp(phxo, q, colx && ok && j <= ny - 2 && pml_h(j, ny, P));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb + r;
+    const bool ok = j < ny;
+    const bool inner = j >= 1 && j <= ny - 2;
+    const size_t q = (size_t)(ok ? j : 0) * pitch + i;
+    er[r] = ldp(ez, q + 1, ok && hasr);
+    el[r] = ldp(ez, q - 1, ok && hasl);
+    hy[r] = ldp(hyo, q, ok);
+    hyl[r] = ldp(hyo, q - 1, ok && hasl);
+    phy[r] = ldp(phyo, q, inner && coly && pxh);
+    phyl[r] = ldp(phyo, q - 1, inner && pxhl);
+    pex[r] = ldp(pexo, q, ok && pxe && (ADJ || (colx && inner)));
+    pexr[r] = ldp(pexo, q + 1, ADJ && ok && pxer);
+    pexl[r] = ldp(pexo, q - 1, ADJ && ok && pxel);
+    const int dj = j - p.dy0, gj = j - p.gy0;
+    const bool des = dcol && inner && dj >= 0 && dj < p.dny;
+    const bool gap = gcol && inner && gj >= 0 && gj < p.gny;
+    const size_t d = (size_t)(des ? dj * p.dnx + di : 0);
+    rr[r] = ldp(rho, d, des);
+    Jo[r] = ldp((const T *)Jc, d, des && !gap);
+    Em[r] = ldp((const T *)hist, (size_t)(n - 1) * nd + d, ADJ && des && !gap);
+    gacc[r] = ldp((const double *)grad, d, ADJ && des && !gap);
+    src[r] = ldp(p.asrc, (size_t)n * p.ng + (gap ? gj * p.gnx + gi : 0), ADJ && gap);
+    const bool tfr = !ADJ && tfy && j >= p.ja && j <= p.jb;
+    einc_r[r] = ldp(p.einc, (size_t)n * p.L + (tfr ? j - p.jref : 0), tfr);
+  }
+  T eA = T(0), eB = T(0), hA = T(0), hB = T(0);
+  if (!ADJ && EDGE && p.tf_on) {
+    eA = p.einc[(size_t)n * p.L + (p.ja - p.jref)];
+    eB = p.einc[(size_t)n * p.L + (p.jb - p.jref)];
+    hA = p.hinc[(size_t)n * p.L + (p.ja - 1 - p.jref)];
+    hB = p.hinc[(size_t)n * p.L + (p.jb - p.jref)];
+  }
+
+  // ---------------------------------------------------------------- H
+  // hxv[r]: H_x at (i, jb-1+r); hyv/hylv[r]: H_y at (i+1/2, jb+r) / (i-1/2, jb+r).
+  // Forward: the new field.  Adjoint: the graded new field H*/kappa + nu.
+  T hxv[R + 1], hxn[R + 1], hyv[R], hyn[R], hylv[R];
+  T phxn[R + 1], phyn[R], peyn[R + 2], pexn[R];
+  if (!ADJ) {
+#pragma unroll
+    for (int r = 0; r < R + 1; ++r) {
+      const int j = jb - 1 + r;
+      T h = T(0), ps = T(0);
+      if (colx && j >= 0 && j <= ny - 2) {
+        const T dE = e[r + 1] - e[r];
+        if (pml_h(j, ny, P)) {
+          ps = p.byh[j] * phx[r] + p.ayh[j] * dE;
+          h = hx[r] - p.chx * (dE * p.ikyh[j] + ps);
+        } else {
+          h = hx[r] - p.chx * dE;
+        }
+        if (tfx && j == p.ja - 1) h += p.chx * eA;
+        if (tfx && j == p.jb) h -= p.chx * eB;
+      }
+      hxv[r] = h;
+      hxn[r] = h;
+      phxn[r] = ps;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = jb + r;
+      T h = T(0), hl = T(0), ps = T(0);
+      if (j >= 1 && j <= ny - 2) {
+        const bool tfr = j >= p.ja && j <= p.jb;
+        if (coly) {
+          const T dE = er[r] - e[r + 1];
+          if (pxh) {
+            ps = p.bxh[i] * phy[r] + p.axh[i] * dE;
+            h = hy[r] + p.chx * (dE * p.ikxh[i] + ps);
+          } else {
+            h = hy[r] + p.chx * dE;
+          }
+          if (tfr && i == p.ia - 1) h -= p.chx * einc_r[r];
+          if (tfr && i == p.ib) h += p.chx * einc_r[r];
+        }
+        if (hasl) {
+          const T dE = e[r + 1] - el[r];
+          if (pxhl) {
+            const T psl = p.bxh[i - 1] * phyl[r] + p.axh[i - 1] * dE;
+            hl = hyl[r] + p.chx * (dE * p.ikxh[i - 1] + psl);
+          } else {
+            hl = hyl[r] + p.chx * dE;
+          }
+          if (tfr && i - 1 == p.ia - 1) hl -= p.chx * einc_r[r];
+          if (tfr && i - 1 == p.ib) hl += p.chx * einc_r[r];
+        }
+      }
+      hyv[r] = h;
+      hyn[r] = h;
+      hylv[r] = hl;
+      phyn[r] = ps;
+    }
+  } else {
+    T gy[R + 2], gx[R], gxr[R], gxl[R];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const int j = jb - 1 + r;
+      gy[r] = e[r];
+      peyn[r] = T(0);
+      if (j >= 0 && j < ny && pml_e(j, ny, P)) {
+        peyn[r] = p.bye[j] * pey[r] + p.aye[j] * e[r];
+        gy[r] = e[r] * p.ikye[j] + peyn[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      gx[r] = e[r + 1];
+      pexn[r] = T(0);
+      if (pxe) {
+        pexn[r] = p.bxe[i] * pex[r] + p.axe[i] * e[r + 1];
+        gx[r] = e[r + 1] * p.ikxe[i] + pexn[r];
+      }
+      gxr[r] = pxer ? er[r] * p.ikxe[i + 1] + (p.bxe[i + 1] * pexr[r] + p.axe[i + 1] * er[r]) : er[r];
+      gxl[r] = pxel ? el[r] * p.ikxe[i - 1] + (p.bxe[i - 1] * pexl[r] + p.axe[i - 1] * el[r]) : el[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R + 1; ++r) {
+      const int j = jb - 1 + r;
+      T h = T(0), g = T(0), nu = T(0);
+      if (colx && j >= 0 && j <= ny - 2) {
+        h = hx[r] - p.chx * (gy[r + 1] - gy[r]);
+        g = h;
+        if (pml_h(j, ny, P)) {
+          nu = p.byh[j] * phx[r] + p.ayh[j] * h;
+          g = h * p.ikyh[j] + nu;
+        }
+      }
+      hxn[r] = h;
+      hxv[r] = g;
+      phxn[r] = nu;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = jb + r;
+      T h = T(0), g = T(0), gl = T(0), nu = T(0);
+      if (j >= 1 && j <= ny - 2) {
+        if (coly) {
+          h = hy[r] + p.chx * (gxr[r] - gx[r]);
+          g = h;
+          if (pxh) {
+            nu = p.bxh[i] * phy[r] + p.axh[i] * h;
+            g = h * p.ikxh[i] + nu;
+          }
+        }
+        if (hasl) {
+          const T hl = hyl[r] + p.chx * (gx[r] - gxl[r]);
+          gl = hl;
+          if (pxhl) gl = hl * p.ikxh[i - 1] + (p.bxh[i - 1] * phyl[r] + p.axh[i - 1] * hl);
+        }
+      }
+      hyn[r] = h;
+      hyv[r] = g;
+      hylv[r] = gl;
+      phyn[r] = nu;
+    }
+  }
+
+  // ---------------------------------------------------------------- E, J
+  T en[R], Jn[R], pexf[R], peyf[R];
+  double gnew[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb + r;
+    const T dHy = hyv[r] - hylv[r];
+    const T dHx = hxv[r + 1] - hxv[r];
     T curl;
+    pexf[r] = T(0);
+    peyf[r] = T(0);
     if (!ADJ) {
       T cx = dHy, cy = dHx;
-      if (pml_e(i, nx, P)) {
-        const T ps = p.bxe[i] * p.pex[par][q] + p.axe[i] * dHy;
-        cx = dHy * p.ikxe[i] + ps;
-        p.pex[wr][q] = ps;
+      if (pxe) {
+        pexf[r] = p.bxe[i] * pex[r] + p.axe[i] * dHy;
+        cx = dHy * p.ikxe[i] + pexf[r];
       }
       if (pml_e(j, ny, P)) {
-        const T ps = p.bye[j] * p.pey[par][q] + p.aye[j] * dHx;
-        cy = dHx * p.ikye[j] + ps;
-        p.pey[wr][q] = ps;
+        peyf[r] = p.bye[j] * pey[r + 1] + p.aye[j] * dHx;
+        cy = dHx * p.ikye[j] + peyf[r];
       }
       curl = cx - cy;
-      if (p.tf_on && i >= p.ia && i <= p.ib) {
-        if (j == p.ja) curl += p.hinc[(size_t)n * p.L + (p.ja - 1 - p.jref)];
-        if (j == p.jb) curl -= p.hinc[(size_t)n * p.L + (p.jb - p.jref)];
-      }
+      if (tfx && j == p.ja) curl += hA;
+      if (tfx && j == p.jb) curl -= hB;
     } else {
-      curl = dHy - dHx;
+      curl = dHy - dHx + src[r];
     }
-    const int gi = i - p.gx0, gj = j - p.gy0;
-    const bool gap = gi >= 0 && gi < p.gnx && gj >= 0 && gj < p.gny;
-    const int g = gj * p.gnx + gi;
-    if (ADJ && gap) curl += p.asrc[(size_t)n * p.ng + g];
-    const int di = i - p.dx0, dj = j - p.dy0;
-    const bool des = di >= 0 && di < p.dnx && dj >= 0 && dj < p.dny;
-    const int d = dj * p.dnx + di;
-    const T e0 = ez[q];
+    const int gj = j - p.gy0, dj = j - p.dy0;
+    const bool gap = gcol && gj >= 0 && gj < p.gny;
+    const bool des = dcol && dj >= 0 && dj < p.dny;
+    const T e0 = e[r + 1];
     T e1;
+    Jn[r] = T(0);
+    gnew[r] = 0.0;
     if (des && !gap) {
-      const T r = p.rho[d];
-      const T eps2 = p.A0 + r * p.A1;
-      const T beta = p.B0 + r * p.B1;
-      const T bs = beta * p.dt_ + p.Sg * r * (T(1) - r);
+      const T x = rr[r];
+      const T eps2 = p.A0 + x * p.A1;
+      const T beta = p.B0 + x * p.B1;
+      const T bs = beta * p.dt_ + p.Sg * x * (T(1) - x);
       const T inv = T(2) / (eps2 + bs);
-      const T Jo = p.J[d];
-      const T dE = inv * (p.dtdx * curl - p.dthJ * Jo - bs * e0);
+      const T dE = inv * (p.dtdx * curl - p.dthJ * Jo[r] - bs * e0);
       e1 = e0 + dE;
-      const T Jn = p.kp * Jo + beta * (e0 + e1);
-      p.J[d] = Jn;
-      if (!ADJ) {
-        p.hist[(size_t)n * nd + d] = e1;
-      } else {
-        const T Em = p.hist[(size_t)(n - 1) * nd + d];
-        const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + r * (T(1) - p.rs)));
-        const T gb = p.gsm * (T(1) - T(2) * r);
-        p.grad[d] += (double)(Em * (p.ga * dE + gb * (e0 + e1) + gc * (Jn + Jo)));
+      Jn[r] = p.kp * Jo[r] + beta * (e0 + e1);
+      if (ADJ) {
+        const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + x * (T(1) - p.rs)));
+        const T gb = p.gsm * (T(1) - T(2) * x);
+        gnew[r] = gacc[r] + (double)(Em[r] * (p.ga * dE + gb * (e0 + e1) + gc * (Jn[r] + Jo[r])));
       }
     } else {
       e1 = e0 + (gap ? p.ce_g : p.ce_s) * curl;
-      if (!ADJ && des) p.hist[(size_t)n * nd + d] = e1;
     }
-    p.ez[wr][q] = e1;
-    if (!ADJ && gap) {
-      const double ev = (double)e1;
-      p.gapE[(size_t)(n + 1) * p.ng + g] = ev;
-      const double *ph = p.phasor + (size_t)(n + 1) * p.K * 2;
-      for (int kk = 0; kk < p.K; ++kk) {
-        double *a = p.dft + ((size_t)kk * p.ng + g) * 2;
-        a[0] += p.dt * ev * ph[2 * kk];
-        a[1] -= p.dt * ev * ph[2 * kk + 1];
-      }
+    en[r] = e1;
+  }
+
+  // ---------------------------------------------------------------- stores
+#pragma unroll
+  for (int r = 1; r < R + 1; ++r) {
+    const int j = jb - 1 + r;
+    if (colx && j <= ny - 2) {
+      const size_t q = (size_t)j * pitch + i;
+      hxw[q] = hxn[r];
+      if (pml_h(j, ny, P)) phxw[q] = phxn[r];
     }
   }
+  if (ADJ) {
+#pragma unroll
+    for (int r = 1; r <= R; ++r) {
+      const int j = jb - 1 + r;
+      if (j < ny && pml_e(j, ny, P)) peyw[(size_t)j * pitch + i] = peyn[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = jb + r;
+    if (j >= ny) continue;
+    const size_t q = (size_t)j * pitch + i;
+    const bool inner = j >= 1 && j <= ny - 2;
+    if (ADJ && pxe) pexw[q] = pexn[r];
+    if (inner && coly) {
+      hyw[q] = hyn[r];
+      if (pxh) phyw[q] = phyn[r];
+    }
+    if (!(inner && colx)) continue;
+    ezw[q] = en[r];
+    if (!ADJ) {
+      if (pxe) pexw[q] = pexf[r];
+      if (pml_e(j, ny, P)) peyw[q] = peyf[r];
+    }
+    const int gj = j - p.gy0, dj = j - p.dy0;
+    const bool gap = gcol && gj >= 0 && gj < p.gny;
+    const bool des = dcol && dj >= 0 && dj < p.dny;
+    const int d = dj * p.dnx + di;
+    if (des && !gap) {
+      Jc[d] = Jn[r];
+      if (ADJ) grad[d] = gnew[r];
+    }
+    if (!ADJ && des) hist[(size_t)n * nd + d] = en[r];
+    if (!ADJ && gap) p.gapE[(size_t)(n + 1) * p.ng + gj * p.gnx + gi] = (double)en[r];
+  }
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES) step2d_kernel(const Step2D<T> p, const int n, const int par) {
+  const int nx = p.nx, ny = p.ny, P = p.P;
+  const int nbx = (nx + TXW - 1) / TXW, nby = (ny + TYB - 1) / TYB;
+  int tx, ty;
+  tile_of(blockIdx.x, nbx, nby, tx, ty);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = tx * TXW;
+  const int i = i0 + lane;
+  const int jb = ty * TYB + wave * R;
+  if (jb >= ny) return;  // no barriers in this kernel
+  const int ia = p.tf_on ? p.ia : -8, ib = p.tf_on ? p.ib : -8, ja = p.tf_on ? p.ja : -8, jbt = p.tf_on ? p.jb : -8;
+  if (!wave_is_edge(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
+    if (!wave_touches_box(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) && !wave_touches_box(i0, jb, p.gx0, p.gy0, p.gnx, p.gny))
+      step_bulk(p, par, i, jb);
+    else
+      step_general<T, ADJ, false>(p, n, par, i, jb);
+    return;
+  }
+  step_general<T, ADJ, true>(p, n, par, i, jb);
 }
 
 }  // namespace
 
 template <typename T>
 void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s) {
-  const dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY);
+  const int nbx = (p.nx + TXW - 1) / TXW, nby = (p.ny + TYB - 1) / TYB;
+  const dim3 grid(nbx * nby);
   if (adjoint)
     hipLaunchKernelGGL((step2d_kernel<T, true>), grid, dim3(NT), 0, s, p, n, par);
   else

@@ -22,9 +22,7 @@ struct Step2D {
   const T *rho;                          // density over the design box
   T *hist;                               // forward E over the design box, [N][dny][dnx]
   double *grad;                          // sensitivity sums over the design box (adjoint)
-  double *dft;                           // gap DFT [K][ng][2]
-  const double *phasor;                  // [N+1][K][cos, sin]
-  double *gapE;                          // gap time series [N+1][ng]
+  double *gapE;                          // gap time series [N+1][ng] (the DFT is taken after the solve)
   const T *asrc;                         // adjoint source table [N+1][ng] (scaled by dx and S')
   const T *einc, *hinc;                  // incident line [N+1][L], [N][L]
   const T *bxe, *axe, *ikxe, *bxh, *axh, *ikxh;  // x grading at nodes / half nodes

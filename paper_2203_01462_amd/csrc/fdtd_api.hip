@@ -92,7 +92,7 @@ void fill_params2d(fdtd_ctx *c, Step2D<T> &p) {
     p.phx[b] = c->pml[b][2].as<T>(); p.phy[b] = c->pml[b][3].as<T>();
   }
   p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
-  p.dft = c->dft.as<double>(); p.phasor = c->phasor.as<double>(); p.gapE = c->gapE.as<double>();
+  p.gapE = c->gapE.as<double>();
   p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
   const T **ax[12] = {&p.bxe, &p.axe, &p.ikxe, &p.bxh, &p.axh, &p.ikxh, &p.bye, &p.aye, &p.ikye, &p.byh, &p.ayh, &p.ikyh};
   for (int k = 0; k < 12; ++k) *ax[k] = c->axis[k].as<T>();
@@ -339,10 +339,11 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
     if (ctx->state < 1) throw Error{FDTD_ESTATE, "forward before set_density"};
     ctx->state = 1;
     zero_state(ctx);
-    zero(ctx, ctx->dft);
     zero(ctx, ctx->gapE);
     if (ctx->prec == 32) run_steps<float>(ctx, false); else run_steps<double>(ctx, false);
     const fdtd_config &g = ctx->cfg;
+    launch_dft(ctx->stream, ctx->gapE.as<double>(), ctx->phasor.as<double>(), ctx->K, ctx->nmon, ctx->N, ctx->dt,
+               ctx->dft.as<double>());
     const double te_scale = 0.5 * g.eps_g * ctx->dt * g.dx * g.dx * g.dx;
     launch_objective(ctx->stream, ctx->dft.as<double>(), ctx->wts.as<double>(), ctx->gapE.as<double>(), ctx->K,
                      ctx->nmon, ctx->N, g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_scale, ctx->Fdev.as<double>());

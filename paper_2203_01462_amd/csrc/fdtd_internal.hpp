@@ -131,6 +131,8 @@ void launch_incident_line(hipStream_t s, int precision, const double *g, int N, 
 void launch_phasors(hipStream_t s, const double *freqs, int K, int N, double dt, double *phasor);
 void launch_weights(hipStream_t s, const double *g, const double *freqs, int K, int N, double dt,
                     int unit, double *w);
+void launch_dft(hipStream_t s, const double *gapE, const double *phasor, int K, int nmon, int N, double dt,
+                double *dft);
 void launch_objective(hipStream_t s, const double *dft, const double *w, const double *gapE, int K,
                       int nmon, int N, int time_energy, double te_scale, double *F_out);
 void launch_adjoint_source(hipStream_t s, int precision, const double *dft, const double *w,

@@ -101,6 +101,27 @@ __global__ void weights_kernel(const double *__restrict__ g, const double *__res
   if (threadIdx.x == 0) w[k] = unit ? 1.0 : 1.0 / (R * R + I * I);
 }
 
+// Running DFT of the gap monitors from their time series (one workgroup per
+// frequency k and monitor m): dft[k][m] = dt sum_{n=1..N} E_m^n exp(-j w_k n dt).
+__global__ void dft_kernel(const double *__restrict__ gapE, const double *__restrict__ ph, int K, int nmon, int N,
+                           double dt, double *__restrict__ dft) {
+  __shared__ double sh[16];
+  const int k = blockIdx.x / nmon, m = blockIdx.x % nmon;
+  double re = 0.0, im = 0.0;
+  for (int n = 1 + threadIdx.x; n <= N; n += blockDim.x) {
+    const double e = gapE[(size_t)n * nmon + m];
+    re += e * ph[2 * ((size_t)n * K + k)];
+    im -= e * ph[2 * ((size_t)n * K + k) + 1];
+  }
+  const double R = block_sum(re, sh);
+  __syncthreads();
+  const double I = block_sum(im, sh);
+  if (threadIdx.x == 0) {
+    dft[2 * ((size_t)k * nmon + m)] = dt * R;
+    dft[2 * ((size_t)k * nmon + m) + 1] = dt * I;
+  }
+}
+
 // F = sum_k w_k sum_m |dft[k][m]|^2, or te_scale * sum_n sum_m gapE[n][m]^2.
 __global__ void objective_kernel(const double *__restrict__ dft, const double *__restrict__ w,
                                  const double *__restrict__ gapE, int K, int nmon, int N, int te,
@@ -224,6 +245,12 @@ void launch_phasors(hipStream_t s, const double *freqs, int K, int N, double dt,
 void launch_weights(hipStream_t s, const double *g, const double *freqs, int K, int N, double dt, int unit,
                     double *w) {
   hipLaunchKernelGGL(weights_kernel, dim3(K), dim3(kRed), 0, s, g, freqs, N, dt, unit, w);
+  FDTD_HIP(hipGetLastError());
+}
+
+void launch_dft(hipStream_t s, const double *gapE, const double *phasor, int K, int nmon, int N, double dt,
+                double *dft) {
+  hipLaunchKernelGGL(dft_kernel, dim3((unsigned)(K * nmon)), dim3(kRed), 0, s, gapE, phasor, K, nmon, N, dt, dft);
   FDTD_HIP(hipGetLastError());
 }
 
