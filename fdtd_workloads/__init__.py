@@ -113,10 +113,10 @@ def tiny2d(**over):
 def tiny3d(**over):
     """Small 3D case exercising every feature."""
     w = dict(_COMMON)
-    w.update(name="yee3d_tiny", dims=3, precision=64, n=(22, 22, 26), dx=5e-9,
+    w.update(name="yee3d_tiny", dims=3, precision=64, n=(24, 24, 28), dx=5e-9,
              n_steps=900, pml_cells=5, tfsf_margin=2, t0_over_tau=3.0,
-             design_lo=(7, 7, 10), design_n=(8, 8, 6),
-             gap_lo=(10, 10, 12), gap_n=(2, 2, 2),
+             design_lo=(8, 8, 11), design_n=(8, 8, 6),
+             gap_lo=(11, 11, 13), gap_n=(2, 2, 2),
              lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=4,
              sigma_max=5e5, gamma_mult=4.0)
     w.update(over)

@@ -93,6 +93,9 @@ def lib():
             getattr(L, pre + "_adjoint_ext").argtypes = [P, dp, dp]
             getattr(L, pre + "_step_free").argtypes = [P, C.c_int]
             getattr(L, pre + "_incident_column").argtypes = [P, C.c_int, dp]
+        dpa = C.POINTER(dp)
+        L.or3d_set_state.argtypes = [P, dpa, dpa, dpa]
+        L.or3d_get_state.argtypes = [P, dpa, dpa, dpa]
         L.or2d_set_state.argtypes = [P, dp, dp, dp, dp]
         L.or2d_get_state.argtypes = [P, dp, dp, dp, dp]
         L.or2d_num_threads.restype = C.c_int
@@ -253,6 +256,7 @@ class Oracle:
 
     # -- test hooks ------------------------------------------------------
     def forward_ext(self, q):
+        """q: [N][ny][nx] (2D) or [N][3][nz][ny][nx] (3D) extra source in the curl bracket."""
         q = np.ascontiguousarray(q, dtype=np.float64)
         out = np.zeros_like(q)
         self._check(self._fn("forward_ext")(self.h, _dp(q), _dp(out)))
@@ -264,14 +268,29 @@ class Oracle:
         self._check(self._fn("adjoint_ext")(self.h, _dp(s), _dp(out)))
         return out
 
-    def set_state(self, Ez, Hx, Hy, J):
-        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in (Ez, Hx, Hy, J)]
-        self._check(lib().or2d_set_state(self.h, *[_dp(a) for a in arrs]))
+    def set_state(self, *fields):
+        """2D: (Ez, Hx, Hy, J).  3D: (E[3], H[3], J[3]) lists of arrays."""
+        if self.dims == 2:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in fields]
+            self._check(lib().or2d_set_state(self.h, *[_dp(a) for a in arrs]))
+            return
+        self._keep = []
+        ptrs = []
+        for group in fields:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in group]
+            self._keep += arrs
+            ptrs.append((C.POINTER(C.c_double) * 3)(*[_dp(a) for a in arrs]))
+        self._check(lib().or3d_set_state(self.h, *ptrs))
 
     def get_state(self):
-        arrs = [np.zeros(self.shape) for _ in range(4)]
-        self._check(lib().or2d_get_state(self.h, *[_dp(a) for a in arrs]))
-        return arrs
+        if self.dims == 2:
+            arrs = [np.zeros(self.shape) for _ in range(4)]
+            self._check(lib().or2d_get_state(self.h, *[_dp(a) for a in arrs]))
+            return arrs
+        groups = [[np.zeros(self.shape) for _ in range(3)] for _ in range(3)]
+        ptrs = [(C.POINTER(C.c_double) * 3)(*[_dp(a) for a in g]) for g in groups]
+        self._check(lib().or3d_get_state(self.h, *ptrs))
+        return groups
 
     def step_free(self, k):
         self._check(self._fn("step_free")(self.h, int(k)))
