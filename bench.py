@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -157,7 +157,8 @@ def main():
     achieved = (bf * launches_f + ba * launches_a) / ((fwd_ms + adj_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "step2d_kernel", "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
+                "kernel": "step2d_kernel" if base["dims"] == 2 else "step3d_bulk+step3d_general (one time step)",
+                "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
                 "avg_launch_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
                 "avg_launch_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}
     nx, ny, nz = base["n"]

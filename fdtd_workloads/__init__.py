@@ -97,6 +97,19 @@ def medium2d(**over):
     return w
 
 
+def medium3d(**over):
+    """80^3 3D case large enough to hold plain-background blocks as well as
+    absorber, injection, design and gap blocks; sized for the oracle."""
+    w = dict(_COMMON)
+    w.update(name="yee3d_80", dims=3, precision=64, n=(80, 80, 80), dx=5e-9,
+             n_steps=900, pml_cells=6, tfsf_margin=3, t0_over_tau=3.0,
+             design_lo=(30, 30, 35), design_n=(20, 20, 10),
+             gap_lo=(39, 39, 39), gap_n=(2, 2, 2),
+             lambda_lo=600e-9, lambda_hi=900e-9, n_freq=8)
+    w.update(over)
+    return w
+
+
 def tiny2d(**over):
     """Small 2D TMz case exercising every feature: CPML, plane wave, Drude design, gap."""
     w = dict(_COMMON)
@@ -123,7 +136,8 @@ def tiny3d(**over):
     return w
 
 
-PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "tiny2d": tiny2d, "tiny3d": tiny3d}
+PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "medium3d": medium3d, "tiny2d": tiny2d,
+           "tiny3d": tiny3d}
 
 
 def with_(w, **over):

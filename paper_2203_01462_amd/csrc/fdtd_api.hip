@@ -5,6 +5,7 @@
 #include <memory>
 
 #include "fdtd_2d.hpp"
+#include "fdtd_3d.hpp"
 
 using namespace fdtd;
 
@@ -20,11 +21,15 @@ struct fdtd_ctx {
   int N = 0, K = 0, nd = 0, ng = 0, ncomp = 1, nmon = 0;
   double dt = 0;
   int ia = 0, ib = 0, ja = 0, jb = 0, jref = 0, L = 0;
-  // device memory
-  DevBuf fld[2][3], pml[2][4], J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
-  DevBuf axis[12], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
+  int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
+  // device memory: fields (2D: Ez, Hx, Hy; 3D: Ex, Ey, Ez, Hx, Hy, Hz) and
+  // absorber memories (2D: 4; 3D: 12), two copies each
+  DevBuf fld[2][6], pml[2][12], J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
+  DevBuf axis[18], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
   Step2D<float> p2f{};
   Step2D<double> p2d{};
+  Step3D<float> p3f{};
+  Step3D<double> p3d{};
   int state = 0;  // 0 created, 1 density, 2 forward, 3 adjoint
   double F = 0;
   std::string err;
@@ -145,6 +150,96 @@ void create_2d(fdtd_ctx *c) {
   if (c->prec == 32) build_axis_tables<float>(c); else build_axis_tables<double>(c);
 }
 
+template <typename T>
+void build_axis_tables3(fdtd_ctx *c) {
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  for (int a = 0; a < 3; ++a) {
+    AxisTables<T> t;
+    t.build(c->cfg, c->dt, n3[a], c->cfg.pml_cells);
+    const std::vector<T> *v[6] = {&t.be, &t.ae, &t.ike, &t.bh, &t.ah, &t.ikh};
+    for (int k = 0; k < 6; ++k) upload(c->stream, c->axis[6 * a + k], *v[k]);
+  }
+}
+
+void create_3d(fdtd_ctx *c) {
+  const fdtd_config &g = c->cfg;
+  const int P = g.pml_cells, m = g.tfsf_margin;
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  for (int d = 0; d < 3; ++d) {
+    c->lo3[d] = P + m;
+    c->hi3[d] = n3[d] - 1 - P - m;
+    if (c->lo3[d] < 3 || c->hi3[d] - c->lo3[d] < 2) throw einval("total-field box does not fit inside the absorber");
+    if (!box_inside(g.design_lo[d], g.design_n[d], c->lo3[d] + 1, c->hi3[d] - 1) ||
+        !box_inside(g.gap_lo[d], g.gap_n[d], c->lo3[d] + 1, c->hi3[d] - 1))
+      throw einval("design/gap boxes must lie strictly inside the total-field box");
+  }
+  c->pitch = (c->nx + 31) & ~31;
+  c->nd = g.design_n[0] * g.design_n[1] * g.design_n[2];
+  c->ng = g.gap_n[0] * g.gap_n[1] * g.gap_n[2];
+  c->ncomp = 3;
+  c->nmon = 3 * c->ng;
+  c->jref = c->lo3[2] - 2;
+  c->L = c->hi3[2] + 2 - c->jref + 1;
+  const size_t n = (size_t)c->pitch * c->ny * c->nz * c->esz;
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 6; ++k) c->fld[b][k].alloc(n);
+    for (int k = 0; k < 12; ++k) c->pml[b][k].alloc(n);
+  }
+  if (c->prec == 32) build_axis_tables3<float>(c); else build_axis_tables3<double>(c);
+}
+
+template <typename T>
+void fill_params3d(fdtd_ctx *c, Step3D<T> &p) {
+  const fdtd_config &g = c->cfg;
+  p.n[0] = c->nx; p.n[1] = c->ny; p.n[2] = c->nz;
+  p.pitch = c->pitch;
+  p.sz = (long long)c->pitch * c->ny;
+  p.P = g.pml_cells;
+  for (int d = 0; d < 3; ++d) {
+    p.d0[d] = g.design_lo[d]; p.dn[d] = g.design_n[d];
+    p.g0[d] = g.gap_lo[d]; p.gn[d] = g.gap_n[d];
+    p.lo[d] = c->lo3[d]; p.hi[d] = c->hi3[d];
+  }
+  p.kref = c->jref; p.L = c->L; p.tf_on = 1; p.ng = c->ng;
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 3; ++k) { p.E[b][k] = c->fld[b][k].as<T>(); p.H[b][k] = c->fld[b][3 + k].as<T>(); }
+    int slot = 0;
+    for (int cc = 0; cc < 3; ++cc)
+      for (int u = 0; u < 3; ++u) {
+        p.pE[b][cc][u] = nullptr; p.pH[b][cc][u] = nullptr;
+        if (u == cc) continue;
+        p.pE[b][cc][u] = c->pml[b][slot].as<T>();
+        p.pH[b][cc][u] = c->pml[b][6 + slot].as<T>();
+        ++slot;
+      }
+  }
+  p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
+  p.gapE = c->gapE.as<double>(); p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
+  for (int a = 0; a < 3; ++a) {
+    p.be[a] = c->axis[6 * a + 0].as<T>(); p.ae[a] = c->axis[6 * a + 1].as<T>(); p.ike[a] = c->axis[6 * a + 2].as<T>();
+    p.bh[a] = c->axis[6 * a + 3].as<T>(); p.ah[a] = c->axis[6 * a + 4].as<T>(); p.ikh[a] = c->axis[6 * a + 5].as<T>();
+  }
+  const double dt = c->dt, dx = g.dx;
+  const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
+  const double gam = g.gamma_mult * g.gamma_p;
+  const double den = 1.0 + gam * dt / 2.0;
+  p.ch = T(dt / (kMu0 * dx));
+  p.ce_s = T(dt / (kEps0 * g.eps_s * dx));
+  p.ce_g = T(dt / (kEps0 * g.eps_g * dx));
+  p.A0 = T(2.0 * kEps0 * g.eps_s);
+  p.A1 = T(2.0 * kEps0 * (g.eps_inf - g.eps_s));
+  p.B0 = T(kEps0 * psi_s * dt / 2.0 / den);
+  p.B1 = T(kEps0 * (psi - psi_s) * dt / 2.0 / den);
+  p.Sg = T(g.sigma_max * dt);
+  p.dt_ = T(dt);
+  p.dtdx = T(dt / dx);
+  p.kp = T((1.0 - gam * dt / 2.0) / den);
+  p.dthJ = T(dt * 0.5 * (1.0 + (1.0 - gam * dt / 2.0) / den));
+  p.ga = T(-(kEps0 / dt) * (g.eps_inf - g.eps_s));
+  p.gsm = T(-0.5 * g.sigma_max);
+  p.rs = T(g.psi_s_ratio);
+}
+
 void create_common(fdtd_ctx *c) {
   const fdtd_config &g = c->cfg;
   hipStream_t s = c->stream;
@@ -200,8 +295,8 @@ void zero(fdtd_ctx *c, DevBuf &b) { launch_fill_zero(c->stream, b.p, b.bytes); }
 
 void zero_state(fdtd_ctx *c) {
   for (int b = 0; b < 2; ++b) {
-    for (int k = 0; k < 3; ++k) zero(c, c->fld[b][k]);
-    for (int k = 0; k < 4; ++k) zero(c, c->pml[b][k]);
+    for (int k = 0; k < 6; ++k) if (c->fld[b][k].p) zero(c, c->fld[b][k]);
+    for (int k = 0; k < 12; ++k) if (c->pml[b][k].p) zero(c, c->pml[b][k]);
   }
   zero(c, c->J);
 }
@@ -212,15 +307,30 @@ template <>
 Step2D<float> &params2d<float>(fdtd_ctx *c) { return c->p2f; }
 template <>
 Step2D<double> &params2d<double>(fdtd_ctx *c) { return c->p2d; }
+template <typename T>
+Step3D<T> &params3d(fdtd_ctx *c);
+template <>
+Step3D<float> &params3d<float>(fdtd_ctx *c) { return c->p3f; }
+template <>
+Step3D<double> &params3d<double>(fdtd_ctx *c) { return c->p3d; }
 
 template <typename T>
 void run_steps(fdtd_ctx *c, bool adjoint) {
-  Step2D<T> &p = params2d<T>(c);
   FDTD_HIP(hipEventRecord(c->ev[adjoint ? 2 : 0], c->stream));
-  if (!adjoint) {
-    for (int n = 0; n < c->N; ++n) launch_step2d<T>(p, n, n & 1, false, c->stream);
+  if (c->dims == 2) {
+    Step2D<T> &p = params2d<T>(c);
+    if (!adjoint) {
+      for (int n = 0; n < c->N; ++n) launch_step2d<T>(p, n, n & 1, false, c->stream);
+    } else {
+      for (int m = c->N; m >= 1; --m) launch_step2d<T>(p, m, (c->N - m) & 1, true, c->stream);
+    }
   } else {
-    for (int m = c->N; m >= 1; --m) launch_step2d<T>(p, m, (c->N - m) & 1, true, c->stream);
+    Step3D<T> &p = params3d<T>(c);
+    if (!adjoint) {
+      for (int n = 0; n < c->N; ++n) launch_step3d<T>(p, n, n & 1, false, c->stream);
+    } else {
+      for (int m = c->N; m >= 1; --m) launch_step3d<T>(p, m, (c->N - m) & 1, true, c->stream);
+    }
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[adjoint ? 3 : 1], c->stream));
@@ -281,10 +391,13 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
       c->own_stream = true;
     }
     for (int k = 0; k < 4; ++k) FDTD_HIP(hipEventCreate(&c->ev[k]));
-    if (c->dims == 3) throw einval("dims = 3 is not available in this build");
-    create_2d(c.get());
+    if (c->dims == 2) create_2d(c.get()); else create_3d(c.get());
     create_common(c.get());
-    if (c->prec == 32) fill_params2d(c.get(), c->p2f); else fill_params2d(c.get(), c->p2d);
+    if (c->dims == 2) {
+      if (c->prec == 32) fill_params2d(c.get(), c->p2f); else fill_params2d(c.get(), c->p2d);
+    } else {
+      if (c->prec == 32) fill_params3d(c.get(), c->p3f); else fill_params3d(c.get(), c->p3d);
+    }
     FDTD_HIP(hipStreamSynchronize(c->stream));
     FDTD_HIP(hipGetLastError());
   });
