@@ -29,6 +29,30 @@ import fdtd_workloads as W  # noqa: E402
 METRIC = "Drude-FDTD fwd+adjoint Gcell-updates/s, % HBM roofline; time-to-design vs plain"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (scaled by the copy-probe factors: fetch x2, write x1), recorded with
+# the kernel source they were taken on.  Reported only while that source is
+# unchanged; the summaries live in profiles/.
+MEASURED_TRAFFIC = {
+    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "fa4adb05999414b8",
+                        "fwd": 116.0e6, "adj": 120.2e6,
+                        "profile": "profiles/step2d_kernel_tmz2d_2048_fp32.md"},
+}
+
+
+def measured_traffic(name):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(name)
+    if rec is None:
+        return None, None
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None, None
+    if h != rec["sha256_16"]:
+        return None, None
+    return rec, 0.5 * (rec["fwd"] + rec["adj"])
+
 
 def algorithmic_bytes(w, adjoint):
     """HBM bytes one launch of the fused step kernel must move at minimum:
@@ -155,8 +179,10 @@ def main():
     bf = algorithmic_bytes(base, False)
     ba = algorithmic_bytes(base, True)
     achieved = (bf * launches_f + ba * launches_a) / ((fwd_ms + adj_ms) * 1e-3) / 1e9
+    trec, traffic = measured_traffic(base["name"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_per_launch_fwd_adj": [trec["fwd"], trec["adj"]] if trec else None,
                 "kernel": "step2d_kernel" if base["dims"] == 2 else "step3d_bulk+step3d_general (one time step)",
                 "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
                 "avg_launch_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),

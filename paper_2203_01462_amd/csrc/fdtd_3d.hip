@@ -26,21 +26,38 @@ constexpr int TX = 32, TY = 8, R = 2, NT = TX * TY;
 __device__ __forceinline__ bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
 __device__ __forceinline__ bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
 
+#ifndef FDTD3D_MAP
+#define FDTD3D_MAP 1
+#endif
+#ifndef FDTD3D_GROUP
+#define FDTD3D_GROUP 4
+#endif
+
 // Block -> (bx, by, bz).  Consecutive dispatch slots go round-robin over the
-// 8 XCDs; XCD x takes z-slabs of blocks x, x+8, ... so the blocks sharing a
-// plane neighbourhood share an L2.
+// 8 XCDs (each with its own L2).  Within an XCD blocks are taken x fastest,
+// then y, so in-plane neighbours share an L2.  Mode 1: XCD x takes z-slabs
+// x, x+8, ...; mode 2: one contiguous z-band per XCD; mode 3: runs of
+// FDTD3D_GROUP consecutive z-slabs dealt round-robin to the XCDs (z-halos
+// shared inside a run, slow slabs spread over the XCDs).
 __device__ __forceinline__ void block_of(int bid, int nbx, int nby, int nbz, int &bx, int &by, int &bz) {
-  int t = bid;
-  if (nbz % 8 == 0) {
-    const int k = bid >> 3, per = nbx * nby;
-    bx = k % nbx;
-    by = (k / nbx) % nby;
-    bz = (bid & 7) + 8 * (k / per);
+  const int per = nbx * nby;
+  const int x = bid & 7, k = bid >> 3;
+  if (FDTD3D_MAP == 1 && nbz % 8 == 0) {
+    bx = k % nbx; by = (k / nbx) % nby; bz = x + 8 * (k / per);
     return;
   }
-  bx = t % nbx;
-  by = (t / nbx) % nby;
-  bz = t / (nbx * nby);
+  if (FDTD3D_MAP == 2 && nbz % 8 == 0) {
+    bx = k % nbx; by = (k / nbx) % nby; bz = x * (nbz / 8) + k / per;
+    return;
+  }
+  if (FDTD3D_MAP == 3 && nbz % (8 * FDTD3D_GROUP) == 0) {
+    const int zl = k / per, c = zl / FDTD3D_GROUP, s = zl % FDTD3D_GROUP;
+    bx = k % nbx; by = (k / nbx) % nby; bz = (c * 8 + x) * FDTD3D_GROUP + s;
+    return;
+  }
+  bx = bid % nbx;
+  by = (bid / nbx) % nby;
+  bz = bid / per;
 }
 
 template <typename T>

@@ -404,3 +404,19 @@ def test_error_handling(oracle_mod):
     with pytest.raises(oracle_mod.OracleError) as e:
         o.gradient()
     assert e.value.name == "ESTATE"
+
+
+@pytest.mark.parametrize("source", ["gauss", "sinc_hann"])
+def test_excitation_spectrum_band_edges(oracle_mod, source):
+    """The Gaussian-modulated pulse has half its peak spectral amplitude at the
+    band edges; the paper's Hann-windowed four-lobe sinc (Sec. 2) is nearly
+    flat across the band with rounded edges.  Read through the enhancement
+    weights w_k = 1/|G(f_k)|^2 of a run long enough to hold the whole pulse."""
+    w = W.tiny2d(n_steps=6000, source=source, n_freq=5)
+    o = oracle_mod.Oracle(w)
+    amp = 1.0 / np.sqrt(o.info()["weights"])   # |G(f_k)| at f_lo .. f_hi
+    rel = amp / amp[2]
+    if source == "gauss":
+        assert abs(rel[0] - 0.5) < 2e-3 and abs(rel[-1] - 0.5) < 2e-3, rel
+    else:
+        assert np.all(rel[1:-1] > 0.85) and rel[0] < 0.8 and rel[-1] < 0.8, rel
