@@ -1,58 +1,73 @@
-// fdtd_3d.hip -- fused time step of the 3D Drude-FDTD solve and its adjoint.
+// fdtd_3d.hip -- time step of the 3D Drude-FDTD solve and its adjoint.
 //
 // Per step, on the full Yee cell (Sec. 3.2; eqs. (10a-c)):
 //   H^{n+1/2} = H^{n-1/2} - dt/mu0 curl E^n                (CPML, total-field faces)
 //   E^{n+1} = E^n + 2/D [dt curl H^{n+1/2} - dt (1+kp)/2 J^n - (beta+sigma) dt E^n]
 //   J^{n+1} = kp J^n + beta (E^{n+1} + E^n)                 (Drude edges, eqs. (4)-(5))
 // The adjoint step (eq. (20)) is the same update on (E*, H*, J*) driven by
-// the gap source, with each CPML term replaced by its exact transpose, and it
-// accumulates the per-edge sensitivity of eq. (25) folded with eq. (27).
+// the gap source, with each CPML term replaced by its exact transpose (the
+// grading and the recursive memory act on the differenced field before the
+// difference), and it accumulates the per-edge sensitivity of eq. (25) folded
+// with eq. (27) into one FP64 sum per edge.
 //
-// Work split: a workgroup owns a 32 x 8 x 2 block of cells (one thread per
-// (i, j) column, two cells along z).  Each thread recomputes the new H it
-// needs on the low side (j-1, i-1, k-1) instead of waiting for another
-// workgroup, so a step is one pass over two copies of every array.  Blocks
-// whose reach holds only background dielectric run step3d_bulk (one batch
-// of loads, the plain update, identical for forward and adjoint); all other
-// blocks run step3d_general.  The two kernels are launched back to back on
-// complementary block sets.
+// Work split.  A workgroup owns a 32 x 8 column tile (one thread per (i, j))
+// and marches through KC planes along z, carrying the new H_x, H_y of the
+// plane below (needed by the E update) between planes.  The x/y halo (new H
+// one node to the left and one row down) is recomputed from the previous
+// step's values, which the ping-pong copies keep intact.  A tile-plane is
+// "plain" when its whole reach is background dielectric; all others
+// (absorber, walls, injection faces, Drude design edges, gap) are "general".
+// One step is two launches on one stream: step3d_general first, then
+// step3d_plain, which reads back the general kernel's new H where a plain
+// plane sits on a general one.  The general path keeps its cost down by
+// loading each group of absorber memories only in tiles/planes that reach
+// that absorber (uniform branches), by addressing the whole state of a copy
+// through one base pointer with 32-bit offsets, and by CPML tables that are
+// the identity outside the absorber, so the graded differences need no
+// per-lane branches.
+#include <cstdint>
+#include <type_traits>
+
 #include "fdtd_3d.hpp"
 
 namespace fdtd {
 namespace {
 
-constexpr int TX = 32, TY = 8, R = 2, NT = TX * TY;
+constexpr int TX = 32, TY = 8, NT = TX * TY;
+#ifndef FDTD3D_KC
+#define FDTD3D_KC 8
+#endif
+constexpr int KC = FDTD3D_KC;  // planes per workgroup
+
+// Read-only data with wave-uniform addresses goes through the constant
+// address space, which lets the compiler use scalar loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
 
 __device__ __forceinline__ bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
 __device__ __forceinline__ bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
+__device__ __forceinline__ int slab(int i, int n, int P) { return i < P ? i : i - (n - 1 - 2 * P); }
 
-#ifndef FDTD3D_MAP
-#define FDTD3D_MAP 1
-#endif
-#ifndef FDTD3D_GROUP
-#define FDTD3D_GROUP 4
-#endif
+// Element e of an arena (32-bit byte offsets).
+template <typename T>
+__device__ __forceinline__ T ld(const T *a, uint32_t e) {
+  return *(const T *)((const char *)a + e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T *a, uint32_t e, T v) {
+  *(T *)((char *)a + e * (uint32_t)sizeof(T)) = v;
+}
 
-// Block -> (bx, by, bz).  Consecutive dispatch slots go round-robin over the
-// 8 XCDs (each with its own L2).  Within an XCD blocks are taken x fastest,
-// then y, so in-plane neighbours share an L2.  Mode 1: XCD x takes z-slabs
-// x, x+8, ...; mode 2: one contiguous z-band per XCD; mode 3: runs of
-// FDTD3D_GROUP consecutive z-slabs dealt round-robin to the XCDs (z-halos
-// shared inside a run, slow slabs spread over the XCDs).
+// Workgroup -> (bx, by, bz).  Dispatch slots go round-robin over the 8 XCDs
+// (each with its own L2); XCD x takes z-chunks x, x+8, ..., and inside an XCD
+// tiles run x fastest, then y, so in-plane neighbours share an L2.
 __device__ __forceinline__ void block_of(int bid, int nbx, int nby, int nbz, int &bx, int &by, int &bz) {
   const int per = nbx * nby;
-  const int x = bid & 7, k = bid >> 3;
-  if (FDTD3D_MAP == 1 && nbz % 8 == 0) {
-    bx = k % nbx; by = (k / nbx) % nby; bz = x + 8 * (k / per);
-    return;
-  }
-  if (FDTD3D_MAP == 2 && nbz % 8 == 0) {
-    bx = k % nbx; by = (k / nbx) % nby; bz = x * (nbz / 8) + k / per;
-    return;
-  }
-  if (FDTD3D_MAP == 3 && nbz % (8 * FDTD3D_GROUP) == 0) {
-    const int zl = k / per, c = zl / FDTD3D_GROUP, s = zl % FDTD3D_GROUP;
-    bx = k % nbx; by = (k / nbx) % nby; bz = (c * 8 + x) * FDTD3D_GROUP + s;
+  if (nbz % 8 == 0) {
+    const int k = bid >> 3;
+    bx = k % nbx;
+    by = (k / nbx) % nby;
+    bz = (bid & 7) + 8 * (k / per);
     return;
   }
   bx = bid % nbx;
@@ -60,370 +75,580 @@ __device__ __forceinline__ void block_of(int bid, int nbx, int nby, int nbz, int
   bz = bid / per;
 }
 
+struct Tile {
+  int i0, j0, kb, ke;
+  bool xy_plain;     // x/y reach holds no absorber, wall or injection face
+  bool tf_hit;       // x/y reach meets an injection face line
+  bool tf_meet;      // x/y reach overlaps the total-field box grown by one node
+  bool dxy, gxy;     // tile meets the design / gap box in x/y
+};
+
+// x/y classification of the general kernel's tile with origin (i0, j0).
 template <typename T>
-__device__ __forceinline__ bool block_is_bulk(const Step3D<T> &p, int i0, int j0, int k0) {
-  const int P = p.P;
-  if (i0 < P + 1 || i0 + TX > p.n[0] - 1 - P) return false;
-  if (j0 < P + 1 || j0 + TY > p.n[1] - 1 - P) return false;
-  if (k0 < P + 1 || k0 + R > p.n[2] - 1 - P) return false;
+__device__ __forceinline__ Tile tile_xy(const Step3D<T> &p, int i0, int j0) {
+  const int nx = p.n[0], ny = p.n[1], P = p.P;
+  Tile t;
+  t.i0 = i0;
+  t.j0 = j0;
+  t.kb = t.ke = 0;
+  const int x0 = i0 - 1, x1 = i0 + TX, y0 = j0 - 1, y1 = j0 + TY;
   auto hit = [](int lo, int hi, int v) { return v >= lo && v <= hi; };
-  if (p.tf_on) {
-    const int x0 = i0 - 1, x1 = i0 + TX, y0 = j0 - 1, y1 = j0 + TY, z0 = k0 - 1, z1 = k0 + R;
-    for (int d = -1; d <= 0; ++d) {
-      if (hit(x0, x1, p.lo[0] + d) || hit(x0, x1, p.hi[0] + 1 + d)) return false;
-      if (hit(y0, y1, p.lo[1] + d) || hit(y0, y1, p.hi[1] + 1 + d)) return false;
-      if (hit(z0, z1, p.lo[2] + d) || hit(z0, z1, p.hi[2] + 1 + d)) return false;
-    }
-  }
-  auto meets = [&](const int *b0, const int *bn) {
-    return i0 + TX - 1 >= b0[0] && i0 < b0[0] + bn[0] && j0 + TY - 1 >= b0[1] && j0 < b0[1] + bn[1] &&
-           k0 + R - 1 >= b0[2] && k0 < b0[2] + bn[2];
-  };
-  return !meets(p.d0, p.dn) && !meets(p.g0, p.gn);
+  t.tf_hit = p.tf_on &&
+             (hit(x0, x1, p.lo[0] - 1) || hit(x0, x1, p.lo[0]) || hit(x0, x1, p.hi[0]) || hit(x0, x1, p.hi[0] + 1) ||
+              hit(y0, y1, p.lo[1] - 1) || hit(y0, y1, p.lo[1]) || hit(y0, y1, p.hi[1]) || hit(y0, y1, p.hi[1] + 1));
+  t.tf_meet = p.tf_on && x1 >= p.lo[0] - 1 && x0 <= p.hi[0] + 1 && y1 >= p.lo[1] - 1 && y0 <= p.hi[1] + 1;
+  t.xy_plain = i0 >= P + 1 && i0 + TX <= nx - 1 - P && j0 >= P + 1 && j0 + TY <= ny - 1 - P && !t.tf_hit;
+  t.dxy = i0 + TX - 1 >= p.d0[0] && i0 < p.d0[0] + p.dn[0] && j0 + TY - 1 >= p.d0[1] && j0 < p.d0[1] + p.dn[1];
+  t.gxy = i0 + TX - 1 >= p.g0[0] && i0 < p.g0[0] + p.gn[0] && j0 + TY - 1 >= p.g0[1] && j0 < p.g0[1] + p.gn[1];
+  return t;
 }
 
-// ---------------------------------------------------------------- bulk
+// Tile of a workgroup of the general kernel.
 template <typename T>
-__global__ void __launch_bounds__(NT) step3d_bulk(const Step3D<T> p, const int par) {
-  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + R - 1) / R;
+__device__ __forceinline__ Tile tile_of(const Step3D<T> &p) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY, nbz = (nz + KC - 1) / KC;
   int bx, by, bz;
   block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
-  const int i0 = bx * TX, j0 = by * TY, k0 = bz * R;
-  if (!block_is_bulk(p, i0, j0, k0)) return;
-  const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
-  const long long sy = p.pitch, sz = p.sz;
-  const long long q = (long long)k0 * sz + (long long)j * sy + i;
-  const T *__restrict__ Ex = p.E[par][0];
-  const T *__restrict__ Ey = p.E[par][1];
-  const T *__restrict__ Ez = p.E[par][2];
-  const T *__restrict__ Hx = p.H[par][0];
-  const T *__restrict__ Hy = p.H[par][1];
-  const T *__restrict__ Hz = p.H[par][2];
-  T *__restrict__ Exw = p.E[par ^ 1][0];
-  T *__restrict__ Eyw = p.E[par ^ 1][1];
-  T *__restrict__ Ezw = p.E[par ^ 1][2];
-  T *__restrict__ Hxw = p.H[par ^ 1][0];
-  T *__restrict__ Hyw = p.H[par ^ 1][1];
-  T *__restrict__ Hzw = p.H[par ^ 1][2];
-#define A3(arr, di, dj, dk) arr[q + (di) + (long long)(dj) * sy + (long long)(dk) * sz]
-  T exC[4], exL[3], exN[2], exS[2], exLN[2];
-  T eyC[4], eyS[3], eyR[2], eyRS[2], eyL[2];
-  T ezC[3], ezN[3], ezR[3], ezS[2], ezL[2];
-  T hxC[3], hxS[2], hyC[3], hyL[2], hzC[2], hzS[2], hzL[2];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) { exC[r] = A3(Ex, 0, 0, r - 1); eyC[r] = A3(Ey, 0, 0, r - 1); }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    exL[r] = A3(Ex, -1, 0, r); eyS[r] = A3(Ey, 0, -1, r);
-    ezC[r] = A3(Ez, 0, 0, r - 1); ezN[r] = A3(Ez, 0, 1, r - 1); ezR[r] = A3(Ez, 1, 0, r - 1);
-    hxC[r] = A3(Hx, 0, 0, r - 1); hyC[r] = A3(Hy, 0, 0, r - 1);
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    exN[s] = A3(Ex, 0, 1, s); exS[s] = A3(Ex, 0, -1, s); exLN[s] = A3(Ex, -1, 1, s);
-    eyR[s] = A3(Ey, 1, 0, s); eyRS[s] = A3(Ey, 1, -1, s); eyL[s] = A3(Ey, -1, 0, s);
-    ezS[s] = A3(Ez, 0, -1, s); ezL[s] = A3(Ez, -1, 0, s);
-    hxS[s] = A3(Hx, 0, -1, s); hyL[s] = A3(Hy, -1, 0, s);
-    hzC[s] = A3(Hz, 0, 0, s); hzS[s] = A3(Hz, 0, -1, s); hzL[s] = A3(Hz, -1, 0, s);
-  }
-  const T ch = p.ch, ce = p.ce_s;
-  T hx00[3], hy00[3], hx0m[2], hym0[2], hz00[2], hz0m[2], hzm0[2];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    hx00[r] = hxC[r] - ch * ((ezN[r] - ezC[r]) - (eyC[r + 1] - eyC[r]));
-    hy00[r] = hyC[r] - ch * ((exC[r + 1] - exC[r]) - (ezR[r] - ezC[r]));
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    hx0m[s] = hxS[s] - ch * ((ezC[s + 1] - ezS[s]) - (eyS[s + 1] - eyS[s]));
-    hym0[s] = hyL[s] - ch * ((exL[s + 1] - exL[s]) - (ezC[s + 1] - ezL[s]));
-    hz00[s] = hzC[s] - ch * ((eyR[s] - eyC[s + 1]) - (exN[s] - exC[s + 1]));
-    hz0m[s] = hzS[s] - ch * ((eyRS[s] - eyS[s]) - (exC[s + 1] - exS[s]));
-    hzm0[s] = hzL[s] - ch * ((eyC[s + 1] - eyL[s]) - (exLN[s] - exL[s]));
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    A3(Hxw, 0, 0, s) = hx00[s + 1];
-    A3(Hyw, 0, 0, s) = hy00[s + 1];
-    A3(Hzw, 0, 0, s) = hz00[s];
-    A3(Exw, 0, 0, s) = exC[s + 1] + ce * ((hz00[s] - hz0m[s]) - (hy00[s + 1] - hy00[s]));
-    A3(Eyw, 0, 0, s) = eyC[s + 1] + ce * ((hx00[s + 1] - hx00[s]) - (hz00[s] - hzm0[s]));
-    A3(Ezw, 0, 0, s) = ezC[s + 1] + ce * ((hy00[s + 1] - hym0[s]) - (hx00[s + 1] - hx0m[s]));
-  }
-#undef A3
+  Tile t = tile_xy(p, bx * TX, by * TY);
+  t.kb = bz * KC;
+  t.ke = min(t.kb + KC, nz);
+  return t;
+}
+
+// Plane k of tile t takes the plain update: x/y reach plain, k and its two z
+// neighbours outside the absorber and the walls (so the new H of plane k-1 is
+// ungraded in the adjoint too), k not an injection plane, and the tile-plane
+// misses the design and gap boxes.  Every other tile-plane belongs to the
+// general kernel.
+template <typename T>
+__device__ __forceinline__ bool plane_plain(const Step3D<T> &p, const Tile &t, int k) {
+  const int P = p.P, nz = p.n[2];
+  bool pl = t.xy_plain && k >= P + 1 && k <= nz - 2 - P;
+  if (p.tf_on && (k == p.lo[2] - 1 || k == p.lo[2] || k == p.hi[2])) pl = false;
+  if (t.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2]) pl = false;
+  if (t.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2]) pl = false;
+  return pl;
+}
+
+// CPML grading of one axis at one position: (1/kappa, b, a).  The tables hold
+// (1, 1, 0) outside the absorber, where the memories are zero, so grading is
+// the identity there.
+template <typename T>
+struct Ax {
+  T ik, b, a;
+};
+template <typename T>
+__device__ __forceinline__ Ax<T> ax_id() {
+  return {T(1), T(0), T(0)};
+}
+// kind 0: E (integer) positions, 1: H (half) positions
+template <typename T>
+__device__ __forceinline__ Ax<T> ax_ld(const Step3D<T> &p, int axis, int kind, int i) {
+  const T *t = p.tab + (size_t)(axis * 6 + kind * 3) * p.tn;
+  return {t[2 * p.tn + i], t[i], t[p.tn + i]};
+}
+template <typename T>
+__device__ __forceinline__ Ax<T> ax_ld_uniform(const Step3D<T> &p, int axis, int kind, int i) {
+  const cptr<T> t = (cptr<T>)(p.tab + (size_t)(axis * 6 + kind * 3) * p.tn);
+  return {t[2 * p.tn + i], t[i], t[p.tn + i]};
+}
+
+// Graded value v/kappa + m_new with m_new = b m + a v: in the forward v is a
+// difference and m its memory psi; in the adjoint v is the field itself and m
+// its memory nu.
+template <typename T>
+__device__ __forceinline__ T gr(T v, T m, const Ax<T> &x, T &mn) {
+  mn = x.b * m + x.a * v;
+  return v * x.ik + mn;
 }
 
 // ---------------------------------------------------------------- general
-// Indexing helper: components, validity ranges, bounds-checked loads.
-template <typename T>
-struct G3 {
-  const Step3D<T> &p;
-  int par;
-  long long sy, sz;
-  __device__ G3(const Step3D<T> &p_, int par_) : p(p_), par(par_), sy(p_.pitch), sz(p_.sz) {}
-  __device__ long long at(int i, int j, int k) const { return (long long)k * sz + (long long)j * sy + i; }
-  __device__ bool inside(int i, int j, int k) const {
-    return i >= 0 && i < p.n[0] && j >= 0 && j < p.n[1] && k >= 0 && k < p.n[2];
-  }
-  // E_c is updated for index c in [0, n-2] and the others in [1, n-2];
-  // H_c for index c in [1, n-2] and the others in [0, n-2].
-  __device__ bool evalid(int c, int i, int j, int k) const {
-    const int x[3] = {i, j, k};
-    for (int d = 0; d < 3; ++d)
-      if (x[d] < (d == c ? 0 : 1) || x[d] > p.n[d] - 2) return false;
-    return true;
-  }
-  __device__ bool hvalid(int c, int i, int j, int k) const {
-    const int x[3] = {i, j, k};
-    for (int d = 0; d < 3; ++d)
-      if (x[d] < (d == c ? 1 : 0) || x[d] > p.n[d] - 2) return false;
-    return true;
-  }
-  __device__ T ld(const T *a, int i, int j, int k) const { return inside(i, j, k) ? a[at(i, j, k)] : T(0); }
-  __device__ T einc(int n, int k) const { return p.einc[(long long)n * p.L + (k - p.kref)]; }
-  __device__ T hinc(int n, int k) const { return p.hinc[(long long)n * p.L + (k - p.kref)]; }
-};
-
-// Forward: new H_c at (i,j,k) with CPML and the total-field corrections.
-template <typename T, int C>
-__device__ T h_fwd(const G3<T> &g, int n, int i, int j, int k, bool own) {
-  if (!g.hvalid(C, i, j, k)) return T(0);
-  constexpr int u = (C + 1) % 3, v = (C + 2) % 3;
-  const Step3D<T> &p = g.p;
-  const int x[3] = {i, j, k};
-  int pu[3] = {i, j, k}, pv[3] = {i, j, k};
-  pu[u] += 1;
-  pv[v] += 1;
-  const T *Ev = p.E[g.par][v], *Eu = p.E[g.par][u];
-  const T du = g.ld(Ev, pu[0], pu[1], pu[2]) - g.ld(Ev, i, j, k);
-  const T dv = g.ld(Eu, pv[0], pv[1], pv[2]) - g.ld(Eu, i, j, k);
-  const long long q = g.at(i, j, k);
-  T tu = du * p.ikh[u][x[u]], tv = dv * p.ikh[v][x[v]];
-  if (pml_h(x[u], p.n[u], p.P)) {
-    const T ps = p.bh[u][x[u]] * p.pH[g.par][C][u][q] + p.ah[u][x[u]] * du;
-    tu += ps;
-    if (own) p.pH[g.par ^ 1][C][u][q] = ps;
-  }
-  if (pml_h(x[v], p.n[v], p.P)) {
-    const T ps = p.bh[v][x[v]] * p.pH[g.par][C][v][q] + p.ah[v][x[v]] * dv;
-    tv += ps;
-    if (own) p.pH[g.par ^ 1][C][v][q] = ps;
-  }
-  T h = p.H[g.par][C][q] - p.ch * (tu - tv);
-  if (p.tf_on) {
-    if (C == 1 && i >= p.lo[0] && i <= p.hi[0] - 1 && j >= p.lo[1] && j <= p.hi[1]) {
-      if (k == p.lo[2] - 1) h += p.ch * g.einc(n, p.lo[2]);
-      if (k == p.hi[2]) h -= p.ch * g.einc(n, p.hi[2]);
-    }
-    if (C == 2 && i >= p.lo[0] && i <= p.hi[0] - 1 && k >= p.lo[2] && k <= p.hi[2]) {
-      if (j == p.lo[1] - 1) h -= p.ch * g.einc(n, k);
-      if (j == p.hi[1]) h += p.ch * g.einc(n, k);
-    }
-  }
-  if (own) p.H[g.par ^ 1][C][q] = h;
-  return h;
-}
-
-// Adjoint: E*_V graded along axis U at node (i,j,k): E*/kappa + nu (nu new).
-template <typename T, int V, int U>
-__device__ T ge_adj(const G3<T> &g, int i, int j, int k) {
-  const Step3D<T> &p = g.p;
-  const int x[3] = {i, j, k};
-  const T e = g.ld(p.E[g.par][V], i, j, k);
-  if (!pml_e(x[U], p.n[U], p.P) || !g.inside(i, j, k)) return e;
-  const T nu = p.be[U][x[U]] * p.pE[g.par][V][U][g.at(i, j, k)] + p.ae[U][x[U]] * e;
-  return e * p.ike[U][x[U]] + nu;
-}
-
-// Adjoint: new H*_C at (i,j,k); graded values along its two axes to gu, gv.
-template <typename T, int C>
-__device__ void h_adj(const G3<T> &g, int i, int j, int k, bool own, T &gu, T &gv) {
-  gu = gv = T(0);
-  if (!g.hvalid(C, i, j, k)) return;
-  constexpr int u = (C + 1) % 3, v = (C + 2) % 3;
-  const Step3D<T> &p = g.p;
-  const int x[3] = {i, j, k};
-  int pu[3] = {i, j, k}, pv[3] = {i, j, k};
-  pu[u] += 1;
-  pv[v] += 1;
-  const T du = ge_adj<T, v, u>(g, pu[0], pu[1], pu[2]) - ge_adj<T, v, u>(g, i, j, k);
-  const T dv = ge_adj<T, u, v>(g, pv[0], pv[1], pv[2]) - ge_adj<T, u, v>(g, i, j, k);
-  const long long q = g.at(i, j, k);
-  const T h = p.H[g.par][C][q] - p.ch * (du - dv);
-  gu = h * p.ikh[u][x[u]];
-  gv = h * p.ikh[v][x[v]];
-  if (pml_h(x[u], p.n[u], p.P)) {
-    const T nu = p.bh[u][x[u]] * p.pH[g.par][C][u][q] + p.ah[u][x[u]] * h;
-    gu += nu;
-    if (own) p.pH[g.par ^ 1][C][u][q] = nu;
-  }
-  if (pml_h(x[v], p.n[v], p.P)) {
-    const T nu = p.bh[v][x[v]] * p.pH[g.par][C][v][q] + p.ah[v][x[v]] * h;
-    gv += nu;
-    if (own) p.pH[g.par ^ 1][C][v][q] = nu;
-  }
-  if (own) p.H[g.par ^ 1][C][q] = h;
-}
-
-// E_C (or E*_C) update at an owned node given the curl bracket (in units of
-// H: the difference of the (graded) H values, plus sources).
-template <typename T, bool ADJ, int C>
-__device__ void e_update(const G3<T> &g, int n, int i, int j, int k, T curl) {
-  const Step3D<T> &p = g.p;
-  const long long q = g.at(i, j, k);
-  const int di[3] = {i - p.d0[0], j - p.d0[1], k - p.d0[2]};
-  const int gi[3] = {i - p.g0[0], j - p.g0[1], k - p.g0[2]};
-  const bool des = di[0] >= 0 && di[0] < p.dn[0] && di[1] >= 0 && di[1] < p.dn[1] && di[2] >= 0 && di[2] < p.dn[2];
-  const bool gap = gi[0] >= 0 && gi[0] < p.gn[0] && gi[1] >= 0 && gi[1] < p.gn[1] && gi[2] >= 0 && gi[2] < p.gn[2];
-  const int nd = p.dn[0] * p.dn[1] * p.dn[2];
-  const int d = (di[2] * p.dn[1] + di[1]) * p.dn[0] + di[0];
-  const int gg = (gi[2] * p.gn[1] + gi[1]) * p.gn[0] + gi[0];
-  if (ADJ && gap) curl += p.asrc[((long long)n * p.ng + gg) * 3 + C];
-  const T e0 = p.E[g.par][C][q];
-  T e1;
-  if (des && !gap) {
-    const T r = p.rho[d];
-    const T eps2 = p.A0 + r * p.A1;
-    const T beta = p.B0 + r * p.B1;
-    const T bs = beta * p.dt_ + p.Sg * r * (T(1) - r);
-    const T inv = T(2) / (eps2 + bs);
-    T *Jc = p.J + (long long)C * nd;
-    const T Jo = Jc[d];
-    const T dE = inv * (p.dtdx * curl - p.dthJ * Jo - bs * e0);
-    e1 = e0 + dE;
-    const T Jn = p.kp * Jo + beta * (e0 + e1);
-    Jc[d] = Jn;
-    if (!ADJ) {
-      p.hist[((long long)n * 3 + C) * nd + d] = e1;
-    } else {
-      const T Em = p.hist[((long long)(n - 1) * 3 + C) * nd + d];
-      const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + r * (T(1) - p.rs)));
-      const T gb = p.gsm * (T(1) - T(2) * r);
-      p.grad[(long long)C * nd + d] += (double)(Em * (p.ga * dE + gb * (e0 + e1) + gc * (Jn + Jo)));
-    }
-  } else {
-    e1 = e0 + (gap ? p.ce_g : p.ce_s) * curl;
-    if (!ADJ && des) p.hist[((long long)n * 3 + C) * nd + d] = e1;
-  }
-  p.E[g.par ^ 1][C][q] = e1;
-  if (!ADJ && gap) p.gapE[((long long)(n + 1) * p.ng + gg) * 3 + C] = (double)e1;
-}
-
-// Forward curl bracket of E_C at (i,j,k) from new H values hv0/hv1 (H_v at the
-// node and one step back along u) and hu0/hu1 (H_u at the node and back
-// along v), with the E-side CPML memory and the total-field corrections.
-template <typename T, int C>
-__device__ T curl_fwd(const G3<T> &g, int n, int i, int j, int k, T hv0, T hv1, T hu0, T hu1) {
-  constexpr int u = (C + 1) % 3, v = (C + 2) % 3;
-  const Step3D<T> &p = g.p;
-  const int x[3] = {i, j, k};
-  const long long q = g.at(i, j, k);
-  const T du = hv0 - hv1, dv = hu0 - hu1;
-  T tu = du * p.ike[u][x[u]], tv = dv * p.ike[v][x[v]];
-  if (pml_e(x[u], p.n[u], p.P)) {
-    const T ps = p.be[u][x[u]] * p.pE[g.par][C][u][q] + p.ae[u][x[u]] * du;
-    tu += ps;
-    p.pE[g.par ^ 1][C][u][q] = ps;
-  }
-  if (pml_e(x[v], p.n[v], p.P)) {
-    const T ps = p.be[v][x[v]] * p.pE[g.par][C][v][q] + p.ae[v][x[v]] * dv;
-    tv += ps;
-    p.pE[g.par ^ 1][C][v][q] = ps;
-  }
-  T curl = tu - tv;
-  if (p.tf_on) {
-    if (C == 0 && i >= p.lo[0] && i <= p.hi[0] - 1 && j >= p.lo[1] && j <= p.hi[1]) {
-      if (k == p.lo[2]) curl += g.hinc(n, p.lo[2] - 1);
-      if (k == p.hi[2]) curl -= g.hinc(n, p.hi[2]);
-    }
-    if (C == 2 && j >= p.lo[1] && j <= p.hi[1] && k >= p.lo[2] && k <= p.hi[2] - 1) {
-      if (i == p.lo[0]) curl -= g.hinc(n, k);
-      if (i == p.hi[0]) curl += g.hinc(n, k);
-    }
-  }
-  return curl;
-}
-
-// Adjoint: store the new nu of the owned E*_C node along both its axes.
-template <typename T, int C>
-__device__ void store_nu_e(const G3<T> &g, int i, int j, int k) {
-  constexpr int u = (C + 1) % 3, v = (C + 2) % 3;
-  const Step3D<T> &p = g.p;
-  const int x[3] = {i, j, k};
-  const long long q = g.at(i, j, k);
-  const T e = p.E[g.par][C][q];
-  if (pml_e(x[u], p.n[u], p.P)) p.pE[g.par ^ 1][C][u][q] = p.be[u][x[u]] * p.pE[g.par][C][u][q] + p.ae[u][x[u]] * e;
-  if (pml_e(x[v], p.n[v], p.P)) p.pE[g.par ^ 1][C][v][q] = p.be[v][x[v]] * p.pE[g.par][C][v][q] + p.ae[v][x[v]] * e;
-}
-
 template <typename T, bool ADJ>
-__global__ void __launch_bounds__(NT) step3d_general(const Step3D<T> p, const int n, const int par) {
-  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + R - 1) / R;
+__global__ void __launch_bounds__(NT) step3d_general(const Step3D<T> p, const int n) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2], P = p.P;
+  const Tile tl = tile_of(p);
+  const int i = tl.i0 + (threadIdx.x % TX), j = tl.j0 + (threadIdx.x / TX);
+  if (i >= nx || j >= ny) return;  // no barriers in this kernel
+  const T *__restrict__ R = p.A[0];
+  T *__restrict__ Wr = p.A[1];
+  const uint32_t pitch = p.pitch, PL = p.PL, S = p.S, W = p.W;
+  const uint32_t EX = 0, EY = S, EZ = 2 * S, HX = 3 * S, HY = 4 * S, HZ = 5 * S;
+  const uint32_t qxy = p.G0 + (uint32_t)j * pitch + (uint32_t)i;
+
+  // absorber groups reached by this tile (uniform)
+  const bool tx = P > 0 && (tl.i0 <= P || tl.i0 + TX >= nx - 1 - P);
+  const bool ty = P > 0 && (tl.j0 <= P || tl.j0 + TY >= ny - 1 - P);
+  // per-lane absorber flags along x and y
+  const bool okL = i >= 1, okR = i + 1 < nx, okS = j >= 1, okN = j + 1 < ny;
+  const bool hx_i = pml_h(i, nx, P), hx_im = okL && pml_h(i - 1, nx, P);
+  const bool ex_i = pml_e(i, nx, P), ex_im = okL && pml_e(i - 1, nx, P), ex_ip = okR && pml_e(i + 1, nx, P);
+  const bool hy_j = pml_h(j, ny, P), hy_jm = okS && pml_h(j - 1, ny, P);
+  const bool ey_j = pml_e(j, ny, P), ey_jm = okS && pml_e(j - 1, ny, P), ey_jp = okN && pml_e(j + 1, ny, P);
+  Ax<T> xh0 = ax_id<T>(), xhm = ax_id<T>(), xe0 = ax_id<T>(), xem = ax_id<T>(), xep = ax_id<T>();
+  Ax<T> yh0 = ax_id<T>(), yhm = ax_id<T>(), ye0 = ax_id<T>(), yem = ax_id<T>(), yep = ax_id<T>();
+  if (tx) {
+    const int im = max(i - 1, 0), ip = min(i + 1, nx - 1);
+    xh0 = ax_ld(p, 0, 1, i);
+    xhm = ax_ld(p, 0, 1, im);
+    xe0 = ax_ld(p, 0, 0, i);
+    if (ADJ) {
+      xem = ax_ld(p, 0, 0, im);
+      xep = ax_ld(p, 0, 0, ip);
+    }
+  }
+  if (ty) {
+    const int jm = max(j - 1, 0), jp = min(j + 1, ny - 1);
+    yh0 = ax_ld(p, 1, 1, j);
+    yhm = ax_ld(p, 1, 1, jm);
+    ye0 = ax_ld(p, 1, 0, j);
+    if (ADJ) {
+      yem = ax_ld(p, 1, 0, jm);
+      yep = ax_ld(p, 1, 0, jp);
+    }
+  }
+  // slab offsets of this column (meaningful only where the matching flag is set)
+  const uint32_t oX0 = (uint32_t)j * W + (uint32_t)slab(i, nx, P);
+  const uint32_t oXm = (uint32_t)j * W + (uint32_t)slab(i - 1, nx, P);
+  const uint32_t oXp = (uint32_t)j * W + (uint32_t)slab(i + 1, nx, P);
+  const uint32_t oY0 = (uint32_t)slab(j, ny, P) * pitch + (uint32_t)i;
+  const uint32_t oYm = (uint32_t)slab(j - 1, ny, P) * pitch + (uint32_t)i;
+  const uint32_t oYp = (uint32_t)slab(j + 1, ny, P) * pitch + (uint32_t)i;
+  const uint32_t oZ = (uint32_t)j * pitch + (uint32_t)i;
+  // wall validity along x and y of the owned and neighbour positions
+  auto rng = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+  const bool xa1 = rng(i, 1, nx - 2), xa0 = rng(i, 0, nx - 2), xm0 = rng(i - 1, 0, nx - 2);
+  const bool ya1 = rng(j, 1, ny - 2), ya0 = rng(j, 0, ny - 2), ym0 = rng(j - 1, 0, ny - 2);
+  // design and gap columns
+  const int nd = p.dn[0] * p.dn[1] * p.dn[2];
+  const int di = i - p.d0[0], dj = j - p.d0[1], gi = i - p.g0[0], gj = j - p.g0[1];
+  const bool dcol = di >= 0 && di < p.dn[0] && dj >= 0 && dj < p.dn[1];
+  const bool gcol = gi >= 0 && gi < p.gn[0] && gj >= 0 && gj < p.gn[1];
+
+  // new H_x, H_y of the plane below (adjoint: graded along z), carried
+  T hxp = T(0), hyp = T(0);
+
+  auto plane = [&](auto store_tag, const int k) {
+    constexpr bool STORE = decltype(store_tag)::value;
+    if (k < 0) {  // below the grid: no H
+      hxp = hyp = T(0);
+      return;
+    }
+    const bool kh = k <= nz - 2, kz = k >= 1 && k <= nz - 2, okU = k + 1 < nz;
+    const bool vx00 = xa1 && ya0 && kh, vx0m = xa1 && ym0 && kh;
+    const bool vy00 = xa0 && ya1 && kh, vym0 = xm0 && ya1 && kh;
+    const bool vz00 = xa0 && ya0 && kz, vz0m = xa0 && ym0 && kz, vzm0 = xm0 && ya0 && kz;
+    const bool vex = xa0 && ya1 && kz, vey = xa1 && ya0 && kz, vez = xa1 && ya1 && kh;
+    // absorber along z at this plane (uniform)
+    const bool hz_k = pml_h(k, nz, P), ez_k = pml_e(k, nz, P), ez_k1 = okU && pml_e(k + 1, nz, P);
+    const bool tz = hz_k || ez_k || ez_k1;
+    Ax<T> zh = ax_id<T>(), ze = ax_id<T>(), ze1 = ax_id<T>();
+    uint32_t zb = 0, zb1 = 0;
+    if (tz) {
+      zh = ax_ld_uniform(p, 2, 1, k);
+      ze = ax_ld_uniform(p, 2, 0, k);
+      if (ADJ) ze1 = ax_ld_uniform(p, 2, 0, min(k + 1, nz - 1));
+      zb = p.zs + (uint32_t)slab(k, nz, P) * PL + oZ;
+      zb1 = p.zs + (uint32_t)slab(k + 1, nz, P) * PL + oZ;
+    }
+    const uint32_t xb = p.xs + (uint32_t)k * ny * W, yb = p.ys + (uint32_t)k * W * pitch;
+    // injection, design and gap at this tile-plane (uniform)
+    const bool tfp = tl.tf_meet && k >= p.lo[2] - 1 && k <= p.hi[2] &&
+                     (tl.tf_hit || k == p.lo[2] - 1 || k == p.lo[2] || k == p.hi[2]);
+    const bool dp = tl.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2];
+    const bool gp = tl.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2];
+    const bool des = dp && dcol, gap = gp && gcol, drude = des && !gap;
+    const uint32_t d = des ? (uint32_t)(((k - p.d0[2]) * p.dn[1] + dj) * p.dn[0] + di) : 0u;
+    const uint32_t g = gap ? (uint32_t)(((k - p.g0[2]) * p.gn[1] + gj) * p.gn[0] + gi) : 0u;
+
+    const uint32_t q = qxy + (uint32_t)k * PL;
+    // fields (the guard keeps every neighbour offset inside the arena; values
+    // read across an edge only feed nodes that the wall masks discard)
+    const T exC = ld(R, EX + q), exLl = ld(R, EX + q - 1), exN = ld(R, EX + q + pitch), exS = ld(R, EX + q - pitch);
+    const T exLN = ld(R, EX + q + pitch - 1), exc1 = ld(R, EX + q + PL), exl1 = ld(R, EX + q + PL - 1);
+    const T eyC = ld(R, EY + q), eySl = ld(R, EY + q - pitch), eyR = ld(R, EY + q + 1), eyRS = ld(R, EY + q + 1 - pitch);
+    const T eyL = ld(R, EY + q - 1), eyc1 = ld(R, EY + q + PL), eys1 = ld(R, EY + q + PL - pitch);
+    const T ezC = ld(R, EZ + q), ezN = ld(R, EZ + q + pitch), ezR = ld(R, EZ + q + 1), ezS = ld(R, EZ + q - pitch);
+    const T ezL = ld(R, EZ + q - 1);
+    const T hxC = ld(R, HX + q), hxS = ld(R, HX + q - pitch), hyC = ld(R, HY + q), hyL = ld(R, HY + q - 1);
+    const T hzC = ld(R, HZ + q), hzS = ld(R, HZ + q - pitch), hzL = ld(R, HZ + q - 1);
+    // design edges and gap
+    const T rr = dp ? ld(p.rho, d) : T(0);
+    T Jo[3] = {T(0), T(0), T(0)}, Em[3] = {T(0), T(0), T(0)}, src[3] = {T(0), T(0), T(0)};
+    double gacc[3] = {0.0, 0.0, 0.0};
+    if (dp) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Jo[c] = ld(p.J, drude ? (uint32_t)c * nd + d : 0u);
+        if (ADJ) {
+          Em[c] = p.hist[drude ? ((size_t)(n - 1) * 3 + c) * nd + d : 0];
+          gacc[c] = p.grad[drude ? (size_t)c * nd + d : 0];
+        }
+      }
+    }
+    if (ADJ && gp) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) src[c] = gap ? p.asrc[((size_t)n * p.ng + g) * 3 + c] : T(0);
+    }
+
+    T hx00, hx0m, hy00, hym0, hz00, hz0m, hzm0;  // forward: new H; adjoint: new H*
+    T cx, cy, cz;                                  // curl brackets of the three E updates
+    T sn[12];                                      // new memories of the owned nodes
+    T t;
+    if constexpr (!ADJ) {
+      // old memories of the differences below
+      T s_hx00y = 0, s_hx0my = 0, s_hz00y = 0, s_hz0my = 0, s_hzm0y = 0, s_exy = 0, s_ezy = 0;
+      T s_hy00x = 0, s_hym0x = 0, s_hz00x = 0, s_hz0mx = 0, s_hzm0x = 0, s_eyx = 0, s_ezx = 0;
+      T s_hx00z = 0, s_hx0mz = 0, s_hy00z = 0, s_hym0z = 0, s_exz = 0, s_eyz = 0;
+      if (ty) {
+        s_hx00y = ld(R, vx00 && hy_j ? yb + oY0 : 0u);
+        s_hx0my = ld(R, vx0m && hy_jm ? yb + oYm : 0u);
+        s_hz00y = ld(R, vz00 && hy_j ? yb + p.YS + oY0 : 0u);
+        s_hz0my = ld(R, vz0m && hy_jm ? yb + p.YS + oYm : 0u);
+        s_hzm0y = ld(R, vzm0 && hy_j ? yb + p.YS + oY0 - 1 : 0u);
+        s_exy = ld(R, vex && ey_j ? yb + 2 * p.YS + oY0 : 0u);
+        s_ezy = ld(R, vez && ey_j ? yb + 3 * p.YS + oY0 : 0u);
+      }
+      if (tx) {
+        s_hy00x = ld(R, vy00 && hx_i ? xb + oX0 : 0u);
+        s_hym0x = ld(R, vym0 && hx_im ? xb + oXm : 0u);
+        s_hz00x = ld(R, vz00 && hx_i ? xb + p.XS + oX0 : 0u);
+        s_hz0mx = ld(R, vz0m && hx_i ? xb + p.XS + oX0 - W : 0u);
+        s_hzm0x = ld(R, vzm0 && hx_im ? xb + p.XS + oXm : 0u);
+        s_eyx = ld(R, vey && ex_i ? xb + 2 * p.XS + oX0 : 0u);
+        s_ezx = ld(R, vez && ex_i ? xb + 3 * p.XS + oX0 : 0u);
+      }
+      if (tz) {
+        s_hx00z = ld(R, vx00 && hz_k ? zb : 0u);
+        s_hx0mz = ld(R, vx0m && hz_k ? zb - pitch : 0u);
+        s_hy00z = ld(R, vy00 && hz_k ? zb + p.ZS : 0u);
+        s_hym0z = ld(R, vym0 && hz_k ? zb + p.ZS - 1 : 0u);
+        s_exz = ld(R, vex && ez_k ? zb + 2 * p.ZS : 0u);
+        s_eyz = ld(R, vey && ez_k ? zb + 3 * p.ZS : 0u);
+      }
+      const T ch = p.ch;
+      // H_x: d_y E_z - d_z E_y;  H_y: d_z E_x - d_x E_z;  H_z: d_x E_y - d_y E_x
+      hx00 = hxC - ch * (gr(ezN - ezC, s_hx00y, yh0, sn[0]) - gr(eyc1 - eyC, s_hx00z, zh, sn[1]));
+      hx0m = hxS - ch * (gr(ezC - ezS, s_hx0my, yhm, t) - gr(eys1 - eySl, s_hx0mz, zh, t));
+      hy00 = hyC - ch * (gr(exc1 - exC, s_hy00z, zh, sn[2]) - gr(ezR - ezC, s_hy00x, xh0, sn[3]));
+      hym0 = hyL - ch * (gr(exl1 - exLl, s_hym0z, zh, t) - gr(ezC - ezL, s_hym0x, xhm, t));
+      hz00 = hzC - ch * (gr(eyR - eyC, s_hz00x, xh0, sn[4]) - gr(exN - exC, s_hz00y, yh0, sn[5]));
+      hz0m = hzS - ch * (gr(eyRS - eySl, s_hz0mx, xh0, t) - gr(exC - exS, s_hz0my, yhm, t));
+      hzm0 = hzL - ch * (gr(eyC - eyL, s_hzm0x, xhm, t) - gr(exLN - exLl, s_hzm0y, yh0, t));
+      T hA = T(0), hB = T(0), hK = T(0);
+      if (tfp) {
+        // total-field / scattered-field corrections from the incident line
+        const cptr<T> ei = (cptr<T>)(p.einc + (size_t)n * p.L);
+        const cptr<T> hi = (cptr<T>)(p.hinc + (size_t)n * p.L);
+        const bool kin = k >= p.lo[2] && k <= p.hi[2];
+        const T eA = ei[p.lo[2] - p.kref], eB = ei[p.hi[2] - p.kref], eK = kin ? ei[k - p.kref] : T(0);
+        hA = hi[p.lo[2] - 1 - p.kref];
+        hB = hi[p.hi[2] - p.kref];
+        hK = kin ? hi[k - p.kref] : T(0);
+        const bool xin0 = i >= p.lo[0] && i <= p.hi[0] - 1, xinm = i - 1 >= p.lo[0] && i - 1 <= p.hi[0] - 1;
+        const bool yin = j >= p.lo[1] && j <= p.hi[1];
+        if (yin && k == p.lo[2] - 1) {
+          if (xin0) hy00 += ch * eA;
+          if (xinm) hym0 += ch * eA;
+        }
+        if (yin && k == p.hi[2]) {
+          if (xin0) hy00 -= ch * eB;
+          if (xinm) hym0 -= ch * eB;
+        }
+        if (kin) {
+          if (xin0 && j == p.lo[1] - 1) hz00 -= ch * eK;
+          if (xin0 && j == p.hi[1]) hz00 += ch * eK;
+          if (xin0 && j - 1 == p.lo[1] - 1) hz0m -= ch * eK;
+          if (xin0 && j - 1 == p.hi[1]) hz0m += ch * eK;
+          if (xinm && j == p.lo[1] - 1) hzm0 -= ch * eK;
+          if (xinm && j == p.hi[1]) hzm0 += ch * eK;
+        }
+      }
+      // walls hold no H
+      hx00 = vx00 ? hx00 : T(0);
+      hx0m = vx0m ? hx0m : T(0);
+      hy00 = vy00 ? hy00 : T(0);
+      hym0 = vym0 ? hym0 : T(0);
+      hz00 = vz00 ? hz00 : T(0);
+      hz0m = vz0m ? hz0m : T(0);
+      hzm0 = vzm0 ? hzm0 : T(0);
+      // E_x: d_y H_z - d_z H_y;  E_y: d_z H_x - d_x H_z;  E_z: d_x H_y - d_y H_x
+      cx = gr(hz00 - hz0m, s_exy, ye0, sn[6]) - gr(hy00 - hyp, s_exz, ze, sn[7]);
+      cy = gr(hx00 - hxp, s_eyz, ze, sn[8]) - gr(hz00 - hzm0, s_eyx, xe0, sn[9]);
+      cz = gr(hy00 - hym0, s_ezx, xe0, sn[10]) - gr(hx00 - hx0m, s_ezy, ye0, sn[11]);
+      if (tfp) {
+        if (i >= p.lo[0] && i <= p.hi[0] - 1 && j >= p.lo[1] && j <= p.hi[1]) {
+          if (k == p.lo[2]) cx += hA;
+          if (k == p.hi[2]) cx -= hB;
+        }
+        if (j >= p.lo[1] && j <= p.hi[1] && k >= p.lo[2] && k <= p.hi[2] - 1) {
+          if (i == p.lo[0]) cz -= hK;
+          if (i == p.hi[0]) cz += hK;
+        }
+      }
+      hxp = hx00;
+      hyp = hy00;
+    } else {
+      // old memories of the E* values graded below (transposed CPML) and of the new H*
+      T n_ezyN = 0, n_ezyC = 0, n_ezyS = 0, n_exyN = 0, n_exyC = 0, n_exyS = 0, n_exyLN = 0, n_exyL = 0;
+      T n_hx00y = 0, n_hx0my = 0, n_hz00y = 0, n_hz0my = 0;
+      T n_ezxR = 0, n_ezxC = 0, n_ezxL = 0, n_eyxR = 0, n_eyxC = 0, n_eyxRS = 0, n_eyxS = 0, n_eyxL = 0;
+      T n_hy00x = 0, n_hym0x = 0, n_hz00x = 0, n_hzm0x = 0;
+      T n_eyzU = 0, n_eyzC = 0, n_eyzSU = 0, n_eyzS = 0, n_exzU = 0, n_exzC = 0, n_exzLU = 0, n_exzL = 0;
+      T n_hx00z = 0, n_hy00z = 0;
+      if (ty) {
+        const uint32_t yEx = yb + 2 * p.YS, yEz = yb + 3 * p.YS;
+        n_ezyN = ld(R, ey_jp ? yEz + oYp : 0u);
+        n_ezyC = ld(R, ey_j ? yEz + oY0 : 0u);
+        n_ezyS = ld(R, ey_jm ? yEz + oYm : 0u);
+        n_exyN = ld(R, ey_jp ? yEx + oYp : 0u);
+        n_exyC = ld(R, ey_j ? yEx + oY0 : 0u);
+        n_exyS = ld(R, ey_jm ? yEx + oYm : 0u);
+        n_exyLN = ld(R, okL && ey_jp ? yEx + oYp - 1 : 0u);
+        n_exyL = ld(R, okL && ey_j ? yEx + oY0 - 1 : 0u);
+        n_hx00y = ld(R, vx00 && hy_j ? yb + oY0 : 0u);
+        n_hx0my = ld(R, vx0m && hy_jm ? yb + oYm : 0u);
+        n_hz00y = ld(R, vz00 && hy_j ? yb + p.YS + oY0 : 0u);
+        n_hz0my = ld(R, vz0m && hy_jm ? yb + p.YS + oYm : 0u);
+      }
+      if (tx) {
+        const uint32_t xEy = xb + 2 * p.XS, xEz = xb + 3 * p.XS;
+        n_ezxR = ld(R, ex_ip ? xEz + oXp : 0u);
+        n_ezxC = ld(R, ex_i ? xEz + oX0 : 0u);
+        n_ezxL = ld(R, ex_im ? xEz + oXm : 0u);
+        n_eyxR = ld(R, ex_ip ? xEy + oXp : 0u);
+        n_eyxC = ld(R, ex_i ? xEy + oX0 : 0u);
+        n_eyxRS = ld(R, okS && ex_ip ? xEy + oXp - W : 0u);
+        n_eyxS = ld(R, okS && ex_i ? xEy + oX0 - W : 0u);
+        n_eyxL = ld(R, ex_im ? xEy + oXm : 0u);
+        n_hy00x = ld(R, vy00 && hx_i ? xb + oX0 : 0u);
+        n_hym0x = ld(R, vym0 && hx_im ? xb + oXm : 0u);
+        n_hz00x = ld(R, vz00 && hx_i ? xb + p.XS + oX0 : 0u);
+        n_hzm0x = ld(R, vzm0 && hx_im ? xb + p.XS + oXm : 0u);
+      }
+      if (tz) {
+        n_eyzU = ld(R, ez_k1 ? zb1 + 3 * p.ZS : 0u);
+        n_eyzC = ld(R, ez_k ? zb + 3 * p.ZS : 0u);
+        n_eyzSU = ld(R, okS && ez_k1 ? zb1 + 3 * p.ZS - pitch : 0u);
+        n_eyzS = ld(R, okS && ez_k ? zb + 3 * p.ZS - pitch : 0u);
+        n_exzU = ld(R, ez_k1 ? zb1 + 2 * p.ZS : 0u);
+        n_exzC = ld(R, ez_k ? zb + 2 * p.ZS : 0u);
+        n_exzLU = ld(R, okL && ez_k1 ? zb1 + 2 * p.ZS - 1 : 0u);
+        n_exzL = ld(R, okL && ez_k ? zb + 2 * p.ZS - 1 : 0u);
+        n_hx00z = ld(R, vx00 && hz_k ? zb : 0u);
+        n_hy00z = ld(R, vy00 && hz_k ? zb + p.ZS : 0u);
+      }
+      // graded E*
+      const T gyEzN = gr(ezN, n_ezyN, yep, t), gyEzC = gr(ezC, n_ezyC, ye0, sn[11]), gyEzS = gr(ezS, n_ezyS, yem, t);
+      const T gzEyU = gr(eyc1, n_eyzU, ze1, t), gzEyC = gr(eyC, n_eyzC, ze, sn[8]);
+      const T gzEySU = gr(eys1, n_eyzSU, ze1, t), gzEyS = gr(eySl, n_eyzS, ze, t);
+      const T gzExU = gr(exc1, n_exzU, ze1, t), gzExC = gr(exC, n_exzC, ze, sn[7]);
+      const T gzExLU = gr(exl1, n_exzLU, ze1, t), gzExL = gr(exLl, n_exzL, ze, t);
+      const T gxEzR = gr(ezR, n_ezxR, xep, t), gxEzC = gr(ezC, n_ezxC, xe0, sn[10]), gxEzL = gr(ezL, n_ezxL, xem, t);
+      const T gxEyR = gr(eyR, n_eyxR, xep, t), gxEyC = gr(eyC, n_eyxC, xe0, sn[9]);
+      const T gxEyRS = gr(eyRS, n_eyxRS, xep, t), gxEyS = gr(eySl, n_eyxS, xe0, t), gxEyL = gr(eyL, n_eyxL, xem, t);
+      const T gyExN = gr(exN, n_exyN, yep, t), gyExC = gr(exC, n_exyC, ye0, sn[6]), gyExS = gr(exS, n_exyS, yem, t);
+      const T gyExLN = gr(exLN, n_exyLN, yep, t), gyExL = gr(exLl, n_exyL, ye0, t);
+      const T ch = p.ch;
+      hx00 = vx00 ? hxC - ch * ((gyEzN - gyEzC) - (gzEyU - gzEyC)) : T(0);
+      hx0m = vx0m ? hxS - ch * ((gyEzC - gyEzS) - (gzEySU - gzEyS)) : T(0);
+      hy00 = vy00 ? hyC - ch * ((gzExU - gzExC) - (gxEzR - gxEzC)) : T(0);
+      hym0 = vym0 ? hyL - ch * ((gzExLU - gzExL) - (gxEzC - gxEzL)) : T(0);
+      hz00 = vz00 ? hzC - ch * ((gxEyR - gxEyC) - (gyExN - gyExC)) : T(0);
+      hz0m = vz0m ? hzS - ch * ((gxEyRS - gxEyS) - (gyExC - gyExS)) : T(0);
+      hzm0 = vzm0 ? hzL - ch * ((gxEyC - gxEyL) - (gyExLN - gyExL)) : T(0);
+      // graded H* for the E* brackets
+      const T gyHx00 = gr(hx00, n_hx00y, yh0, sn[0]), gzHx00 = gr(hx00, n_hx00z, zh, sn[1]);
+      const T gyHx0m = gr(hx0m, n_hx0my, yhm, t);
+      const T gzHy00 = gr(hy00, n_hy00z, zh, sn[2]), gxHy00 = gr(hy00, n_hy00x, xh0, sn[3]);
+      const T gxHym0 = gr(hym0, n_hym0x, xhm, t);
+      const T gxHz00 = gr(hz00, n_hz00x, xh0, sn[4]), gyHz00 = gr(hz00, n_hz00y, yh0, sn[5]);
+      const T gyHz0m = gr(hz0m, n_hz0my, yhm, t), gxHzm0 = gr(hzm0, n_hzm0x, xhm, t);
+      cx = (gyHz00 - gyHz0m) - (gzHy00 - hyp) + src[0];
+      cy = (gzHx00 - hxp) - (gxHz00 - gxHzm0) + src[1];
+      cz = (gxHy00 - gxHym0) - (gyHx00 - gyHx0m) + src[2];
+      hxp = gzHx00;
+      hyp = gzHy00;
+    }
+    if constexpr (!STORE) return;
+
+    // E (or E*) and J on the owned edges
+    const T e0[3] = {exC, eyC, ezC};
+    const T curl[3] = {cx, cy, cz};
+    const bool ev[3] = {vex, vey, vez};
+    const T ce = gap ? p.ce_g : p.ce_s;
+    T e1[3], Jn[3];
+    double gn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Jn[c] = T(0);
+      gn[c] = gacc[c];
+      e1[c] = e0[c] + ce * curl[c];
+      if (dp && drude) {
+        const T eps2 = p.A0 + rr * p.A1;
+        const T beta = p.B0 + rr * p.B1;
+        const T bs = beta * p.dt_ + p.Sg * rr * (T(1) - rr);
+        const T inv = T(2) / (eps2 + bs);
+        const T dE = inv * (p.dtdx * curl[c] - p.dthJ * Jo[c] - bs * e0[c]);
+        e1[c] = e0[c] + dE;
+        Jn[c] = p.kp * Jo[c] + beta * (e0[c] + e1[c]);
+        if (ADJ) {
+          const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + rr * (T(1) - p.rs)));
+          const T gb = p.gsm * (T(1) - T(2) * rr);
+          gn[c] = gacc[c] + (double)(Em[c] * (p.ga * dE + gb * (e0[c] + e1[c]) + gc * (Jn[c] + Jo[c])));
+        }
+      }
+    }
+
+    // ---- stores
+    if (vx00) st(Wr, HX + q, hx00);
+    if (vy00) st(Wr, HY + q, hy00);
+    if (vz00) st(Wr, HZ + q, hz00);
+    if (vex) st(Wr, EX + q, e1[0]);
+    if (vey) st(Wr, EY + q, e1[1]);
+    if (vez) st(Wr, EZ + q, e1[2]);
+    // memories: the H ones on valid nodes; the forward E ones on valid
+    // nodes, the adjoint E ones on every in-grid node (zero on the walls)
+    const bool wex = ADJ || vex, wey = ADJ || vey, wez = ADJ || vez;
+    if (ty) {
+      if (vx00 && hy_j) st(Wr, yb + oY0, sn[0]);
+      if (vz00 && hy_j) st(Wr, yb + p.YS + oY0, sn[5]);
+      if (wex && ey_j) st(Wr, yb + 2 * p.YS + oY0, sn[6]);
+      if (wez && ey_j) st(Wr, yb + 3 * p.YS + oY0, sn[11]);
+    }
+    if (tx) {
+      if (vy00 && hx_i) st(Wr, xb + oX0, sn[3]);
+      if (vz00 && hx_i) st(Wr, xb + p.XS + oX0, sn[4]);
+      if (wey && ex_i) st(Wr, xb + 2 * p.XS + oX0, sn[9]);
+      if (wez && ex_i) st(Wr, xb + 3 * p.XS + oX0, sn[10]);
+    }
+    if (tz) {
+      if (vx00 && hz_k) st(Wr, zb, sn[1]);
+      if (vy00 && hz_k) st(Wr, zb + p.ZS, sn[2]);
+      if (wex && ez_k) st(Wr, zb + 2 * p.ZS, sn[7]);
+      if (wey && ez_k) st(Wr, zb + 3 * p.ZS, sn[8]);
+    }
+    if (dp) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (!ev[c] || !des) continue;
+        if (drude) {
+          p.J[(size_t)c * nd + d] = Jn[c];
+          if (ADJ) p.grad[(size_t)c * nd + d] = gn[c];
+        }
+        if (!ADJ) p.hist[((size_t)n * 3 + c) * nd + d] = e1[c];
+      }
+    }
+    if (!ADJ && gp && gap) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (ev[c]) p.gapE[((size_t)(n + 1) * p.ng + g) * 3 + c] = (double)e1[c];
+    }
+  };
+
+  bool have = false;  // carried values hold plane k-1
+  for (int k = tl.kb; k < tl.ke; ++k) {
+    if (plane_plain(p, tl, k)) {
+      have = false;
+      continue;
+    }
+    if (!have) plane(std::integral_constant<bool, false>(), k - 1);  // new H of plane k-1, not stored
+    plane(std::integral_constant<bool, true>(), k);
+    have = true;
+  }
+}
+
+// ---------------------------------------------------------------- plain
+// Background dielectric only, identical for the forward and the adjoint.
+// Launched after step3d_general in the same step, so where plane k-1 was
+// general its new H is read back from the write copy.  Its own tiling is
+// wider than the general kernel's (fewer halo lines per owned line); each
+// lane takes the nodes whose general-kernel tile-plane is plain.
+#ifndef FDTD3D_PTX
+#define FDTD3D_PTX 128
+#endif
+#ifndef FDTD3D_PTY
+#define FDTD3D_PTY 4
+#endif
+#ifndef FDTD3D_PKC
+#define FDTD3D_PKC 8
+#endif
+constexpr int PTX = FDTD3D_PTX, PTY = FDTD3D_PTY, PNT = PTX * PTY, PKC = FDTD3D_PKC;
+
+template <typename T>
+__global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+  const int nbx = (nx + PTX - 1) / PTX, nby = (ny + PTY - 1) / PTY, nbz = (nz + PKC - 1) / PKC;
   int bx, by, bz;
   block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
-  const int i0 = bx * TX, j0 = by * TY, k0 = bz * R;
-  if (block_is_bulk(p, i0, j0, k0)) return;
-  const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
-  if (i >= p.n[0] || j >= p.n[1]) return;
-  const G3<T> g(p, par);
-  if (!ADJ) {
-    // new H: (i,j) column at k0-1..k0+R-1 for H_x, H_y; neighbours at j-1 / i-1
-    T hx00[R + 1], hy00[R + 1], hx0m[R], hym0[R], hz00[R], hz0m[R], hzm0[R];
-#pragma unroll
-    for (int r = 0; r <= R; ++r) {
-      const int k = k0 - 1 + r;
-      const bool own = r >= 1 && k < p.n[2];
-      hx00[r] = h_fwd<T, 0>(g, n, i, j, k, own);
-      hy00[r] = h_fwd<T, 1>(g, n, i, j, k, own);
+  const int i = bx * PTX + (threadIdx.x % PTX), j = by * PTY + (threadIdx.x / PTX);
+  if (i >= nx || j >= ny) return;  // no barriers in this kernel
+  const Tile tl = tile_xy(p, i - i % TX, j - j % TY);
+  if (!tl.xy_plain) return;
+  const int kb = bz * PKC, ke = min(kb + PKC, nz);
+  const uint32_t pitch = p.pitch, PL = p.PL, S = p.S;
+  const T *__restrict__ Ex = p.A[0] + p.G0;
+  const T *__restrict__ Ey = Ex + S;
+  const T *__restrict__ Ez = Ex + 2 * (size_t)S;
+  const T *__restrict__ Hx = Ex + 3 * (size_t)S;
+  const T *__restrict__ Hy = Ex + 4 * (size_t)S;
+  const T *__restrict__ Hz = Ex + 5 * (size_t)S;
+  T *__restrict__ Exw = p.A[1] + p.G0;
+  T *__restrict__ Eyw = Exw + S;
+  T *__restrict__ Ezw = Exw + 2 * (size_t)S;
+  T *__restrict__ Hxw = Exw + 3 * (size_t)S;
+  T *__restrict__ Hyw = Exw + 4 * (size_t)S;
+  T *__restrict__ Hzw = Exw + 5 * (size_t)S;
+  const T ch = p.ch, ce = p.ce_s;
+  T hxp = T(0), hyp = T(0), exc = T(0), exl = T(0), eyc = T(0), eys = T(0);
+  bool have = false;
+  for (int k = kb; k < ke; ++k) {
+    if (!plane_plain(p, tl, k)) {
+      have = false;
+      continue;
     }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int k = k0 + s;
-      hx0m[s] = h_fwd<T, 0>(g, n, i, j - 1, k, false);
-      hym0[s] = h_fwd<T, 1>(g, n, i - 1, j, k, false);
-      hz00[s] = h_fwd<T, 2>(g, n, i, j, k, k < p.n[2]);
-      hz0m[s] = h_fwd<T, 2>(g, n, i, j - 1, k, false);
-      hzm0[s] = h_fwd<T, 2>(g, n, i - 1, j, k, false);
+    const uint32_t q = (uint32_t)k * PL + (uint32_t)j * pitch + (uint32_t)i;
+    if (!have) {
+      exc = Ex[q];
+      exl = Ex[q - 1];
+      eyc = Ey[q];
+      eys = Ey[q - pitch];
+      if (plane_plain(p, tl, k - 1)) {
+        const uint32_t r = q - PL;
+        const T ezr = Ez[r];
+        hxp = Hx[r] - ch * ((Ez[r + pitch] - ezr) - (eyc - Ey[r]));
+        hyp = Hy[r] - ch * ((exc - Ex[r]) - (Ez[r + 1] - ezr));
+      } else {
+        hxp = Hxw[q - PL];
+        hyp = Hyw[q - PL];
+      }
+      have = true;
     }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int k = k0 + s;
-      if (g.evalid(0, i, j, k)) e_update<T, false, 0>(g, n, i, j, k, curl_fwd<T, 0>(g, n, i, j, k, hz00[s], hz0m[s], hy00[s + 1], hy00[s]));
-      if (g.evalid(1, i, j, k)) e_update<T, false, 1>(g, n, i, j, k, curl_fwd<T, 1>(g, n, i, j, k, hx00[s + 1], hx00[s], hz00[s], hzm0[s]));
-      if (g.evalid(2, i, j, k)) e_update<T, false, 2>(g, n, i, j, k, curl_fwd<T, 2>(g, n, i, j, k, hy00[s + 1], hym0[s], hx00[s + 1], hx0m[s]));
-    }
-  } else {
-    // graded new H*: gA_B = H*_A graded along axis B
-    T hx_y[R + 1], hx_z[R + 1], hy_z[R + 1], hy_x[R + 1];
-    T hx0m_y[R], hym0_x[R], hz_x[R], hz_y[R], hz0m_y[R], hzm0_x[R], tmp;
-#pragma unroll
-    for (int r = 0; r <= R; ++r) {
-      const int k = k0 - 1 + r;
-      const bool own = r >= 1 && k < p.n[2];
-      h_adj<T, 0>(g, i, j, k, own, hx_y[r], hx_z[r]);   // H_x: u = y, v = z
-      h_adj<T, 1>(g, i, j, k, own, hy_z[r], hy_x[r]);   // H_y: u = z, v = x
-    }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int k = k0 + s;
-      h_adj<T, 0>(g, i, j - 1, k, false, hx0m_y[s], tmp);
-      h_adj<T, 1>(g, i - 1, j, k, false, tmp, hym0_x[s]);
-      h_adj<T, 2>(g, i, j, k, k < p.n[2], hz_x[s], hz_y[s]);  // H_z: u = x, v = y
-      h_adj<T, 2>(g, i, j - 1, k, false, tmp, hz0m_y[s]);
-      h_adj<T, 2>(g, i - 1, j, k, false, hzm0_x[s], tmp);
-    }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int k = k0 + s;
-      if (k >= p.n[2]) continue;
-      store_nu_e<T, 0>(g, i, j, k);
-      store_nu_e<T, 1>(g, i, j, k);
-      store_nu_e<T, 2>(g, i, j, k);
-      // (curl H*)_x = d_y G_y(H*_z) - d_z G_z(H*_y), etc.
-      if (g.evalid(0, i, j, k)) e_update<T, true, 0>(g, n, i, j, k, (hz_y[s] - hz0m_y[s]) - (hy_z[s + 1] - hy_z[s]));
-      if (g.evalid(1, i, j, k)) e_update<T, true, 1>(g, n, i, j, k, (hx_z[s + 1] - hx_z[s]) - (hz_x[s] - hzm0_x[s]));
-      if (g.evalid(2, i, j, k)) e_update<T, true, 2>(g, n, i, j, k, (hy_x[s + 1] - hym0_x[s]) - (hx_y[s + 1] - hx0m_y[s]));
-    }
+    const T exN = Ex[q + pitch], exS = Ex[q - pitch], exLN = Ex[q + pitch - 1];
+    const T eyR = Ey[q + 1], eyRS = Ey[q + 1 - pitch], eyL = Ey[q - 1];
+    const T ezC = Ez[q], ezN = Ez[q + pitch], ezR = Ez[q + 1], ezS = Ez[q - pitch], ezL = Ez[q - 1];
+    const T exc1 = Ex[q + PL], exl1 = Ex[q + PL - 1], eyc1 = Ey[q + PL], eys1 = Ey[q + PL - pitch];
+    const T hxC = Hx[q], hxS = Hx[q - pitch], hyC = Hy[q], hyL = Hy[q - 1];
+    const T hzC = Hz[q], hzS = Hz[q - pitch], hzL = Hz[q - 1];
+    const T hx00 = hxC - ch * ((ezN - ezC) - (eyc1 - eyc));
+    const T hx0m = hxS - ch * ((ezC - ezS) - (eys1 - eys));
+    const T hy00 = hyC - ch * ((exc1 - exc) - (ezR - ezC));
+    const T hym0 = hyL - ch * ((exl1 - exl) - (ezC - ezL));
+    const T hz00 = hzC - ch * ((eyR - eyc) - (exN - exc));
+    const T hz0m = hzS - ch * ((eyRS - eys) - (exc - exS));
+    const T hzm0 = hzL - ch * ((eyc - eyL) - (exLN - exl));
+    Hxw[q] = hx00;
+    Hyw[q] = hy00;
+    Hzw[q] = hz00;
+    Exw[q] = exc + ce * ((hz00 - hz0m) - (hy00 - hyp));
+    Eyw[q] = eyc + ce * ((hx00 - hxp) - (hz00 - hzm0));
+    Ezw[q] = ezC + ce * ((hy00 - hym0) - (hx00 - hx0m));
+    hxp = hx00;
+    hyp = hy00;
+    exc = exc1;
+    exl = exl1;
+    eyc = eyc1;
+    eys = eys1;
   }
 }
 
@@ -431,13 +656,17 @@ __global__ void __launch_bounds__(NT) step3d_general(const Step3D<T> p, const in
 
 template <typename T>
 void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s) {
-  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + R - 1) / R;
+  Step3D<T> q = p;  // copy 0 is read, copy 1 written
+  q.A[0] = p.A[par];
+  q.A[1] = p.A[par ^ 1];
+  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + KC - 1) / KC;
   const dim3 grid(nbx * nby * nbz);
-  hipLaunchKernelGGL(step3d_bulk<T>, grid, dim3(NT), 0, s, p, par);
   if (adjoint)
-    hipLaunchKernelGGL((step3d_general<T, true>), grid, dim3(NT), 0, s, p, n, par);
+    hipLaunchKernelGGL((step3d_general<T, true>), grid, dim3(NT), 0, s, q, n);
   else
-    hipLaunchKernelGGL((step3d_general<T, false>), grid, dim3(NT), 0, s, p, n, par);
+    hipLaunchKernelGGL((step3d_general<T, false>), grid, dim3(NT), 0, s, q, n);
+  const int pbx = (p.n[0] + PTX - 1) / PTX, pby = (p.n[1] + PTY - 1) / PTY, pbz = (p.n[2] + PKC - 1) / PKC;
+  hipLaunchKernelGGL(step3d_plain<T>, dim3(pbx * pby * pbz), dim3(PNT), 0, s, q);
 }
 
 template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t);

@@ -1,30 +1,74 @@
-// fdtd_3d.hpp -- parameters of the 3D step kernels.
+// fdtd_3d.hpp -- state layout and parameters of the 3D step kernels.
 #pragma once
+
+#include <cstdint>
 
 #include "fdtd_internal.hpp"
 
 namespace fdtd {
 
-// Everything one launch of the 3D step reads.  Index (i, j, k) with
-// i fastest; element (i, j, k) of an array is at k*sz + j*pitch + i.
-// Components: E_x (i+1/2, j, k), E_y (i, j+1/2, k), E_z (i, j, k+1/2),
-// H_x (i, j+1/2, k+1/2), H_y (i+1/2, j, k+1/2), H_z (i+1/2, j+1/2, k).
-// Fields and absorber memories come in two copies (read par, write par^1).
+// One copy of the 3D state lives in one device allocation (an "arena"), so a
+// kernel reaches every field and absorber memory through a single base
+// pointer and 32-bit element offsets.  Offsets in elements:
+//   [0, G0)          guard, permanently zero: every neighbour offset of an
+//                    in-grid node stays inside the arena, and predicated-off
+//                    loads read element 0
+//   G0 + c*S         field c = E_x, E_y, E_z, H_x, H_y, H_z; node (i, j, k)
+//                    at k*PL + j*pitch + i.  E_x sits at (i+1/2, j, k),
+//                    H_x at (i, j+1/2, k+1/2), and so on (full Yee cell).
+//   xs + s*XS        x-absorber memories s = H_y, H_z, E_y, E_z along x,
+//                    node at (k*ny + j)*W + sx(i)
+//   ys + s*YS        y-absorber memories s = H_x, H_z, E_x, E_z along y,
+//                    node at (k*W + sy(j))*pitch + i
+//   zs + s*ZS        z-absorber memories s = H_x, H_y, E_x, E_y along z,
+//                    node at (sz(k)*ny + j)*pitch + i
+//   ... tail guard
+// W = 2P + 1 nodes per axis hold every absorber position of E (integer
+// positions i < P or i > n-1-P) and of H (half positions, i < P or
+// i >= n-1-P): s?(i) = i for i < P, i - (n - 1 - 2P) otherwise.
+#ifndef FDTD3D_SKEW
+#define FDTD3D_SKEW 4160
+#endif
+#ifndef FDTD3D_PITCH_PAD
+#define FDTD3D_PITCH_PAD 0
+#endif
+
+struct Arena3 {
+  uint32_t G0, S, PL, xs, ys, zs, XS, YS, ZS, W;
+  uint64_t total;  // elements
+};
+
+inline Arena3 arena3_layout(int nx, int ny, int nz, int pitch, int P) {
+  auto up = [](uint64_t v) { return (v + 63) & ~uint64_t(63); };
+  Arena3 a{};
+  const uint64_t PL = (uint64_t)pitch * ny;
+  const uint64_t G0 = up(PL + pitch + 64);
+  // arrays are skewed off power-of-two strides so that the same node of the
+  // six fields does not land in one L2 set
+  const uint64_t S = up(PL * nz) + FDTD3D_SKEW;
+  const uint64_t W = P > 0 ? 2 * (uint64_t)P + 1 : 0;
+  const uint64_t XS = up((uint64_t)nz * ny * W), YS = up((uint64_t)nz * W * pitch), ZS = up(W * PL);
+  const uint64_t xs = G0 + 6 * S, ys = xs + 4 * XS, zs = ys + 4 * YS, end = zs + 4 * ZS + G0;
+  a.G0 = (uint32_t)G0; a.S = (uint32_t)S; a.PL = (uint32_t)PL;
+  a.xs = (uint32_t)xs; a.ys = (uint32_t)ys; a.zs = (uint32_t)zs;
+  a.XS = (uint32_t)XS; a.YS = (uint32_t)YS; a.ZS = (uint32_t)ZS; a.W = (uint32_t)W;
+  a.total = end;
+  return a;
+}
+
+// Everything one launch of the 3D step reads.
 template <typename T>
 struct Step3D {
   int n[3];            // nodes per axis
   int pitch;           // row pitch (elements)
-  long long sz;        // plane stride (elements)
   int P;               // CPML cells
   int d0[3], dn[3];    // design box
   int g0[3], gn[3];    // gap box
   int lo[3], hi[3];    // total-field box (inclusive nodes)
   int kref, L, tf_on;
   int ng;              // gap cells
-  T *E[2][3], *H[2][3];
-  // absorber memory of component c along axis u (u != c), slot [c][u]; the
-  // forward uses them as psi*dx of the curl terms, the adjoint as nu
-  T *pE[2][3][3], *pH[2][3][3];
+  uint32_t G0, S, PL, xs, ys, zs, XS, YS, ZS, W;  // arena layout
+  T *A[2];             // the two state copies; the launcher passes read in A[0], write in A[1]
   T *J;                // Drude currents [3][nd] over the design box
   const T *rho;        // density [nd]
   T *hist;             // forward E on design edges [N][3][nd]
@@ -32,8 +76,8 @@ struct Step3D {
   double *gapE;        // gap monitor series [N+1][ng][3]
   const T *asrc;       // adjoint source [N+1][ng][3] (scaled by dx and S')
   const T *einc, *hinc;// incident line along z: [N+1][L], [N][L]
-  const T *be[3], *ae[3], *ike[3];  // grading per axis at integer positions
-  const T *bh[3], *ah[3], *ikh[3];  // and at half positions
+  const T *tab;        // CPML tables [axis][b_E, a_E, 1/kappa_E, b_H, a_H, 1/kappa_H][tn]
+  int tn;              // table length (largest axis)
   T ch;                // dt / (mu0 dx)
   T ce_s, ce_g;        // dt / (eps0 eps dx)
   T A0, A1, B0, B1, Sg, dt_, dtdx, dthJ, kp;

@@ -18,13 +18,16 @@ struct fdtd_ctx {
   bool own_stream = false;
   int device = 0;
   int nx = 0, ny = 0, nz = 1, pitch = 0;
+  Arena3 lay3{};
+  int tn3 = 0;
   int N = 0, K = 0, nd = 0, ng = 0, ncomp = 1, nmon = 0;
   double dt = 0;
   int ia = 0, ib = 0, ja = 0, jb = 0, jref = 0, L = 0;
   int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
-  // device memory: fields (2D: Ez, Hx, Hy; 3D: Ex, Ey, Ez, Hx, Hy, Hz) and
-  // absorber memories (2D: 4; 3D: 12), two copies each
-  DevBuf fld[2][6], pml[2][12], J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
+  // device memory: 2D fields (Ez, Hx, Hy) and absorber memories (4), two
+  // copies each; 3D: one arena per copy (fields and absorber slabs) and the
+  // packed CPML tables
+  DevBuf fld[2][6], pml[2][12], arena3[2], tab3, J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
   DevBuf axis[18], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
   Step2D<float> p2f{};
   Step2D<double> p2d{};
@@ -152,13 +155,21 @@ void create_2d(fdtd_ctx *c) {
 
 template <typename T>
 void build_axis_tables3(fdtd_ctx *c) {
+  // packed [axis][b_E, a_E, 1/kappa_E, b_H, a_H, 1/kappa_H][tn]; entries past an
+  // axis' end repeat the identity grading
   const int n3[3] = {c->nx, c->ny, c->nz};
+  const int tn = std::max(c->nx, std::max(c->ny, c->nz));
+  std::vector<T> all((size_t)18 * tn);
   for (int a = 0; a < 3; ++a) {
     AxisTables<T> t;
     t.build(c->cfg, c->dt, n3[a], c->cfg.pml_cells);
     const std::vector<T> *v[6] = {&t.be, &t.ae, &t.ike, &t.bh, &t.ah, &t.ikh};
-    for (int k = 0; k < 6; ++k) upload(c->stream, c->axis[6 * a + k], *v[k]);
+    const T idv[6] = {T(1), T(0), T(1), T(1), T(0), T(1)};
+    for (int k = 0; k < 6; ++k)
+      for (int i = 0; i < tn; ++i) all[((size_t)a * 6 + k) * tn + i] = i < n3[a] ? (*v[k])[i] : idv[k];
   }
+  c->tn3 = tn;
+  upload(c->stream, c->tab3, all);
 }
 
 void create_3d(fdtd_ctx *c) {
@@ -173,18 +184,18 @@ void create_3d(fdtd_ctx *c) {
         !box_inside(g.gap_lo[d], g.gap_n[d], c->lo3[d] + 1, c->hi3[d] - 1))
       throw einval("design/gap boxes must lie strictly inside the total-field box");
   }
-  c->pitch = (c->nx + 31) & ~31;
+  c->pitch = ((c->nx + 31) & ~31) + FDTD3D_PITCH_PAD;
   c->nd = g.design_n[0] * g.design_n[1] * g.design_n[2];
   c->ng = g.gap_n[0] * g.gap_n[1] * g.gap_n[2];
   c->ncomp = 3;
   c->nmon = 3 * c->ng;
   c->jref = c->lo3[2] - 2;
   c->L = c->hi3[2] + 2 - c->jref + 1;
-  const size_t n = (size_t)c->pitch * c->ny * c->nz * c->esz;
-  for (int b = 0; b < 2; ++b) {
-    for (int k = 0; k < 6; ++k) c->fld[b][k].alloc(n);
-    for (int k = 0; k < 12; ++k) c->pml[b][k].alloc(n);
-  }
+  c->lay3 = arena3_layout(c->nx, c->ny, c->nz, c->pitch, P);
+  // kernels address a copy with 32-bit byte offsets
+  if (c->lay3.total * (uint64_t)c->esz >= (uint64_t(1) << 32))
+    throw einval("3D state too large for one 4 GiB arena per copy (fields + absorber memories)");
+  for (int b = 0; b < 2; ++b) c->arena3[b].alloc((size_t)c->lay3.total * c->esz);
   if (c->prec == 32) build_axis_tables3<float>(c); else build_axis_tables3<double>(c);
 }
 
@@ -193,7 +204,6 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p) {
   const fdtd_config &g = c->cfg;
   p.n[0] = c->nx; p.n[1] = c->ny; p.n[2] = c->nz;
   p.pitch = c->pitch;
-  p.sz = (long long)c->pitch * c->ny;
   p.P = g.pml_cells;
   for (int d = 0; d < 3; ++d) {
     p.d0[d] = g.design_lo[d]; p.dn[d] = g.design_n[d];
@@ -201,24 +211,15 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p) {
     p.lo[d] = c->lo3[d]; p.hi[d] = c->hi3[d];
   }
   p.kref = c->jref; p.L = c->L; p.tf_on = 1; p.ng = c->ng;
-  for (int b = 0; b < 2; ++b) {
-    for (int k = 0; k < 3; ++k) { p.E[b][k] = c->fld[b][k].as<T>(); p.H[b][k] = c->fld[b][3 + k].as<T>(); }
-    int slot = 0;
-    for (int cc = 0; cc < 3; ++cc)
-      for (int u = 0; u < 3; ++u) {
-        p.pE[b][cc][u] = nullptr; p.pH[b][cc][u] = nullptr;
-        if (u == cc) continue;
-        p.pE[b][cc][u] = c->pml[b][slot].as<T>();
-        p.pH[b][cc][u] = c->pml[b][6 + slot].as<T>();
-        ++slot;
-      }
-  }
+  const Arena3 &a = c->lay3;
+  p.G0 = a.G0; p.S = a.S; p.PL = a.PL; p.xs = a.xs; p.ys = a.ys; p.zs = a.zs;
+  p.XS = a.XS; p.YS = a.YS; p.ZS = a.ZS; p.W = a.W;
+  p.A[0] = c->arena3[0].as<T>();
+  p.A[1] = c->arena3[1].as<T>();
   p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
   p.gapE = c->gapE.as<double>(); p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
-  for (int a = 0; a < 3; ++a) {
-    p.be[a] = c->axis[6 * a + 0].as<T>(); p.ae[a] = c->axis[6 * a + 1].as<T>(); p.ike[a] = c->axis[6 * a + 2].as<T>();
-    p.bh[a] = c->axis[6 * a + 3].as<T>(); p.ah[a] = c->axis[6 * a + 4].as<T>(); p.ikh[a] = c->axis[6 * a + 5].as<T>();
-  }
+  p.tab = c->tab3.as<T>();
+  p.tn = c->tn3;
   const double dt = c->dt, dx = g.dx;
   const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
   const double gam = g.gamma_mult * g.gamma_p;
@@ -297,6 +298,7 @@ void zero_state(fdtd_ctx *c) {
   for (int b = 0; b < 2; ++b) {
     for (int k = 0; k < 6; ++k) if (c->fld[b][k].p) zero(c, c->fld[b][k]);
     for (int k = 0; k < 12; ++k) if (c->pml[b][k].p) zero(c, c->pml[b][k]);
+    if (c->arena3[b].p) zero(c, c->arena3[b]);
   }
   zero(c, c->J);
 }
