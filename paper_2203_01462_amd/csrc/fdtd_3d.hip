@@ -164,8 +164,11 @@ __device__ __forceinline__ T gr(T v, T m, const Ax<T> &x, T &mn) {
 }
 
 // ---------------------------------------------------------------- general
+// The FP32 forward variant fits 4 waves per SIMD without spills; the others
+// need more registers and run at the compiler's choice.
 template <typename T, bool ADJ>
-__global__ void __launch_bounds__(NT) step3d_general(const Step3D<T> p, const int n) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(!ADJ && sizeof(T) == 4 ? 4 : 1)))
+step3d_general(const Step3D<T> p, const int n) {
   const int nx = p.n[0], ny = p.n[1], nz = p.n[2], P = p.P;
   const Tile tl = tile_of(p);
   const int i = tl.i0 + (threadIdx.x % TX), j = tl.j0 + (threadIdx.x / TX);
@@ -571,7 +574,7 @@ __global__ void __launch_bounds__(NT) step3d_general(const Step3D<T> p, const in
 #define FDTD3D_PTY 4
 #endif
 #ifndef FDTD3D_PKC
-#define FDTD3D_PKC 8
+#define FDTD3D_PKC 4
 #endif
 constexpr int PTX = FDTD3D_PTX, PTY = FDTD3D_PTY, PNT = PTX * PTY, PKC = FDTD3D_PKC;
 
@@ -637,12 +640,13 @@ __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
     const T hz00 = hzC - ch * ((eyR - eyc) - (exN - exc));
     const T hz0m = hzS - ch * ((eyRS - eys) - (exc - exS));
     const T hzm0 = hzL - ch * ((eyc - eyL) - (exLN - exl));
-    Hxw[q] = hx00;
-    Hyw[q] = hy00;
-    Hzw[q] = hz00;
-    Exw[q] = exc + ce * ((hz00 - hz0m) - (hy00 - hyp));
-    Eyw[q] = eyc + ce * ((hx00 - hxp) - (hz00 - hzm0));
-    Ezw[q] = ezC + ce * ((hy00 - hym0) - (hx00 - hx0m));
+    // streaming stores: the new copy is not read again in this step
+    __builtin_nontemporal_store(hx00, &Hxw[q]);
+    __builtin_nontemporal_store(hy00, &Hyw[q]);
+    __builtin_nontemporal_store(hz00, &Hzw[q]);
+    __builtin_nontemporal_store(exc + ce * ((hz00 - hz0m) - (hy00 - hyp)), &Exw[q]);
+    __builtin_nontemporal_store(eyc + ce * ((hx00 - hxp) - (hz00 - hzm0)), &Eyw[q]);
+    __builtin_nontemporal_store(ezC + ce * ((hy00 - hym0) - (hx00 - hx0m)), &Ezw[q]);
     hxp = hx00;
     hyp = hy00;
     exc = exc1;
