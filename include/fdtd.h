@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 1
+#define FDTD_ABI_VERSION 2
 
 typedef enum {
   FDTD_OK = 0,
@@ -100,7 +100,14 @@ typedef struct {
   double t0_over_tau;    /* Gaussian delay in units of its width */
   double amplitude;      /* incident amplitude (V/m) */
   const double *freqs_hz;/* K frequencies, or NULL for K uniform over [f_lo, f_hi]; copied */
-  int64_t history_budget_bytes; /* cap on the stored forward history; 0 = device limit */
+  int64_t history_budget_bytes; /* cap on the forward history plus checkpoints; 0 = device limit */
+  int32_t ckpt_every;    /* 0: store E on every design edge for all n_steps (the
+                            sums of eq. (25) read it back in reverse).  K > 0:
+                            store only K steps of it plus a full-state snapshot
+                            every K steps; the adjoint re-runs each K-step
+                            segment of the forward from its snapshot, newest
+                            first, before the adjoint steps that need it.  Both
+                            give bit-identical gradients. */
   void *stream;          /* hipStream_t or NULL */
 } fdtd_config;
 
@@ -121,8 +128,9 @@ int32_t fdtd_abi_version(void);
  * ρ-independent tables (absorber grading, incident-field line, phasors,
  * weights).  Fails with EINVAL on: precision not 32/64, dims not 2/3,
  * Courant outside (0, 1/sqrt(dims)), n_steps < 1, n_freq < 1, non-positive
- * permittivities or negative material parameters, boxes outside the
- * total-field region; ENOMEM if the forward history does not fit the budget;
+ * permittivities or negative material parameters, ckpt_every < 0, boxes
+ * outside the total-field region; ENOMEM if the forward history (and, with
+ * ckpt_every > 0, the snapshots) does not fit the budget or the device;
  * EDEVICE without a usable HIP device.  *out is NULL on failure. */
 fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out);
 

@@ -218,7 +218,7 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
     const size_t d = (size_t)(des ? dj * p.dnx + di : 0);
     rr[r] = ldp(rho, d, des);
     Jo[r] = ldp((const T *)Jc, d, des && !gap);
-    Em[r] = ldp((const T *)hist, (size_t)(n - 1) * nd + d, ADJ && des && !gap);
+    Em[r] = ldp((const T *)hist, (size_t)(n - 1 - p.hist_base) * nd + d, ADJ && des && !gap);
     gacc[r] = ldp((const double *)grad, d, ADJ && des && !gap);
     src[r] = ldp(p.asrc, (size_t)n * p.ng + (gap ? gj * p.gnx + gi : 0), ADJ && gap);
     const bool tfr = !ADJ && tfy && j >= p.ja && j <= p.jb;
@@ -452,7 +452,7 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       Jc[d] = Jn[r];
       if (ADJ) grad[d] = gnew[r];
     }
-    if (!ADJ && des) hist[(size_t)n * nd + d] = en[r];
+    if (!ADJ && des && p.hist_on) hist[(size_t)(n - p.hist_base) * nd + d] = en[r];
     if (!ADJ && gap) p.gapE[(size_t)(n + 1) * p.ng + gj * p.gnx + gi] = (double)en[r];
   }
 }

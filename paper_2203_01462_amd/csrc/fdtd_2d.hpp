@@ -22,6 +22,7 @@ struct Step2D {
   const T *rho;                          // density over the design box
   T *hist;                               // forward E over the design box, [N][dny][dnx]
   double *grad;                          // sensitivity sums over the design box (adjoint)
+  int hist_base, hist_on;  // history slot of step n is n - hist_base; the forward writes it when hist_on
   double *gapE;                          // gap time series [N+1][ng] (the DFT is taken after the solve)
   const T *asrc;                         // adjoint source table [N+1][ng] (scaled by dx and S')
   const T *einc, *hinc;                  // incident line [N+1][L], [N][L]

@@ -284,7 +284,7 @@ step3d_general(const Step3D<T> p, const int n) {
       for (int c = 0; c < 3; ++c) {
         Jo[c] = ld(p.J, drude ? (uint32_t)c * nd + d : 0u);
         if (ADJ) {
-          Em[c] = p.hist[drude ? ((size_t)(n - 1) * 3 + c) * nd + d : 0];
+          Em[c] = p.hist[drude ? ((size_t)(n - 1 - p.hist_base) * 3 + c) * nd + d : 0];
           gacc[c] = p.grad[drude ? (size_t)c * nd + d : 0];
         }
       }
@@ -539,7 +539,7 @@ step3d_general(const Step3D<T> p, const int n) {
           p.J[(size_t)c * nd + d] = Jn[c];
           if (ADJ) p.grad[(size_t)c * nd + d] = gn[c];
         }
-        if (!ADJ) p.hist[((size_t)n * 3 + c) * nd + d] = e1[c];
+        if (!ADJ && p.hist_on) p.hist[((size_t)(n - p.hist_base) * 3 + c) * nd + d] = e1[c];
       }
     }
     if (!ADJ && gp && gap) {

@@ -73,6 +73,7 @@ struct Step3D {
   const T *rho;        // density [nd]
   T *hist;             // forward E on design edges [N][3][nd]
   double *grad;        // sensitivity sums [3][nd]
+  int hist_base, hist_on;  // history slot of step n is n - hist_base; the forward writes it when hist_on
   double *gapE;        // gap monitor series [N+1][ng][3]
   const T *asrc;       // adjoint source [N+1][ng][3] (scaled by dx and S')
   const T *einc, *hinc;// incident line along z: [N+1][L], [N][L]

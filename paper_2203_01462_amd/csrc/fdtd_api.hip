@@ -29,10 +29,15 @@ struct fdtd_ctx {
   // packed CPML tables
   DevBuf fld[2][6], pml[2][12], arena3[2], tab3, J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
   DevBuf axis[18], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
-  Step2D<float> p2f{};
-  Step2D<double> p2d{};
-  Step3D<float> p3f{};
-  Step3D<double> p3d{};
+  // checkpointed adjoint: a second state (both copies and J) for re-running
+  // forward segments, and the snapshots [nseg-1][state copy + J]
+  DevBuf fldR[2][6], pmlR[2][12], arenaR[2], JR, snap;
+  int ck = 0, nseg = 1;  // segment length (steps) and count; nseg = 1: full history
+  size_t snap_bytes = 0;
+  Step2D<float> p2f{}, p2fR{};
+  Step2D<double> p2d{}, p2dR{};
+  Step3D<float> p3f{}, p3fR{};
+  Step3D<double> p3d{}, p3dR{};
   int state = 0;  // 0 created, 1 density, 2 forward, 3 adjoint
   double F = 0;
   std::string err;
@@ -62,6 +67,7 @@ void validate(const fdtd_config &c) {
       !(c.psi_s_ratio > 0 || c.omega_p == 0))
     throw einval("invalid Drude parameters (psi_s_ratio must be > 0)");
   if (c.pml_cells < 0 || c.tfsf_margin < 0) throw einval("negative pml_cells / tfsf_margin");
+  if (c.ckpt_every < 0) throw einval("ckpt_every < 0");
   if (c.source_kind != FDTD_SRC_GAUSS && c.source_kind != FDTD_SRC_SINC_HANN) throw einval("unknown source_kind");
   if (c.objective_kind != FDTD_OBJ_DFT && c.objective_kind != FDTD_OBJ_TIME_ENERGY) throw einval("unknown objective_kind");
   if (c.weight_kind != FDTD_W_ENHANCEMENT && c.weight_kind != FDTD_W_UNIT) throw einval("unknown weight_kind");
@@ -87,7 +93,7 @@ void build_axis_tables(fdtd_ctx *c) {
 }
 
 template <typename T>
-void fill_params2d(fdtd_ctx *c, Step2D<T> &p) {
+void fill_params2d(fdtd_ctx *c, Step2D<T> &p, bool rerun) {
   const fdtd_config &g = c->cfg;
   p.nx = c->nx; p.ny = c->ny; p.pitch = c->pitch; p.P = g.pml_cells;
   p.dx0 = g.design_lo[0]; p.dy0 = g.design_lo[1]; p.dnx = g.design_n[0]; p.dny = g.design_n[1];
@@ -95,11 +101,14 @@ void fill_params2d(fdtd_ctx *c, Step2D<T> &p) {
   p.ia = c->ia; p.ib = c->ib; p.ja = c->ja; p.jb = c->jb; p.jref = c->jref; p.L = c->L; p.tf_on = 1;
   p.K = c->K; p.ng = c->ng;
   for (int b = 0; b < 2; ++b) {
-    p.ez[b] = c->fld[b][0].as<T>(); p.hx[b] = c->fld[b][1].as<T>(); p.hy[b] = c->fld[b][2].as<T>();
-    p.pex[b] = c->pml[b][0].as<T>(); p.pey[b] = c->pml[b][1].as<T>();
-    p.phx[b] = c->pml[b][2].as<T>(); p.phy[b] = c->pml[b][3].as<T>();
+    DevBuf *f = rerun ? c->fldR[b] : c->fld[b], *m = rerun ? c->pmlR[b] : c->pml[b];
+    p.ez[b] = f[0].as<T>(); p.hx[b] = f[1].as<T>(); p.hy[b] = f[2].as<T>();
+    p.pex[b] = m[0].as<T>(); p.pey[b] = m[1].as<T>();
+    p.phx[b] = m[2].as<T>(); p.phy[b] = m[3].as<T>();
   }
-  p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
+  p.hist_base = 0;
+  p.hist_on = 1;
+  p.J = (rerun ? c->JR : c->J).as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
   p.gapE = c->gapE.as<double>();
   p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
   const T **ax[12] = {&p.bxe, &p.axe, &p.ikxe, &p.bxh, &p.axh, &p.ikxh, &p.bye, &p.aye, &p.ikye, &p.byh, &p.ayh, &p.ikyh};
@@ -149,6 +158,10 @@ void create_2d(fdtd_ctx *c) {
   for (int b = 0; b < 2; ++b) {
     for (int k = 0; k < 3; ++k) c->fld[b][k].alloc(n2);
     for (int k = 0; k < 4; ++k) c->pml[b][k].alloc(n2);
+    if (c->nseg > 1) {
+      for (int k = 0; k < 3; ++k) c->fldR[b][k].alloc(n2);
+      for (int k = 0; k < 4; ++k) c->pmlR[b][k].alloc(n2);
+    }
   }
   if (c->prec == 32) build_axis_tables<float>(c); else build_axis_tables<double>(c);
 }
@@ -195,12 +208,15 @@ void create_3d(fdtd_ctx *c) {
   // kernels address a copy with 32-bit byte offsets
   if (c->lay3.total * (uint64_t)c->esz >= (uint64_t(1) << 32))
     throw einval("3D state too large for one 4 GiB arena per copy (fields + absorber memories)");
-  for (int b = 0; b < 2; ++b) c->arena3[b].alloc((size_t)c->lay3.total * c->esz);
+  for (int b = 0; b < 2; ++b) {
+    c->arena3[b].alloc((size_t)c->lay3.total * c->esz);
+    if (c->nseg > 1) c->arenaR[b].alloc((size_t)c->lay3.total * c->esz);
+  }
   if (c->prec == 32) build_axis_tables3<float>(c); else build_axis_tables3<double>(c);
 }
 
 template <typename T>
-void fill_params3d(fdtd_ctx *c, Step3D<T> &p) {
+void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
   const fdtd_config &g = c->cfg;
   p.n[0] = c->nx; p.n[1] = c->ny; p.n[2] = c->nz;
   p.pitch = c->pitch;
@@ -214,9 +230,11 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p) {
   const Arena3 &a = c->lay3;
   p.G0 = a.G0; p.S = a.S; p.PL = a.PL; p.xs = a.xs; p.ys = a.ys; p.zs = a.zs;
   p.XS = a.XS; p.YS = a.YS; p.ZS = a.ZS; p.W = a.W;
-  p.A[0] = c->arena3[0].as<T>();
-  p.A[1] = c->arena3[1].as<T>();
-  p.J = c->J.as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
+  p.A[0] = (rerun ? c->arenaR[0] : c->arena3[0]).as<T>();
+  p.A[1] = (rerun ? c->arenaR[1] : c->arena3[1]).as<T>();
+  p.hist_base = 0;
+  p.hist_on = 1;
+  p.J = (rerun ? c->JR : c->J).as<T>(); p.rho = c->rho.as<T>(); p.hist = c->hist.as<T>(); p.grad = c->grad.as<double>();
   p.gapE = c->gapE.as<double>(); p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
   p.tab = c->tab3.as<T>();
   p.tn = c->tn3;
@@ -247,13 +265,31 @@ void create_common(fdtd_ctx *c) {
   c->J.alloc((size_t)c->nd * c->ncomp * c->esz);
   c->rho.alloc((size_t)c->nd * c->esz);
   c->grad.alloc((size_t)c->nd * c->ncomp * sizeof(double));
-  const double hist_bytes = (double)c->N * c->nd * c->ncomp * c->esz;
-  if (g.history_budget_bytes > 0 && hist_bytes > (double)g.history_budget_bytes)
-    throw Error{FDTD_ENOMEM, "forward history (" + std::to_string(hist_bytes) + " bytes) exceeds history_budget_bytes"};
+  // history of ck steps (all N without checkpoints) plus nseg-1 snapshots
+  const int hist_steps = c->nseg > 1 ? c->ck : c->N;
+  const double hist_bytes = (double)hist_steps * c->nd * c->ncomp * c->esz;
+  if (c->nseg > 1) {
+    c->JR.alloc(c->J.bytes);
+    c->snap_bytes = c->J.bytes;
+    for (int b = 0; b < 1; ++b) {
+      if (c->dims == 2) {
+        for (int k = 0; k < 3; ++k) c->snap_bytes += c->fld[b][k].bytes;
+        for (int k = 0; k < 4; ++k) c->snap_bytes += c->pml[b][k].bytes;
+      } else {
+        c->snap_bytes += c->arena3[b].bytes;
+      }
+    }
+  }
+  const double snap_total = (double)(c->nseg - 1) * c->snap_bytes;
+  if (g.history_budget_bytes > 0 && hist_bytes + snap_total > (double)g.history_budget_bytes)
+    throw Error{FDTD_ENOMEM, "forward history and snapshots (" + std::to_string(hist_bytes + snap_total) +
+                                 " bytes) exceed history_budget_bytes"};
   size_t fr = 0, tot = 0;
   FDTD_HIP(hipMemGetInfo(&fr, &tot));
-  if (hist_bytes > 0.92 * (double)fr) throw Error{FDTD_ENOMEM, "forward history does not fit in device memory"};
+  if (hist_bytes + snap_total > 0.92 * (double)fr)
+    throw Error{FDTD_ENOMEM, "forward history and snapshots do not fit in device memory"};
   c->hist.alloc((size_t)hist_bytes);
+  if (c->nseg > 1) c->snap.alloc((size_t)snap_total);
   c->dft.alloc((size_t)c->K * c->nmon * 2 * sizeof(double));
   c->gapE.alloc((size_t)(c->N + 1) * c->nmon * sizeof(double));
   c->asrc.alloc((size_t)(c->N + 1) * c->nmon * c->esz);
@@ -304,38 +340,101 @@ void zero_state(fdtd_ctx *c) {
 }
 
 template <typename T>
-Step2D<T> &params2d(fdtd_ctx *c);
+Step2D<T> &params2d(fdtd_ctx *c, bool rerun);
 template <>
-Step2D<float> &params2d<float>(fdtd_ctx *c) { return c->p2f; }
+Step2D<float> &params2d<float>(fdtd_ctx *c, bool rerun) { return rerun ? c->p2fR : c->p2f; }
 template <>
-Step2D<double> &params2d<double>(fdtd_ctx *c) { return c->p2d; }
+Step2D<double> &params2d<double>(fdtd_ctx *c, bool rerun) { return rerun ? c->p2dR : c->p2d; }
 template <typename T>
-Step3D<T> &params3d(fdtd_ctx *c);
+Step3D<T> &params3d(fdtd_ctx *c, bool rerun);
 template <>
-Step3D<float> &params3d<float>(fdtd_ctx *c) { return c->p3f; }
+Step3D<float> &params3d<float>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3fR : c->p3f; }
 template <>
-Step3D<double> &params3d<double>(fdtd_ctx *c) { return c->p3d; }
+Step3D<double> &params3d<double>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3dR : c->p3d; }
 
+// One time step on the main state (rerun = false) or the re-run state.
 template <typename T>
-void run_steps(fdtd_ctx *c, bool adjoint) {
-  FDTD_HIP(hipEventRecord(c->ev[adjoint ? 2 : 0], c->stream));
+void launch_step(fdtd_ctx *c, bool rerun, int n, int par, bool adjoint, int hist_base, bool hist_on) {
   if (c->dims == 2) {
-    Step2D<T> &p = params2d<T>(c);
-    if (!adjoint) {
-      for (int n = 0; n < c->N; ++n) launch_step2d<T>(p, n, n & 1, false, c->stream);
-    } else {
-      for (int m = c->N; m >= 1; --m) launch_step2d<T>(p, m, (c->N - m) & 1, true, c->stream);
-    }
+    Step2D<T> p = params2d<T>(c, rerun);
+    p.hist_base = hist_base;
+    p.hist_on = hist_on;
+    launch_step2d<T>(p, n, par, adjoint, c->stream);
   } else {
-    Step3D<T> &p = params3d<T>(c);
-    if (!adjoint) {
-      for (int n = 0; n < c->N; ++n) launch_step3d<T>(p, n, n & 1, false, c->stream);
-    } else {
-      for (int m = c->N; m >= 1; --m) launch_step3d<T>(p, m, (c->N - m) & 1, true, c->stream);
-    }
+    Step3D<T> p = params3d<T>(c, rerun);
+    p.hist_base = hist_base;
+    p.hist_on = hist_on;
+    launch_step3d<T>(p, n, par, adjoint, c->stream);
+  }
+}
+
+// The buffers of state copy b (fields and absorber memories) followed by J.
+std::vector<DevBuf *> state_bufs(fdtd_ctx *c, int b, bool rerun) {
+  std::vector<DevBuf *> v;
+  if (c->dims == 2) {
+    for (int k = 0; k < 3; ++k) v.push_back(rerun ? &c->fldR[b][k] : &c->fld[b][k]);
+    for (int k = 0; k < 4; ++k) v.push_back(rerun ? &c->pmlR[b][k] : &c->pml[b][k]);
+  } else {
+    v.push_back(rerun ? &c->arenaR[b] : &c->arena3[b]);
+  }
+  v.push_back(rerun ? &c->JR : &c->J);
+  return v;
+}
+
+// Snapshot s <- main copy b (the state at the start of segment s).
+void snap_save(fdtd_ctx *c, int b, int s) {
+  char *dst = (char *)c->snap.p + (size_t)s * c->snap_bytes;
+  for (DevBuf *d : state_bufs(c, b, false)) {
+    FDTD_HIP(hipMemcpyAsync(dst, d->p, d->bytes, hipMemcpyDeviceToDevice, c->stream));
+    dst += d->bytes;
+  }
+}
+
+// Re-run copy b <- snapshot s.
+void snap_load(fdtd_ctx *c, int b, int s) {
+  const char *src = (const char *)c->snap.p + (size_t)s * c->snap_bytes;
+  for (DevBuf *d : state_bufs(c, b, true)) {
+    FDTD_HIP(hipMemcpyAsync(d->p, src, d->bytes, hipMemcpyDeviceToDevice, c->stream));
+    src += d->bytes;
+  }
+}
+
+// Forward solve: step n reads copy n&1 and writes copy n&1^1.  With
+// checkpoints the state entering each segment but the last is saved, and only
+// the last segment's history is kept.
+template <typename T>
+void run_forward(fdtd_ctx *c) {
+  FDTD_HIP(hipEventRecord(c->ev[0], c->stream));
+  const int K = c->ck, S = c->nseg, last = (S - 1) * K;
+  for (int n = 0; n < c->N; ++n) {
+    if (S > 1 && n % K == 0 && n < last) snap_save(c, n & 1, n / K);
+    launch_step<T>(c, false, n, n & 1, false, last, n >= last);
   }
   FDTD_HIP(hipGetLastError());
-  FDTD_HIP(hipEventRecord(c->ev[adjoint ? 3 : 1], c->stream));
+  FDTD_HIP(hipEventRecord(c->ev[1], c->stream));
+}
+
+// Adjoint solve, m = N..1 (eq. (20)); step m reads the forward E^m from the
+// history.  With checkpoints, when m enters a segment whose history is not
+// held, that segment of the forward is re-run from its snapshot on the re-run
+// state, refilling the history buffer.
+template <typename T>
+void run_adjoint(fdtd_ctx *c) {
+  FDTD_HIP(hipEventRecord(c->ev[2], c->stream));
+  const int K = c->ck, S = c->nseg, N = c->N;
+  int held = S - 1;
+  for (int m = N; m >= 1; --m) {
+    const int s = S > 1 ? (m - 1) / K : 0;
+    if (s != held) {
+      const int a = s * K, b = std::min(a + K, N);
+      snap_load(c, a & 1, s);
+      for (int n = a; n < b; ++n) launch_step<T>(c, true, n, n & 1, false, a, true);
+      held = s;
+    }
+    launch_step<T>(c, false, m, (N - m) & 1, true, s * K, false);
+  }
+  FDTD_HIP(hipGetLastError());
+  FDTD_HIP(hipEventRecord(c->ev[3], c->stream));
 }
 
 template <typename F>
@@ -379,6 +478,8 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
     c->esz = c->prec == 32 ? 4 : 8;
     c->nx = cfg->n[0]; c->ny = cfg->n[1]; c->nz = cfg->dims == 3 ? cfg->n[2] : 1;
     c->N = cfg->n_steps; c->K = cfg->n_freq;
+    c->ck = cfg->ckpt_every > 0 && cfg->ckpt_every < c->N ? cfg->ckpt_every : c->N;
+    c->nseg = (c->N + c->ck - 1) / c->ck;
     c->dt = cfg->courant * cfg->dx / kC0;
     c->freqs.resize(c->K);
     for (int k = 0; k < c->K; ++k)
@@ -396,9 +497,18 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
     if (c->dims == 2) create_2d(c.get()); else create_3d(c.get());
     create_common(c.get());
     if (c->dims == 2) {
-      if (c->prec == 32) fill_params2d(c.get(), c->p2f); else fill_params2d(c.get(), c->p2d);
+      if (c->prec == 32) fill_params2d(c.get(), c->p2f, false); else fill_params2d(c.get(), c->p2d, false);
+      if (c->prec == 32) fill_params2d(c.get(), c->p2fR, true); else fill_params2d(c.get(), c->p2dR, true);
     } else {
-      if (c->prec == 32) fill_params3d(c.get(), c->p3f); else fill_params3d(c.get(), c->p3d);
+      if (c->prec == 32) fill_params3d(c.get(), c->p3f, false); else fill_params3d(c.get(), c->p3d, false);
+      if (c->prec == 32) fill_params3d(c.get(), c->p3fR, true); else fill_params3d(c.get(), c->p3dR, true);
+    }
+    if (c->nseg > 1) {  // the re-run state's never-written nodes stay zero
+      for (int b = 0; b < 2; ++b) {
+        for (int k = 0; k < 6; ++k) if (c->fldR[b][k].p) zero(c.get(), c->fldR[b][k]);
+        for (int k = 0; k < 12; ++k) if (c->pmlR[b][k].p) zero(c.get(), c->pmlR[b][k]);
+        if (c->arenaR[b].p) zero(c.get(), c->arenaR[b]);
+      }
     }
     FDTD_HIP(hipStreamSynchronize(c->stream));
     FDTD_HIP(hipGetLastError());
@@ -455,7 +565,7 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
     ctx->state = 1;
     zero_state(ctx);
     zero(ctx, ctx->gapE);
-    if (ctx->prec == 32) run_steps<float>(ctx, false); else run_steps<double>(ctx, false);
+    if (ctx->prec == 32) run_forward<float>(ctx); else run_forward<double>(ctx);
     const fdtd_config &g = ctx->cfg;
     launch_dft(ctx->stream, ctx->gapE.as<double>(), ctx->phasor.as<double>(), ctx->K, ctx->nmon, ctx->N, ctx->dt,
                ctx->dft.as<double>());
@@ -488,7 +598,7 @@ fdtd_status fdtd_adjoint(fdtd_ctx *ctx) {
                           ctx->asrc.p);
     zero_state(ctx);
     zero(ctx, ctx->grad);
-    if (ctx->prec == 32) run_steps<float>(ctx, true); else run_steps<double>(ctx, true);
+    if (ctx->prec == 32) run_adjoint<float>(ctx); else run_adjoint<double>(ctx);
     ctx->timing.adjoint_launches = ctx->N;
     ctx->state = 3;
   });

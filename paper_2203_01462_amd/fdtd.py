@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 C0 = 299792458.0
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSTABLE"}
@@ -49,6 +49,7 @@ class Config(C.Structure):
         ("amplitude", C.c_double),
         ("freqs_hz", C.POINTER(C.c_double)),
         ("history_budget_bytes", C.c_int64),
+        ("ckpt_every", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -99,8 +100,10 @@ def load_library(path=LIB_PATH):
     return L
 
 
-def make_config(w, stream=None, history_budget_bytes=0):
-    """Translate a workload dict into fdtd_config (pure marshalling)."""
+def make_config(w, stream=None, history_budget_bytes=0, ckpt_every=None):
+    """Translate a workload dict into fdtd_config (pure marshalling).
+    ``ckpt_every`` (or the workload's "ckpt_every"): 0 stores the whole forward
+    history, K > 0 checkpoints every K steps."""
     c = Config()
     c.abi_version = ABI_VERSION
     c.dims = w["dims"]
@@ -134,6 +137,7 @@ def make_config(w, stream=None, history_budget_bytes=0):
         c.n_freq = w["n_freq"]
         c.freqs_hz = C.POINTER(C.c_double)()
     c.history_budget_bytes = int(history_budget_bytes)
+    c.ckpt_every = int(w.get("ckpt_every", 0) if ckpt_every is None else ckpt_every)
     c.stream = stream
     return c, keep
 
@@ -145,12 +149,13 @@ def _is_torch(x):
 class FDTD:
     """One problem instance on the GPU (a context of the HIP library)."""
 
-    def __init__(self, w, stream=None, history_budget_bytes=0):
+    def __init__(self, w, stream=None, history_budget_bytes=0, ckpt_every=None):
         L = load_library()
         self.w = dict(w)
         self.dims = w["dims"]
         self.dtype = np.float32 if w["precision"] == 32 else np.float64
-        cfg, keep = make_config(w, stream, history_budget_bytes)
+        cfg, keep = make_config(w, stream, history_budget_bytes, ckpt_every)
+        self.ckpt_every = cfg.ckpt_every
         h = C.c_void_p()
         rc = L.fdtd_create(C.byref(cfg), C.byref(h))
         if rc:

@@ -37,7 +37,32 @@ def test_library_exports_every_declared_symbol(lib):
     for s in header_symbols():
         assert hasattr(L, s), s
     assert sorted(lib.fdtd.EXPORTS) == header_symbols()
-    assert L.fdtd_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    ver = int(re.search(r"#define FDTD_ABI_VERSION (\d+)", hdr).group(1))
+    assert L.fdtd_abi_version() == ver == lib.fdtd.ABI_VERSION
+
+
+def test_binding_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of fdtd_config / fdtd_timing has the C layout
+    (sizes and every field offset, from a C program compiled against the header)."""
+    import ctypes
+    import subprocess
+    from paper_2203_01462_amd import fdtd as F
+    fields = [f for f, _ in F.Config._fields_]
+    tfields = [f for f, _ in F.Timing._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "fdtd.h"', "int main(void) {",
+           'printf("%zu %zu\\n", sizeof(fdtd_config), sizeof(fdtd_timing));']
+    src += [f'printf("%zu\\n", offsetof(fdtd_config, {f}));' for f in fields]
+    src += [f'printf("%zu\\n", offsetof(fdtd_timing, {f}));' for f in tfields]
+    src += ["return 0; }"]
+    (tmp_path / "l.c").write_text("\n".join(src))
+    exe = str(tmp_path / "l")
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(tmp_path / "l.c"), "-o", exe])
+    out = subprocess.check_output([exe]).decode().split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(F.Config) and vals[1] == ctypes.sizeof(F.Timing)
+    assert vals[2:2 + len(fields)] == [getattr(F.Config, f).offset for f in fields]
+    assert vals[2 + len(fields):] == [getattr(F.Timing, f).offset for f in tfields]
 
 
 @pytest.mark.parametrize("over,msg", [
@@ -47,6 +72,7 @@ def test_library_exports_every_declared_symbol(lib):
     (dict(n_freq=0), "n_freq"),
     (dict(eps_s=-1.0), "permittivity"),
     (dict(psi_s_ratio=0.0), "psi_s_ratio"),
+    (dict(ckpt_every=-1), "ckpt_every"),
 ])
 def test_invalid_configs_rejected_before_device(lib, over, msg):
     w = W.tiny2d(**over)

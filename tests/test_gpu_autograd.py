@@ -1,0 +1,98 @@
+"""rho -> F as a torch.autograd operation (paper_2203_01462_amd.autograd).
+
+The backward pass (adjoint FDTD + eq. (25)/(27) sums in the HIP library) is
+checked against central finite differences of the forward (h = 1e-4, FP64,
+20 random design cells), against the CPU oracle's gradient, with a
+checkpointed solver, and when another forward ran on the same context between
+this forward and its backward."""
+import numpy as np
+import pytest
+
+import fdtd_workloads as W
+from test_gpu_parity_2d import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tg():
+    import torch
+    from paper_2203_01462_amd import autograd as A
+    return torch, A
+
+
+def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3):
+    torch, A = tg
+    s = A.Solver(w, ckpt_every=ckpt_every)
+    rho0 = W.seeded_rho(w, 0)
+    rho = torch.tensor(rho0, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = A.objective(rho, s)
+    F.backward()
+    g = rho.grad.detach().cpu().numpy()
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(rho0.size, size=cells, replace=False)
+    worst = 0.0
+    for f in flat:
+        idx = np.unravel_index(f, rho0.shape)
+        vals = []
+        for sgn in (1, -1):
+            r = rho0.copy()
+            r[idx] += sgn * h
+            vals.append(A.objective(torch.tensor(r, device="cuda"), s).item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        err = abs(g[idx] - fd) / max(abs(fd), 1e-3 * np.abs(g).max())
+        worst = max(worst, err)
+    say(f"[autograd] {w['name']} K={ckpt_every}: F={F.item():.9e} worst FD rel err={worst:.2e}")
+    assert worst <= 1e-6
+    return F.item(), g
+
+
+def test_tiny2d_autograd_matches_fd_and_oracle(tg, oracle_mod):
+    w = W.tiny2d()
+    F, g = fd_check(tg, w, 0)
+    Fo, go = oracle_mod.Oracle(w).run(W.seeded_rho(w, 0))
+    assert abs(F - Fo) <= 1e-11 * abs(Fo) and rel_l2(g, go) <= 1e-11
+
+
+def test_medium3d_autograd_checkpointed_matches_fd(tg):
+    fd_check(tg, W.medium3d(precision=64), 100)
+
+
+def test_backward_after_an_intervening_forward(tg):
+    torch, A = tg
+    w = W.tiny2d()
+    s = A.Solver(w, ckpt_every=200)
+    r1 = torch.tensor(W.seeded_rho(w, 1), device="cuda", requires_grad=True)
+    r2 = torch.tensor(W.seeded_rho(w, 2), device="cuda", requires_grad=True)
+    F1 = A.objective(r1, s)
+    F2 = A.objective(r2, s)          # the context now holds r2's forward
+    (F1 + 2.0 * F2).backward()
+    ref = A.Solver(w)
+    for r, wgt in ((r1, 1.0), (r2, 2.0)):
+        rr = r.detach().clone().requires_grad_(True)
+        A.objective(rr, ref).backward()
+        assert torch.equal(r.grad, wgt * rr.grad)
+
+
+def test_autograd_fp32_chain_rule(tg):
+    torch, A = tg
+    w = W.tiny2d(precision=32)
+    s = A.Solver(w)
+    rho = torch.tensor(W.seeded_rho(w, 0), dtype=torch.float32, device="cuda", requires_grad=True)
+    loss = torch.log(A.objective(rho, s))
+    loss.backward()
+    F = s.solve(rho.detach())
+    s.adjoint()
+    g = torch.empty_like(rho)
+    s.gradient(out=g)
+    assert torch.allclose(rho.grad, g / F, rtol=1e-6, atol=0)
+
+
+def test_objective_rejects_wrong_inputs(tg):
+    torch, A = tg
+    w = W.tiny2d()
+    s = A.Solver(w)
+    with pytest.raises(TypeError):
+        A.objective(torch.zeros(s.nd, dtype=torch.float64), s)
+    with pytest.raises(ValueError):
+        A.objective(torch.zeros(s.nd, dtype=torch.float32, device="cuda"), s)
