@@ -34,9 +34,13 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source they were taken on.  Reported only while that source is
 # unchanged; the summaries live in profiles/.
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "fa4adb05999414b8",
-                        "fwd": 116.0e6, "adj": 120.2e6,
+    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "05ea8ad6322806be",
+                        "fwd": 115.9e6, "adj": 120.2e6,
                         "profile": "profiles/step2d_kernel_tmz2d_2048_fp32.md"},
+    # one time step = step3d_general + step3d_plain
+    "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "152070d68ad79a77",
+                       "fwd": 1238.9e6, "adj": 1247.6e6,
+                       "profile": "profiles/step3d_yee3d_256_fp32.md"},
 }
 
 
@@ -112,6 +116,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="checkpoint the forward every K steps (0: store the full history)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 device copies of 1 GiB (calibrates HBM byte counters)")
@@ -139,7 +145,8 @@ def main():
         base = W.with_(base, n_steps=args.n_steps)
     gmults = [1.0, 4.0, 16.0] if args.workload == "c2" else [1.0]
     stream = torch.cuda.Stream()
-    ctxs = [P.FDTD(W.with_(base, gamma_mult=g), stream=stream.cuda_stream) for g in gmults]
+    ctxs = [P.FDTD(W.with_(base, gamma_mult=g), stream=stream.cuda_stream, ckpt_every=args.ckpt_every)
+            for g in gmults]
     dt_np = np.float32 if base["precision"] == 32 else np.float64
     rho_host = W.seeded_rho(base, 0).astype(dt_np)
     with torch.cuda.stream(stream):
@@ -183,7 +190,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_per_launch_fwd_adj": [trec["fwd"], trec["adj"]] if trec else None,
-                "kernel": "step2d_kernel" if base["dims"] == 2 else "step3d_bulk+step3d_general (one time step)",
+                "kernel": "step2d_kernel" if base["dims"] == 2 else "step3d_general+step3d_plain (one time step)",
                 "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
                 "avg_launch_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
                 "avg_launch_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}
@@ -197,6 +204,7 @@ def main():
                    "dx_nm": base["dx"] * 1e9, "time_steps": base["n_steps"], "pml_cells": base["pml_cells"],
                    "design_box": list(base["design_n"][:base["dims"]]), "gap_box": list(base["gap_n"][:base["dims"]]),
                    "n_freq": base["n_freq"], "gamma_mult_cycle": gmults, "density": "seeded smoothed U[0,1), seed 0",
+                   "ckpt_every": args.ckpt_every,
                    "parallelism": "single GPU"},
         "roofline": roofline,
     }
