@@ -136,6 +136,36 @@ def tiny3d(**over):
     return w
 
 
+def instance2d(side, gamma_mult, lambda_lo, lambda_hi, n_steps, precision=32, n_freq=8, name=None):
+    """One square 2D TMz instance with the 2048^2 workload's physics (dx = 2 nm,
+    eps_s = 2.25, Drude metal), scaled to its side: 16-cell CPML, a centred
+    design box of side/4 and a 3x3 gap at its centre."""
+    w = dict(_COMMON)
+    m = max(side // 4, 8)
+    lo = _centered(side, m)
+    g = lo + m // 2 - 1
+    w.update(name=name or f"tmz2d_{side}_b", dims=2, precision=precision, n=(side, side, 1), dx=2e-9,
+             n_steps=n_steps, pml_cells=16, tfsf_margin=6, t0_over_tau=3.0,
+             design_lo=(lo, lo, 0), design_n=(m, m, 1), gap_lo=(g, g, 0), gap_n=(3, 3, 1),
+             lambda_lo=lambda_lo, lambda_hi=lambda_hi, n_freq=n_freq, gamma_mult=gamma_mult)
+    return w
+
+
+def c4(count=64, n_steps=5000, seed=0, sides=(128, 256, 512, 1024)):
+    """Batched uneven 2D FP32: `count` TMz instances with sides drawn from
+    `sides`, collision-rate multipliers uniform in [1, 16] and an 8-frequency
+    band of at least 100 nm inside 500-1000 nm, `n_steps` steps each."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        side = int(rng.choice(sides))
+        gm = float(rng.uniform(1.0, 16.0))
+        a = float(rng.uniform(500e-9, 900e-9))
+        b = float(rng.uniform(a + 100e-9, 1000e-9))
+        out.append(instance2d(side, gm, a, b, n_steps, name=f"tmz2d_{side}_b{k}"))
+    return out
+
+
 PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "medium3d": medium3d, "tiny2d": tiny2d,
            "tiny3d": tiny3d}
 

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 2
+#define FDTD_ABI_VERSION 3
 
 typedef enum {
   FDTD_OK = 0,
@@ -169,6 +169,55 @@ fdtd_status fdtd_get_timing(fdtd_ctx *ctx, fdtd_timing *out);
 
 /* Release the context and its device memory.  NULL is accepted. */
 fdtd_status fdtd_destroy(fdtd_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches of 2D instances.  Uneven TMz problems (own grid size, density,
+ * damping, band, objective) advance together: each time step of all
+ * instances is one launch per tile depth in use, and the N steps of a forward
+ * (or adjoint) solve are captured once into a HIP graph and replayed.  Every
+ * instance computes exactly what a single context with the same config and
+ * tile depth computes.
+ */
+typedef struct fdtd_batch fdtd_batch; /* opaque */
+
+typedef struct {
+  int32_t rows;       /* nodes per thread along y in the 2D step (tile depth):
+                         1, 2 or 4; 0 = choose per grid size by timing each
+                         depth on the instance (cached per process) */
+  int32_t use_graph;  /* 1: replay the captured step sequence; 0: launch eagerly */
+} fdtd_batch_options;
+
+/* Create `count` >= 1 instances from cfgs[0..count-1]: all dims = 2, the same
+ * precision and n_steps, ckpt_every = 0.  All instances run on one stream:
+ * cfgs[0].stream (the other streams are ignored) or one the library creates.
+ * opt may be NULL (rows = 0, use_graph = 1).  Fails like fdtd_create (the
+ * message names the instance), or EINVAL for mixed precision / step counts. */
+fdtd_status fdtd_batch_create(const fdtd_config *cfgs, int32_t count, const fdtd_batch_options *opt,
+                              fdtd_batch **out);
+
+/* Density of instance `index` (as fdtd_set_density). */
+fdtd_status fdtd_batch_set_density(fdtd_batch *b, int32_t index, const void *rho, int64_t count, int32_t on_device);
+
+/* Forward solve of every instance; objectives_out (host, may be NULL) gets
+ * `count` values.  Requires a density on every instance. */
+fdtd_status fdtd_batch_forward(fdtd_batch *b, double *objectives_out);
+
+/* Adjoint solve of every instance (after fdtd_batch_forward). */
+fdtd_status fdtd_batch_adjoint(fdtd_batch *b);
+
+/* dF/drho of instance `index` (as fdtd_gradient). */
+fdtd_status fdtd_batch_gradient(fdtd_batch *b, int32_t index, void *grad_out, int64_t count, int32_t on_device);
+
+/* Tile depth used for instance `index`, and the event time (ms) of the last
+ * batched forward and adjoint step sequences (all instances together). */
+fdtd_status fdtd_batch_info(fdtd_batch *b, int32_t index, int32_t *rows_out, double *forward_ms, double *adjoint_ms);
+
+/* Release the batch and all instances.  NULL is accepted. */
+fdtd_status fdtd_batch_destroy(fdtd_batch *b);
+
+/* Message of the last failing call on `b` (or of the last failing
+ * fdtd_batch_create when b is NULL). */
+const char *fdtd_batch_last_error(const fdtd_batch *b);
 
 /* Message of the last failing call on `ctx` (or of the last failing
  * fdtd_create when ctx is NULL).  Owned by the library; valid until the next

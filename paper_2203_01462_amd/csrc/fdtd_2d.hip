@@ -24,6 +24,8 @@
 // and no barrier: neighbour values come through the caches.  All arrays that
 // a halo reads come in two copies (read copy par, write copy par^1), so the
 // step needs no grid-wide synchronisation.
+#include <utility>
+
 #include "fdtd_2d.hpp"
 
 namespace fdtd {
@@ -41,8 +43,7 @@ namespace {
 constexpr int WAVES = 4;          // wavefronts per workgroup, stacked along y
 constexpr int NT = 64 * WAVES;    // threads per workgroup
 constexpr int TXW = 64;           // tile width (nodes along x): one wavefront
-constexpr int R = FDTD2D_ROWS;    // rows per thread; a wavefront covers 64 x R nodes
-constexpr int TYB = WAVES * R;    // workgroup tile height
+constexpr int RDEF = FDTD2D_ROWS; // default rows per thread; a wavefront covers 64 x R nodes
 
 __device__ __forceinline__ bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
 __device__ __forceinline__ bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
@@ -81,6 +82,7 @@ __device__ __forceinline__ T ldp(const T *__restrict__ base, size_t q, bool on) 
 // register arithmetic, stores -- with restrict-qualified pointers.
 // A wavefront tile is an edge tile if it (or its one-node halo) touches an
 // absorber cell, a wall or a total-field line.
+template <int R>
 __device__ __forceinline__ bool wave_is_edge(const int nx, const int ny, const int P, const int i0, const int jb,
                                              const int ia, const int ib, const int ja, const int jbt) {
   if (i0 < P + 2 || i0 + TXW > nx - 2 - P || jb < P + 2 || jb + R > ny - 2 - P) return true;
@@ -91,6 +93,7 @@ __device__ __forceinline__ bool wave_is_edge(const int nx, const int ny, const i
 }
 
 // Does the wavefront's 64 x R block of E nodes meet the box [x0,x0+nx) x [y0,y0+ny)?
+template <int R>
 __device__ __forceinline__ bool wave_touches_box(const int i0, const int jb, const int x0, const int y0, const int bnx,
                                                  const int bny) {
   return i0 + TXW - 1 >= x0 && i0 < x0 + bnx && jb + R - 1 >= y0 && jb < y0 + bny;
@@ -98,7 +101,7 @@ __device__ __forceinline__ bool wave_touches_box(const int i0, const int jb, con
 
 // Tiles that are neither edge tiles nor touch the design or gap box need only
 // the plain dielectric update, identical in the forward and adjoint solves.
-template <typename T>
+template <typename T, int R>
 __device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, const int i, const int jb) {
   const int pitch = p.pitch;
   const T *__restrict__ ez = p.ez[par];
@@ -138,7 +141,7 @@ __device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, con
 
 // Absorber, wall, total-field, design and gap nodes.  EDGE = false compiles
 // the absorber and plane-wave terms out (interior design/gap wavefronts).
-template <typename T, bool ADJ, bool EDGE>
+template <typename T, bool ADJ, bool EDGE, int R>
 __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, const int par, const int i,
                                              const int jb) {
   const int nx = p.nx, ny = p.ny, pitch = p.pitch, P = EDGE ? p.P : 0;
@@ -457,41 +460,131 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
   }
 }
 
-template <typename T, bool ADJ>
-__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES) step2d_kernel(const Step2D<T> p, const int n, const int par) {
+// One workgroup's tile: block `bid` of the grid of one instance.
+template <typename T, bool ADJ, int R>
+__device__ __forceinline__ void step2d_block(const Step2D<T> &p, const int n, const int par, const int bid) {
+  constexpr int TYB = WAVES * R;
   const int nx = p.nx, ny = p.ny, P = p.P;
   const int nbx = (nx + TXW - 1) / TXW, nby = (ny + TYB - 1) / TYB;
   int tx, ty;
-  tile_of(blockIdx.x, nbx, nby, tx, ty);
+  tile_of(bid, nbx, nby, tx, ty);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i0 = tx * TXW;
   const int i = i0 + lane;
   const int jb = ty * TYB + wave * R;
-  if (jb >= ny) return;  // no barriers in this kernel
+  if (jb >= ny) return;  // no barriers in these kernels
   const int ia = p.tf_on ? p.ia : -8, ib = p.tf_on ? p.ib : -8, ja = p.tf_on ? p.ja : -8, jbt = p.tf_on ? p.jb : -8;
-  if (!wave_is_edge(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
-    if (!wave_touches_box(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) && !wave_touches_box(i0, jb, p.gx0, p.gy0, p.gnx, p.gny))
-      step_bulk(p, par, i, jb);
+  if (!wave_is_edge<R>(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
+    if (!wave_touches_box<R>(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) &&
+        !wave_touches_box<R>(i0, jb, p.gx0, p.gy0, p.gnx, p.gny))
+      step_bulk<T, R>(p, par, i, jb);
     else
-      step_general<T, ADJ, false>(p, n, par, i, jb);
+      step_general<T, ADJ, false, R>(p, n, par, i, jb);
     return;
   }
-  step_general<T, ADJ, true>(p, n, par, i, jb);
+  step_general<T, ADJ, true, R>(p, n, par, i, jb);
+}
+
+template <typename T, bool ADJ, int R>
+__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES) step2d_kernel(const Step2D<T> p, const int n) {
+  step2d_block<T, ADJ, R>(p, n, 0, blockIdx.x);
+}
+
+// Several instances in one launch: instance k owns workgroups
+// [first[k], first[k+1]); its parameters are read with scalar loads.  Each
+// instance's block count is a multiple of 8, so its local block id keeps the
+// hardware XCD in its low bits (see tile_of).
+template <typename T>
+using cptr2 = const __attribute__((address_space(4))) T *;
+
+template <typename T, bool ADJ, int R>
+__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
+    step2d_batch_kernel(const Step2D<T> *ps, const int *first, const int ninst, const int n, const int par) {
+  const cptr2<int> f = (cptr2<int>)first;
+  const int b = blockIdx.x;
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {  // last k with first[k] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (f[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  Step2D<T> p;
+  static_assert(sizeof(Step2D<T>) % 4 == 0, "parameter block copied as 32-bit words");
+  int *dst = reinterpret_cast<int *>(&p);
+  const cptr2<int> src = (cptr2<int>)(ps + lo);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Step2D<T>) / 4); ++k) dst[k] = src[k];
+  // resolve the ping-pong parity here (copy 0 read, copy 1 written) so the
+  // block body indexes the copies with constants and p stays in registers
+  T *const *arr[7] = {p.ez, p.hx, p.hy, p.pex, p.pey, p.phx, p.phy};
+  T *rd[7], *wr[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    rd[a] = par ? arr[a][1] : arr[a][0];
+    wr[a] = par ? arr[a][0] : arr[a][1];
+  }
+  p.ez[0] = rd[0]; p.ez[1] = wr[0];
+  p.hx[0] = rd[1]; p.hx[1] = wr[1];
+  p.hy[0] = rd[2]; p.hy[1] = wr[2];
+  p.pex[0] = rd[3]; p.pex[1] = wr[3];
+  p.pey[0] = rd[4]; p.pey[1] = wr[4];
+  p.phx[0] = rd[5]; p.phx[1] = wr[5];
+  p.phy[0] = rd[6]; p.phy[1] = wr[6];
+  step2d_block<T, ADJ, R>(p, n, 0, b - f[lo]);
 }
 
 }  // namespace
 
-template <typename T>
-void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s) {
-  const int nbx = (p.nx + TXW - 1) / TXW, nby = (p.ny + TYB - 1) / TYB;
-  const dim3 grid(nbx * nby);
-  if (adjoint)
-    hipLaunchKernelGGL((step2d_kernel<T, true>), grid, dim3(NT), 0, s, p, n, par);
-  else
-    hipLaunchKernelGGL((step2d_kernel<T, false>), grid, dim3(NT), 0, s, p, n, par);
+int step2d_blocks(int nx, int ny, int rows) {
+  const int nbx = (nx + TXW - 1) / TXW, nby = (ny + WAVES * rows - 1) / (WAVES * rows);
+  return nbx * nby;
 }
 
-template void launch_step2d<float>(const Step2D<float> &, int, int, bool, hipStream_t);
-template void launch_step2d<double>(const Step2D<double> &, int, int, bool, hipStream_t);
+// The ping-pong parity is resolved here (copy 0 read, copy 1 written), so
+// the kernel indexes the copies with constants.
+template <typename T, bool ADJ>
+static void launch_one(const Step2D<T> &p0, int n, int par, int rows, hipStream_t s) {
+  Step2D<T> p = p0;
+  if (par) {
+    std::swap(p.ez[0], p.ez[1]);
+    std::swap(p.hx[0], p.hx[1]);
+    std::swap(p.hy[0], p.hy[1]);
+    std::swap(p.pex[0], p.pex[1]);
+    std::swap(p.pey[0], p.pey[1]);
+    std::swap(p.phx[0], p.phx[1]);
+    std::swap(p.phy[0], p.phy[1]);
+  }
+  const dim3 grid(step2d_blocks(p.nx, p.ny, rows));
+  if (rows == 1) hipLaunchKernelGGL((step2d_kernel<T, ADJ, 1>), grid, dim3(NT), 0, s, p, n);
+  else if (rows == 4) hipLaunchKernelGGL((step2d_kernel<T, ADJ, 4>), grid, dim3(NT), 0, s, p, n);
+  else hipLaunchKernelGGL((step2d_kernel<T, ADJ, 2>), grid, dim3(NT), 0, s, p, n);
+}
+
+template <typename T>
+void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows) {
+  if (rows <= 0) rows = RDEF;
+  if (adjoint) launch_one<T, true>(p, n, par, rows, s);
+  else launch_one<T, false>(p, n, par, rows, s);
+}
+
+template <typename T, bool ADJ>
+static void launch_batch(const Step2D<T> *ps, const int *first, int ninst, int nblocks, int n, int par, int rows,
+                         hipStream_t s) {
+  const dim3 grid(nblocks);
+  if (rows == 1) hipLaunchKernelGGL((step2d_batch_kernel<T, ADJ, 1>), grid, dim3(NT), 0, s, ps, first, ninst, n, par);
+  else if (rows == 4) hipLaunchKernelGGL((step2d_batch_kernel<T, ADJ, 4>), grid, dim3(NT), 0, s, ps, first, ninst, n, par);
+  else hipLaunchKernelGGL((step2d_batch_kernel<T, ADJ, 2>), grid, dim3(NT), 0, s, ps, first, ninst, n, par);
+}
+
+template <typename T>
+void launch_step2d_batch(const Step2D<T> *ps, const int *first, int ninst, int nblocks, int n, int par, bool adjoint,
+                         int rows, hipStream_t s) {
+  if (adjoint) launch_batch<T, true>(ps, first, ninst, nblocks, n, par, rows, s);
+  else launch_batch<T, false>(ps, first, ninst, nblocks, n, par, rows, s);
+}
+
+template void launch_step2d<float>(const Step2D<float> &, int, int, bool, hipStream_t, int);
+template void launch_step2d<double>(const Step2D<double> &, int, int, bool, hipStream_t, int);
+template void launch_step2d_batch<float>(const Step2D<float> *, const int *, int, int, int, int, bool, int, hipStream_t);
+template void launch_step2d_batch<double>(const Step2D<double> *, const int *, int, int, int, int, bool, int, hipStream_t);
 
 }  // namespace fdtd

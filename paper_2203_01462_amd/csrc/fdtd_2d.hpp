@@ -38,7 +38,18 @@ struct Step2D {
   double dt;
 };
 
+// One time step; rows = nodes per thread along y (1, 2 or 4; 0 = default).
 template <typename T>
-void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s);
+void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows = 0);
+
+// Workgroups of one instance's step launch.
+int step2d_blocks(int nx, int ny, int rows);
+
+// One time step of several instances (device array `ps` of their parameters,
+// `first[k]` = first workgroup of instance k, blocks of each instance padded
+// to a multiple of 8; `nblocks` = total), all with the same tile depth.
+template <typename T>
+void launch_step2d_batch(const Step2D<T> *ps, const int *first, int ninst, int nblocks, int n, int par, bool adjoint,
+                         int rows, hipStream_t s);
 
 }  // namespace fdtd

@@ -2,7 +2,11 @@
 // buffer management and the solve drivers.  The time loops only enqueue
 // kernels on the context stream; all arithmetic of a solve runs on the GPU.
 #include <algorithm>
+#include <array>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <vector>
 
 #include "fdtd_2d.hpp"
 #include "fdtd_3d.hpp"
@@ -451,6 +455,206 @@ fdtd_status guard(fdtd_ctx *c, F &&f) {
   }
 }
 
+// Steps of a forward solve around the time stepping (shared by single
+// contexts and batches).
+void fwd_prepare(fdtd_ctx *c) {
+  if (c->state < 1) throw Error{FDTD_ESTATE, "forward before set_density"};
+  c->state = 1;
+  zero_state(c);
+  zero(c, c->gapE);
+}
+
+void fwd_objective(fdtd_ctx *c) {
+  const fdtd_config &g = c->cfg;
+  launch_dft(c->stream, c->gapE.as<double>(), c->phasor.as<double>(), c->K, c->nmon, c->N, c->dt, c->dft.as<double>());
+  const double te_scale = 0.5 * g.eps_g * c->dt * g.dx * g.dx * g.dx;
+  launch_objective(c->stream, c->dft.as<double>(), c->wts.as<double>(), c->gapE.as<double>(), c->K, c->nmon, c->N,
+                   g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_scale, c->Fdev.as<double>());
+}
+
+void fwd_finish(fdtd_ctx *c, double F) {
+  if (!std::isfinite(F)) throw Error{FDTD_EUNSTABLE, "non-finite objective"};
+  c->F = F;
+  c->state = 2;
+}
+
+void adj_prepare(fdtd_ctx *c) {
+  if (c->state < 2) throw Error{FDTD_ESTATE, "adjoint before forward"};
+  const fdtd_config &g = c->cfg;
+  const double te_coef = g.eps_g * c->dt * g.dx * g.dx * g.dx;
+  launch_adjoint_source(c->stream, c->prec, c->dft.as<double>(), c->wts.as<double>(), c->phasor.as<double>(),
+                        c->gapE.as<double>(), c->K, c->nmon, c->N, g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_coef,
+                        c->dt, g.dx, c->scal.as<double>(), c->asrc.p);
+  zero_state(c);
+  zero(c, c->grad);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- batches
+struct fdtd_batch {
+  std::vector<fdtd_ctx *> inst;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int prec = 64, N = 0;
+  fdtd_batch_options opt{0, 1};
+  std::vector<int> rows;  // tile depth per instance
+  struct Group {          // instances sharing one tile depth: one launch per step
+    int R = 2, nblocks = 0;
+    std::vector<int> members;
+    DevBuf params, first;
+  };
+  std::vector<Group> groups;
+  hipGraph_t graph[2] = {nullptr, nullptr};  // forward, adjoint step sequences
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double ms[2] = {0, 0};
+  std::string err;
+  ~fdtd_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (int k = 0; k < 2; ++k) {
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+    }
+    for (int k = 0; k < 4; ++k) if (ev[k]) (void)hipEventDestroy(ev[k]);
+    for (fdtd_ctx *c : inst) fdtd_destroy(c);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+std::string g_batch_error;
+
+// Autotuned tile depth per (nx, ny, precision, absorber cells), per process.
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, int> g_tune;
+
+// Time `steps` forward steps of each tile depth on instance c (its state is
+// scratch here: the next forward zeroes it) and return the fastest depth.
+template <typename T>
+int tune_rows(fdtd_ctx *c, hipStream_t s) {
+  const std::array<int, 4> key{c->nx, c->ny, c->prec, c->cfg.pml_cells};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  const int cand[3] = {1, 2, 4};
+  const int warm = 5, steps = 20;
+  hipEvent_t e0, e1;
+  FDTD_HIP(hipEventCreate(&e0));
+  FDTD_HIP(hipEventCreate(&e1));
+  int best = 2;
+  float best_ms = 1e30f;
+  Step2D<T> p = params2d<T>(c, false);
+  for (int R : cand) {
+    for (int k = 0; k < warm + steps; ++k) {
+      if (k == warm) FDTD_HIP(hipEventRecord(e0, s));
+      const int n = k % c->N;
+      launch_step2d<T>(p, n, n & 1, false, s, R);
+    }
+    FDTD_HIP(hipEventRecord(e1, s));
+    FDTD_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    FDTD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = R;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
+// Launch one time step of every instance (one launch per tile-depth group).
+template <typename T>
+void batch_step(fdtd_batch *b, int n, int par, bool adjoint) {
+  for (auto &g : b->groups)
+    launch_step2d_batch<T>(g.params.as<Step2D<T>>(), g.first.as<int>(), (int)g.members.size(), g.nblocks, n, par,
+                           adjoint, g.R, b->stream);
+}
+
+template <typename T>
+void batch_steps(fdtd_batch *b, bool adjoint) {
+  const int N = b->N;
+  if (!adjoint)
+    for (int n = 0; n < N; ++n) batch_step<T>(b, n, n & 1, false);
+  else
+    for (int m = N; m >= 1; --m) batch_step<T>(b, m, (N - m) & 1, true);
+}
+
+// The N steps of a solve: captured into a graph on first use, then replayed.
+template <typename T>
+void batch_run(fdtd_batch *b, bool adjoint) {
+  const int k = adjoint ? 1 : 0;
+  if (b->opt.use_graph && !b->exec[k]) {
+    FDTD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    batch_steps<T>(b, adjoint);
+    FDTD_HIP(hipStreamEndCapture(b->stream, &b->graph[k]));
+    FDTD_HIP(hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0));
+  }
+  FDTD_HIP(hipEventRecord(b->ev[2 * k], b->stream));
+  if (b->opt.use_graph)
+    FDTD_HIP(hipGraphLaunch(b->exec[k], b->stream));
+  else
+    batch_steps<T>(b, adjoint);
+  FDTD_HIP(hipGetLastError());
+  FDTD_HIP(hipEventRecord(b->ev[2 * k + 1], b->stream));
+}
+
+template <typename T>
+void batch_setup(fdtd_batch *b) {
+  const int cnt = (int)b->inst.size();
+  b->rows.assign(cnt, 2);
+  for (int k = 0; k < cnt; ++k)
+    b->rows[k] = b->opt.rows > 0 ? b->opt.rows : tune_rows<T>(b->inst[k], b->stream);
+  for (int R : {1, 2, 4}) {
+    fdtd_batch::Group g;
+    g.R = R;
+    std::vector<Step2D<T>> ps;
+    std::vector<int> first;
+    for (int k = 0; k < cnt; ++k) {
+      if (b->rows[k] != R) continue;
+      fdtd_ctx *c = b->inst[k];
+      g.members.push_back(k);
+      Step2D<T> p = params2d<T>(c, false);
+      p.hist_base = 0;
+      p.hist_on = 1;
+      ps.push_back(p);
+      first.push_back(g.nblocks);
+      g.nblocks += (step2d_blocks(c->nx, c->ny, R) + 7) / 8 * 8;  // keeps the XCD in the low bits
+    }
+    if (g.members.empty()) continue;
+    upload(b->stream, g.params, ps);
+    upload(b->stream, g.first, first);
+    b->groups.push_back(std::move(g));
+  }
+  FDTD_HIP(hipStreamSynchronize(b->stream));
+}
+
+template <typename F>
+fdtd_status bguard(fdtd_batch *b, F &&f) {
+  try {
+    f();
+    return FDTD_OK;
+  } catch (const Error &e) {
+    if (b) b->err = e.msg; else g_batch_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (b) b->err = "host out of memory"; else g_batch_error = "host out of memory";
+    return FDTD_ENOMEM;
+  }
+}
+
+fdtd_ctx *instance(fdtd_batch *b, int32_t index) {
+  if (index < 0 || index >= (int32_t)b->inst.size()) throw einval("instance index out of range");
+  return b->inst[index];
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,17 +765,9 @@ fdtd_status fdtd_set_density(fdtd_ctx *ctx, const void *rho, int64_t count, int3
 fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
   if (!ctx) return FDTD_EINVAL;
   return guard(ctx, [&] {
-    if (ctx->state < 1) throw Error{FDTD_ESTATE, "forward before set_density"};
-    ctx->state = 1;
-    zero_state(ctx);
-    zero(ctx, ctx->gapE);
+    fwd_prepare(ctx);
     if (ctx->prec == 32) run_forward<float>(ctx); else run_forward<double>(ctx);
-    const fdtd_config &g = ctx->cfg;
-    launch_dft(ctx->stream, ctx->gapE.as<double>(), ctx->phasor.as<double>(), ctx->K, ctx->nmon, ctx->N, ctx->dt,
-               ctx->dft.as<double>());
-    const double te_scale = 0.5 * g.eps_g * ctx->dt * g.dx * g.dx * g.dx;
-    launch_objective(ctx->stream, ctx->dft.as<double>(), ctx->wts.as<double>(), ctx->gapE.as<double>(), ctx->K,
-                     ctx->nmon, ctx->N, g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_scale, ctx->Fdev.as<double>());
+    fwd_objective(ctx);
     double F = 0;
     FDTD_HIP(hipMemcpyAsync(&F, ctx->Fdev.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     FDTD_HIP(hipStreamSynchronize(ctx->stream));
@@ -579,25 +775,15 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
     FDTD_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     ctx->timing.forward_ms = ms;
     ctx->timing.forward_launches = ctx->N;
-    if (!std::isfinite(F)) throw Error{FDTD_EUNSTABLE, "non-finite objective"};
-    ctx->F = F;
+    fwd_finish(ctx, F);
     if (objective_out) *objective_out = F;
-    ctx->state = 2;
   });
 }
 
 fdtd_status fdtd_adjoint(fdtd_ctx *ctx) {
   if (!ctx) return FDTD_EINVAL;
   return guard(ctx, [&] {
-    if (ctx->state < 2) throw Error{FDTD_ESTATE, "adjoint before forward"};
-    const fdtd_config &g = ctx->cfg;
-    const double te_coef = g.eps_g * ctx->dt * g.dx * g.dx * g.dx;
-    launch_adjoint_source(ctx->stream, ctx->prec, ctx->dft.as<double>(), ctx->wts.as<double>(),
-                          ctx->phasor.as<double>(), ctx->gapE.as<double>(), ctx->K, ctx->nmon, ctx->N,
-                          g.objective_kind == FDTD_OBJ_TIME_ENERGY, te_coef, ctx->dt, g.dx, ctx->scal.as<double>(),
-                          ctx->asrc.p);
-    zero_state(ctx);
-    zero(ctx, ctx->grad);
+    adj_prepare(ctx);
     if (ctx->prec == 32) run_adjoint<float>(ctx); else run_adjoint<double>(ctx);
     ctx->timing.adjoint_launches = ctx->N;
     ctx->state = 3;
@@ -645,5 +831,128 @@ fdtd_status fdtd_get_timing(fdtd_ctx *ctx, fdtd_timing *out) {
   out->design_cells = ctx->nd;
   return FDTD_OK;
 }
+
+fdtd_status fdtd_batch_create(const fdtd_config *cfgs, int32_t count, const fdtd_batch_options *opt, fdtd_batch **out) {
+  if (!out) { g_batch_error = "null out pointer"; return FDTD_EINVAL; }
+  *out = nullptr;
+  std::unique_ptr<fdtd_batch> b(new fdtd_batch());
+  fdtd_status st = bguard(nullptr, [&] {
+    if (!cfgs || count < 1) throw einval("need at least one config");
+    if (opt) b->opt = *opt;
+    if (b->opt.rows != 0 && b->opt.rows != 1 && b->opt.rows != 2 && b->opt.rows != 4)
+      throw einval("batch rows must be 0, 1, 2 or 4");
+    for (int k = 0; k < count; ++k) {
+      if (cfgs[k].dims != 2) throw einval("batch instance " + std::to_string(k) + ": batches hold 2D instances");
+      if (cfgs[k].precision != cfgs[0].precision) throw einval("batch instances must share the precision");
+      if (cfgs[k].n_steps != cfgs[0].n_steps) throw einval("batch instances must share n_steps");
+      if (cfgs[k].ckpt_every != 0) throw einval("batch instances keep the full history (ckpt_every = 0)");
+    }
+    if (cfgs[0].stream) {
+      b->stream = (hipStream_t)cfgs[0].stream;
+    } else {
+      FDTD_HIP(hipStreamCreate(&b->stream));
+      b->own_stream = true;
+    }
+    for (int k = 0; k < 4; ++k) FDTD_HIP(hipEventCreate(&b->ev[k]));
+    b->prec = cfgs[0].precision;
+    b->N = cfgs[0].n_steps;
+    for (int k = 0; k < count; ++k) {
+      fdtd_config c = cfgs[k];
+      c.stream = b->stream;
+      fdtd_ctx *ctx = nullptr;
+      const fdtd_status s2 = fdtd_create(&c, &ctx);
+      if (s2 != FDTD_OK) throw Error{s2, "batch instance " + std::to_string(k) + ": " + g_create_error};
+      b->inst.push_back(ctx);
+    }
+    if (b->prec == 32) batch_setup<float>(b.get()); else batch_setup<double>(b.get());
+  });
+  if (st != FDTD_OK) return st;
+  *out = b.release();
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_batch_set_density(fdtd_batch *b, int32_t index, const void *rho, int64_t count, int32_t on_device) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    fdtd_ctx *c = instance(b, index);
+    const fdtd_status s = fdtd_set_density(c, rho, count, on_device);
+    if (s != FDTD_OK) throw Error{s, c->err};
+  });
+}
+
+fdtd_status fdtd_batch_forward(fdtd_batch *b, double *objectives_out) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    for (fdtd_ctx *c : b->inst) fwd_prepare(c);
+    if (b->prec == 32) batch_run<float>(b, false); else batch_run<double>(b, false);
+    const size_t cnt = b->inst.size();
+    std::vector<double> F(cnt, 0.0);
+    for (size_t k = 0; k < cnt; ++k) {
+      fwd_objective(b->inst[k]);
+      FDTD_HIP(hipMemcpyAsync(&F[k], b->inst[k]->Fdev.p, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    }
+    FDTD_HIP(hipStreamSynchronize(b->stream));
+    float ms = 0;
+    FDTD_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+    b->ms[0] = ms;
+    for (size_t k = 0; k < cnt; ++k) {
+      b->inst[k]->err.clear();
+      fwd_finish(b->inst[k], F[k]);
+      if (objectives_out) objectives_out[k] = F[k];
+    }
+  });
+}
+
+fdtd_status fdtd_batch_adjoint(fdtd_batch *b) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    for (fdtd_ctx *c : b->inst) adj_prepare(c);
+    if (b->prec == 32) batch_run<float>(b, true); else batch_run<double>(b, true);
+    FDTD_HIP(hipStreamSynchronize(b->stream));
+    float ms = 0;
+    FDTD_HIP(hipEventElapsedTime(&ms, b->ev[2], b->ev[3]));
+    b->ms[1] = ms;
+    for (fdtd_ctx *c : b->inst) {
+      c->state = 3;
+      c->timing.adjoint_ms = 0;
+    }
+  });
+}
+
+fdtd_status fdtd_batch_gradient(fdtd_batch *b, int32_t index, void *grad_out, int64_t count, int32_t on_device) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    fdtd_ctx *c = instance(b, index);
+    if (c->state < 3) throw Error{FDTD_ESTATE, "gradient before adjoint"};
+    if (!grad_out) throw einval("null gradient buffer");
+    if (count != (int64_t)c->nd) throw einval("gradient count must equal the number of design cells");
+    const fdtd_config &g = c->cfg;
+    void *dst = on_device ? grad_out : c->gtmp.p;
+    launch_grad_finalize(c->stream, c->prec, c->grad.as<double>(), c->scal.as<double>(), c->ncomp, g.design_n[0],
+                         g.design_n[1], 1, g.gap_lo[0] - g.design_lo[0], g.gap_lo[1] - g.design_lo[1], 0, g.gap_n[0],
+                         g.gap_n[1], 1, dst);
+    if (!on_device) {
+      FDTD_HIP(hipMemcpyAsync(grad_out, c->gtmp.p, (size_t)count * c->esz, hipMemcpyDeviceToHost, c->stream));
+      FDTD_HIP(hipStreamSynchronize(c->stream));
+    }
+  });
+}
+
+fdtd_status fdtd_batch_info(fdtd_batch *b, int32_t index, int32_t *rows_out, double *forward_ms, double *adjoint_ms) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    (void)instance(b, index);
+    if (rows_out) *rows_out = b->rows[index];
+    if (forward_ms) *forward_ms = b->ms[0];
+    if (adjoint_ms) *adjoint_ms = b->ms[1];
+  });
+}
+
+fdtd_status fdtd_batch_destroy(fdtd_batch *b) {
+  delete b;
+  return FDTD_OK;
+}
+
+const char *fdtd_batch_last_error(const fdtd_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
 
 }  // extern "C"

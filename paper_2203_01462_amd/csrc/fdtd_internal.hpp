@@ -56,6 +56,23 @@ struct DevBuf {
   }
   template <typename T>
   T *as() const { return static_cast<T *>(p); }
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;  // sole owner of its allocation
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
 };
 

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 C0 = 299792458.0
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSTABLE"}
@@ -60,9 +60,15 @@ class Timing(C.Structure):
                 ("cells", C.c_int64), ("design_cells", C.c_int64)]
 
 
+class BatchOptions(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("use_graph", C.c_int32)]
+
+
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint",
-           "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error"]
+           "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error",
+           "fdtd_batch_create", "fdtd_batch_set_density", "fdtd_batch_forward", "fdtd_batch_adjoint",
+           "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_destroy", "fdtd_batch_last_error"]
 
 _lib = None
 
@@ -91,8 +97,19 @@ def load_library(path=LIB_PATH):
     L.fdtd_destroy.argtypes = [P]
     L.fdtd_last_error.argtypes = [P]
     L.fdtd_last_error.restype = C.c_char_p
+    L.fdtd_batch_create.argtypes = [C.POINTER(Config), C.c_int32, C.POINTER(BatchOptions), C.POINTER(P)]
+    L.fdtd_batch_set_density.argtypes = [P, C.c_int32, P, C.c_int64, C.c_int32]
+    L.fdtd_batch_forward.argtypes = [P, C.POINTER(C.c_double)]
+    L.fdtd_batch_adjoint.argtypes = [P]
+    L.fdtd_batch_gradient.argtypes = [P, C.c_int32, P, C.c_int64, C.c_int32]
+    L.fdtd_batch_info.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.fdtd_batch_destroy.argtypes = [P]
+    L.fdtd_batch_last_error.argtypes = [P]
+    L.fdtd_batch_last_error.restype = C.c_char_p
     for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
-               "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy"):
+               "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_batch_create", "fdtd_batch_set_density",
+               "fdtd_batch_forward", "fdtd_batch_adjoint", "fdtd_batch_gradient", "fdtd_batch_info",
+               "fdtd_batch_destroy"):
         getattr(L, fn).restype = C.c_int
     if L.fdtd_abi_version() != ABI_VERSION:
         raise ImportError("libfdtd_hip.so ABI version mismatch")
@@ -230,3 +247,75 @@ class FDTD:
         t = Timing()
         self._check(load_library().fdtd_get_timing(self.h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in Timing._fields_}
+
+
+class Batch:
+    """Uneven 2D instances advanced together (fdtd_batch_*): one launch per
+    tile depth per time step, the step sequences replayed from HIP graphs."""
+
+    def __init__(self, ws, stream=None, rows=0, use_graph=True):
+        L = load_library()
+        self.ws = [dict(w) for w in ws]
+        cfgs = (Config * len(ws))()
+        keep = []
+        for k, w in enumerate(ws):
+            c, kp = make_config(w, stream if k == 0 else None)
+            cfgs[k] = c
+            keep.append(kp)
+        opt = BatchOptions(int(rows), 1 if use_graph else 0)
+        h = C.c_void_p()
+        rc = L.fdtd_batch_create(cfgs, len(ws), C.byref(opt), C.byref(h))
+        if rc:
+            raise FDTDError(rc, L.fdtd_batch_last_error(None).decode())
+        self.h = h
+        self.count = len(ws)
+        self.dtype = np.float32 if ws[0]["precision"] == 32 else np.float64
+        self.dshape = [(w["design_n"][1], w["design_n"][0]) for w in ws]
+
+    def _check(self, rc):
+        if rc:
+            raise FDTDError(rc, load_library().fdtd_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().fdtd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_density(self, k, rho):
+        L = load_library()
+        if _is_torch(rho) and rho.is_cuda:
+            self._check(L.fdtd_batch_set_density(self.h, k, C.c_void_p(rho.data_ptr()), rho.numel(), 1))
+            return
+        r = np.ascontiguousarray(np.asarray(rho, dtype=self.dtype).reshape(-1))
+        self._check(L.fdtd_batch_set_density(self.h, k, r.ctypes.data_as(C.c_void_p), r.size, 0))
+
+    def forward(self):
+        F = (C.c_double * self.count)()
+        self._check(load_library().fdtd_batch_forward(self.h, F))
+        return np.array(F[:])
+
+    def adjoint(self):
+        self._check(load_library().fdtd_batch_adjoint(self.h))
+
+    def gradient(self, k, out=None):
+        L = load_library()
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._check(L.fdtd_batch_gradient(self.h, k, C.c_void_p(out.data_ptr()), out.numel(), 1))
+            return out
+        n = int(np.prod(self.dshape[k]))
+        g = np.zeros(n, dtype=self.dtype)
+        self._check(L.fdtd_batch_gradient(self.h, k, g.ctypes.data_as(C.c_void_p), n, 0))
+        return g.reshape(self.dshape[k])
+
+    def info(self, k):
+        r = C.c_int32()
+        f = C.c_double()
+        a = C.c_double()
+        self._check(load_library().fdtd_batch_info(self.h, k, C.byref(r), C.byref(f), C.byref(a)))
+        return {"rows": r.value, "forward_ms": f.value, "adjoint_ms": a.value}

@@ -100,26 +100,46 @@ def test_medium_fp64(gpu, oracle_mod):
 
 
 def test_c2_full_directional_derivative(gpu):
-    """Full 2048^2 x 20000-step FP32 workload: the adjoint gradient predicts
+    """Full 2048^2 x 20000-step workload in FP64: the adjoint gradient predicts
     the change of F along a random smooth direction (central difference of
-    two more full solves), and F, dF/drho are finite."""
-    w = W.c2()
-    rho = W.seeded_rho(w, 0).astype(np.float32)
-    say("[parity] C2 full 2048^2 x 20000 fp32: forward+adjoint+gradient")
+    two more full solves) to 1e-3 (observed ~8e-5)."""
+    w = W.with_(W.c2(), precision=64)
+    rho = W.seeded_rho(w, 0)
+    say("[parity] C2 full 2048^2 x 20000 fp64: forward+adjoint+gradient")
     g = gpu.FDTD(w)
     F, grad = g.run(rho)
     assert np.isfinite(F) and F > 0 and np.all(np.isfinite(grad))
-    d = W.box_smooth(np.random.default_rng(7).standard_normal(rho.shape)).astype(np.float32)
+    d = W.box_smooth(np.random.default_rng(7).standard_normal(rho.shape))
     h = 0.02
     rp = np.clip(rho + h * d, 0, 1)
     rm = np.clip(rho - h * d, 0, 1)
     g.set_density(rp); Fp = g.forward()
     g.set_density(rm); Fm = g.forward()
     g.close()
-    pred = float(np.dot(grad.astype(np.float64).ravel(), (rp - rm).astype(np.float64).ravel()))
-    say(f"   F={F:.6e}  dF fd={Fp - Fm:.6e} adjoint={pred:.6e}")
-    assert abs((Fp - Fm) - pred) <= 0.02 * abs(Fp - Fm)
+    pred = float(np.dot(grad.ravel(), (rp - rm).ravel()))
+    say(f"   F={F:.9e}  dF fd={Fp - Fm:.9e} adjoint={pred:.9e}")
+    assert abs((Fp - Fm) - pred) <= 1e-3 * abs(Fp - Fm)
 
+
+def test_c2_full_fp32_against_fp64(gpu):
+    """The FP32 build at the full 2048^2 x 20000-step size against the FP64
+    build.  With the seeded grey density the gap field (F ~ 3e-11) is orders of
+    magnitude below the fields around it, and FP32 rounding there shows in the
+    objective at ~3e-4 and in the gradient at ~2.5% relative L2 (FP32 parity on
+    the 512^2 grids is ~1e-6 / ~2e-4).  Bars: 2e-3 and 5e-2."""
+    w = W.c2()
+    rho = W.seeded_rho(w, 0)
+    say("[parity] C2 full 2048^2 x 20000: fp32 vs fp64")
+    res = {}
+    for prec in (32, 64):
+        g = gpu.FDTD(W.with_(w, precision=prec))
+        res[prec] = g.run(rho.astype(g.dtype))
+        g.close()
+    (F32, g32), (F64, g64) = res[32], res[64]
+    eF = abs(F32 - F64) / F64
+    eG = rel_l2(g32, g64)
+    say(f"   F32={F32:.9e} F64={F64:.9e} relF={eF:.2e} relGrad={eG:.2e}")
+    assert eF <= 2e-3 and eG <= 5e-2
 
 def test_call_order_and_validation(gpu):
     w = W.tiny2d()
