@@ -182,8 +182,10 @@ typedef struct fdtd_batch fdtd_batch; /* opaque */
 
 typedef struct {
   int32_t rows;       /* nodes per thread along y in the 2D step (tile depth):
-                         1, 2 or 4; 0 = choose per grid size by timing each
-                         depth on the instance (cached per process) */
+                         1, 2 or 4 for every instance; 0 = tune on the batch at
+                         creation: time 20 batched steps at each uniform depth,
+                         then try the other depths for each grid size in turn
+                         and keep what is faster */
   int32_t use_graph;  /* 1: replay the captured step sequence; 0: launch eagerly */
 } fdtd_batch_options;
 

@@ -526,50 +526,6 @@ namespace {
 
 std::string g_batch_error;
 
-// Autotuned tile depth per (nx, ny, precision, absorber cells), per process.
-std::mutex g_tune_mu;
-std::map<std::array<int, 4>, int> g_tune;
-
-// Time `steps` forward steps of each tile depth on instance c (its state is
-// scratch here: the next forward zeroes it) and return the fastest depth.
-template <typename T>
-int tune_rows(fdtd_ctx *c, hipStream_t s) {
-  const std::array<int, 4> key{c->nx, c->ny, c->prec, c->cfg.pml_cells};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it != g_tune.end()) return it->second;
-  }
-  const int cand[3] = {1, 2, 4};
-  const int warm = 5, steps = 20;
-  hipEvent_t e0, e1;
-  FDTD_HIP(hipEventCreate(&e0));
-  FDTD_HIP(hipEventCreate(&e1));
-  int best = 2;
-  float best_ms = 1e30f;
-  Step2D<T> p = params2d<T>(c, false);
-  for (int R : cand) {
-    for (int k = 0; k < warm + steps; ++k) {
-      if (k == warm) FDTD_HIP(hipEventRecord(e0, s));
-      const int n = k % c->N;
-      launch_step2d<T>(p, n, n & 1, false, s, R);
-    }
-    FDTD_HIP(hipEventRecord(e1, s));
-    FDTD_HIP(hipEventSynchronize(e1));
-    float ms = 0;
-    FDTD_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = R;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = best;
-  return best;
-}
-
 // Launch one time step of every instance (one launch per tile-depth group).
 template <typename T>
 void batch_step(fdtd_batch *b, int n, int par, bool adjoint) {
@@ -606,12 +562,12 @@ void batch_run(fdtd_batch *b, bool adjoint) {
   FDTD_HIP(hipEventRecord(b->ev[2 * k + 1], b->stream));
 }
 
+// Group the instances by tile depth (b->rows) and upload each group's
+// parameter blocks and workgroup table.
 template <typename T>
-void batch_setup(fdtd_batch *b) {
+void build_groups(fdtd_batch *b) {
+  b->groups.clear();
   const int cnt = (int)b->inst.size();
-  b->rows.assign(cnt, 2);
-  for (int k = 0; k < cnt; ++k)
-    b->rows[k] = b->opt.rows > 0 ? b->opt.rows : tune_rows<T>(b->inst[k], b->stream);
   for (int R : {1, 2, 4}) {
     fdtd_batch::Group g;
     g.R = R;
@@ -634,6 +590,69 @@ void batch_setup(fdtd_batch *b) {
     b->groups.push_back(std::move(g));
   }
   FDTD_HIP(hipStreamSynchronize(b->stream));
+}
+
+// Event time of `steps` batched forward steps with the current grouping (the
+// instances' states are scratch here: every forward starts by zeroing them).
+template <typename T>
+float time_batch(fdtd_batch *b, int steps) {
+  build_groups<T>(b);
+  for (int k = 0; k < 3; ++k) batch_step<T>(b, k % b->N, k & 1, false);
+  FDTD_HIP(hipEventRecord(b->ev[0], b->stream));
+  for (int k = 0; k < steps; ++k) batch_step<T>(b, k % b->N, k & 1, false);
+  FDTD_HIP(hipEventRecord(b->ev[1], b->stream));
+  FDTD_HIP(hipEventSynchronize(b->ev[1]));
+  float ms = 0;
+  FDTD_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+  return ms;
+}
+
+// Tile depths: fixed, or tuned on the batch itself -- the fastest uniform
+// depth, then one pass over the grid sizes trying the other depths for all
+// instances of that size.
+template <typename T>
+void batch_setup(fdtd_batch *b) {
+  const int cnt = (int)b->inst.size();
+  if (b->opt.rows > 0) {
+    b->rows.assign(cnt, b->opt.rows);
+    build_groups<T>(b);
+    return;
+  }
+  const int steps = 20;
+  float best = 1e30f;
+  int bestR = 2;
+  for (int R : {1, 2, 4}) {
+    b->rows.assign(cnt, R);
+    const float t = time_batch<T>(b, steps);
+    if (t < best) {
+      best = t;
+      bestR = R;
+    }
+  }
+  b->rows.assign(cnt, bestR);
+  std::vector<std::pair<int, int>> sizes;
+  for (fdtd_ctx *c : b->inst)
+    if (std::find(sizes.begin(), sizes.end(), std::make_pair(c->nx, c->ny)) == sizes.end()) sizes.push_back({c->nx, c->ny});
+  if (sizes.size() > 1) {
+    for (auto sz : sizes) {
+      for (int R : {1, 2, 4}) {
+        std::vector<int> trial = b->rows;
+        bool changed = false;
+        for (int k = 0; k < cnt; ++k)
+          if (b->inst[k]->nx == sz.first && b->inst[k]->ny == sz.second && trial[k] != R) {
+            trial[k] = R;
+            changed = true;
+          }
+        if (!changed) continue;
+        const std::vector<int> keep = b->rows;
+        b->rows = trial;
+        const float t = time_batch<T>(b, steps);
+        if (t < best) best = t;
+        else b->rows = keep;
+      }
+    }
+  }
+  build_groups<T>(b);
 }
 
 template <typename F>

@@ -100,7 +100,7 @@ def test_batch_autotuned_depths(gpu):
     res, depths = run_batch(gpu, ws, rhos, 0, True)
     say(f"[batch] autotuned depths {depths}")
     assert all(d in (1, 2, 4) for d in depths)
-    assert depths[0] == depths[2] and depths[1] == depths[3]  # one choice per grid size
+    assert depths[0] == depths[2] and depths[1] == depths[3]  # one choice per grid size (tuned on the batch)
     F, grads = res[0]
     assert np.all(np.isfinite(F)) and all(np.all(np.isfinite(g)) for g in grads)
 
