@@ -21,23 +21,45 @@ from .fdtd import FDTD
 
 
 class Solver(FDTD):
-    """An FDTD context on torch's current stream that counts its forward solves."""
+    """An FDTD context on a torch stream of its own that counts its forward
+    solves.  Every call first makes that stream wait for the caller's current
+    stream and ends by making the caller's stream wait for it, so tensors
+    flow between torch work and the library in order."""
 
     def __init__(self, w, ckpt_every=None, history_budget_bytes=0, device=None):
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(dev):
-            stream = torch.cuda.current_stream(dev).cuda_stream
-            super().__init__(w, stream=stream, history_budget_bytes=history_budget_bytes, ckpt_every=ckpt_every)
+            self.tstream = torch.cuda.Stream(dev)
+            super().__init__(w, stream=self.tstream.cuda_stream, history_budget_bytes=history_budget_bytes,
+                             ckpt_every=ckpt_every)
         self.device = dev
         self.tdtype = torch.float32 if w["precision"] == 32 else torch.float64
         self.generation = 0
 
+    def _enter(self, *tensors):
+        self.tstream.wait_stream(torch.cuda.current_stream(self.device))
+        for t in tensors:
+            t.record_stream(self.tstream)
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.tstream)
+
     def solve(self, rho):
         """Forward solve on a device density; returns F (host float)."""
+        self._enter(rho)
         self.set_density(rho)
         F = self.forward()
+        self._leave()
         self.generation += 1
         return F
+
+    def adjoint_gradient(self, out):
+        """Adjoint solve and dF/drho into the device tensor `out`."""
+        self._enter(out)
+        self.adjoint()
+        self.gradient(out=out)
+        self._leave()
+        return out
 
 
 class _DensityToObjective(torch.autograd.Function):
@@ -57,9 +79,7 @@ class _DensityToObjective(torch.autograd.Function):
         if s.generation != ctx.generation:
             s.solve(r)
             ctx.generation = s.generation
-        s.adjoint()
-        g = torch.empty_like(r)
-        s.gradient(out=g)
+        g = s.adjoint_gradient(torch.empty_like(r))
         return (gF.to(g.dtype) * g).reshape(r.shape), None
 
 

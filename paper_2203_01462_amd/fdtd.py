@@ -68,7 +68,11 @@ class BatchOptions(C.Structure):
 EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint",
            "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error",
            "fdtd_batch_create", "fdtd_batch_set_density", "fdtd_batch_forward", "fdtd_batch_adjoint",
-           "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_destroy", "fdtd_batch_last_error"]
+           "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_destroy", "fdtd_batch_last_error",
+           # include/fdtd_design.h
+           "fdtd_filter_create", "fdtd_filter_apply", "fdtd_filter_transpose", "fdtd_filter_destroy",
+           "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
+           "fdtd_design_stats", "fdtd_design_last_error"]
 
 _lib = None
 
@@ -106,6 +110,23 @@ def load_library(path=LIB_PATH):
     L.fdtd_batch_destroy.argtypes = [P]
     L.fdtd_batch_last_error.argtypes = [P]
     L.fdtd_batch_last_error.restype = C.c_char_p
+    D = C.c_double
+    L.fdtd_filter_create.argtypes = [C.POINTER(C.c_int32), D, C.c_int32, P, C.POINTER(P)]
+    L.fdtd_filter_apply.argtypes = [P, P, P, D]
+    L.fdtd_filter_transpose.argtypes = [P, P, P]
+    L.fdtd_filter_destroy.argtypes = [P]
+    L.fdtd_mma_create.argtypes = [C.c_int64, C.c_int32, D, D, D, D, D, D, P, C.POINTER(P)]
+    L.fdtd_mma_begin.argtypes = [P, P, D, P, C.POINTER(D)]
+    L.fdtd_mma_solve.argtypes = [P, D, P, C.POINTER(D), C.POINTER(D)]
+    L.fdtd_mma_accept.argtypes = [P, P]
+    L.fdtd_mma_destroy.argtypes = [P]
+    L.fdtd_design_stats.argtypes = [C.c_int64, C.c_int32, P, P, D, D, P, C.POINTER(D)]
+    L.fdtd_design_last_error.argtypes = []
+    L.fdtd_design_last_error.restype = C.c_char_p
+    for fn in ("fdtd_filter_create", "fdtd_filter_apply", "fdtd_filter_transpose", "fdtd_filter_destroy",
+               "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
+               "fdtd_design_stats"):
+        getattr(L, fn).restype = C.c_int
     for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
                "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_batch_create", "fdtd_batch_set_density",
                "fdtd_batch_forward", "fdtd_batch_adjoint", "fdtd_batch_gradient", "fdtd_batch_info",

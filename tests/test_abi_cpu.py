@@ -21,9 +21,13 @@ def lib():
 
 
 def header_symbols():
-    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt)))
+    syms = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            syms |= set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt))
+    return sorted(syms)
 
 
 def test_header_declares_the_boundary():
