@@ -1,0 +1,562 @@
+// fdtd_nn.hip -- kernels of the surrogate network: 3x3 convolutions as
+// implicit GEMMs on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation), their data and weight gradients, and the elementwise,
+// pooling, head, loss and optimizer kernels around them.
+//
+// GEMM tiling: a workgroup (4 wavefronts) owns a 64 x 64 output tile and
+// walks the reduction dimension in steps of 16, staging both operand tiles
+// in LDS (the im2col gather of the 3x3 window happens while staging); each
+// wavefront owns 16 output rows and issues four 16x16x16 MFMAs per step.
+// MFMA operand layout (wave64): lane l holds A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16] and returns D[4(l/16)+j][l%16], j = 0..3.
+#include <cstdint>
+#include <string>
+
+#include "fdtd_internal.hpp"
+#include "fdtd_nn.h"
+
+using namespace fdtd;
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BS = 256;
+constexpr int TM = 64, TN = 64, TK = 16, PAD = 4;
+
+// IEEE binary32 -> bfloat16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < BS / 64; ++k) s += lds[k];
+  __syncthreads();
+  return s;
+}
+
+// One 16-step of the K loop: wavefront `wave` multiplies its 16 rows of As
+// with the four 16-column blocks of Bs.
+__device__ __forceinline__ void mfma_step(const uint16_t (*As)[TK + PAD], const uint16_t (*Bs)[TN + PAD], int wave,
+                                          int lane, f4 acc[4]) {
+  s4 a;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a[j] = (short)As[16 * wave + (lane & 15)][4 * (lane >> 4) + j];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    s4 b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = (short)Bs[4 * (lane >> 4) + j][16 * s + (lane & 15)];
+    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+  }
+}
+
+// z[co][n][p] = bias[co] + sum_k w[co][k] xhat[k][n][p], k = (ci, ky, kx),
+// xhat = the zero-padded 3x3 window of x[ci][n].  Writes z (FP32) and/or
+// a = bf16(max(z, 0)).  grid (ceil(HW/64), ceil(cout/64), n).
+__global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, int w, const uint16_t *__restrict__ x,
+                                                     const uint16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                     float *__restrict__ z, uint16_t *__restrict__ a) {
+  __shared__ uint16_t As[TM][TK + PAD];
+  __shared__ uint16_t Bs[TK][TN + PAD];
+  const int n = blockIdx.z, nimg = gridDim.z, HW = h * w, K = cin * 9;
+  const int p0 = blockIdx.x * TN, co0 = blockIdx.y * TM;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const size_t cs = (size_t)nimg * HW;  // channel stride
+  const uint16_t *xn = x + (size_t)n * HW;
+  f4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    {
+      const int r = t >> 2, c = (t & 3) * 4, co = co0 + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + c + j;
+        As[r][c + j] = (co < cout && k < K) ? wt[(size_t)co * K + k] : (uint16_t)0;
+      }
+    }
+    {
+      const int kk = t >> 4, c = (t & 15) * 4, k = k0 + kk;
+      const int ci = k / 9, r9 = k - ci * 9, ky = r9 / 3, kx = r9 - ky * 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = p0 + c + j;
+        uint16_t v = 0;
+        if (k < K && p < HW) {
+          const int y = p / w, xx = p - y * w, iy = y + ky - 1, ix = xx + kx - 1;
+          if (iy >= 0 && iy < h && ix >= 0 && ix < w) v = xn[(size_t)ci * cs + iy * w + ix];
+        }
+        Bs[kk][c + j] = v;
+      }
+    }
+    __syncthreads();
+    mfma_step(As, Bs, wave, lane, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co0 + 16 * wave + 4 * (lane >> 4) + j, p = p0 + 16 * s + (lane & 15);
+      if (co < cout && p < HW) {
+        const float v = acc[s][j] + (bias ? bias[co] : 0.f);
+        const size_t o = (size_t)co * cs + (size_t)n * HW + p;
+        if (z) z[o] = v;
+        if (a) a[o] = f2bf(fmaxf(v, 0.f));
+      }
+    }
+}
+
+// Partial weight gradients over one range of pixels q = (n, p) of the batch:
+// part[split][co][k] = sum_q dz[co][q] xhat[k][q].  grid (ceil(K/64), ceil(cout/64), splits).
+__global__ void __launch_bounds__(BS) conv_wgrad_kernel(int nimg, int cin, int cout, int h, int w,
+                                                       const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
+                                                       float *__restrict__ part, int chunk) {
+  __shared__ uint16_t As[TM][TK + PAD];  // dz: co x q
+  __shared__ uint16_t Bs[TK][TN + PAD];  // xhat: q x k
+  const int HW = h * w, K = cin * 9;
+  const int64_t P = (int64_t)nimg * HW;
+  const int k0 = blockIdx.x * TN, co0 = blockIdx.y * TM, split = blockIdx.z;
+  const int64_t qb = (int64_t)split * chunk, qe = min(P, qb + chunk);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  f4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t q0 = qb; q0 < qe; q0 += TK) {
+    {
+      const int r = t >> 2, c = (t & 3) * 4, co = co0 + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = q0 + c + j;
+        As[r][c + j] = (co < cout && q < qe) ? dz[(size_t)co * P + q] : (uint16_t)0;
+      }
+    }
+    {
+      const int qq = t >> 4, c = (t & 15) * 4;
+      const int64_t q = q0 + qq;
+      const bool qok = q < qe;
+      const int64_t n = qok ? q / HW : 0;
+      const int p = qok ? (int)(q - n * HW) : 0;
+      const int y = p / w, xx = p - y * w;
+      const uint16_t *xn = x + (size_t)n * HW;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + c + j;
+        uint16_t v = 0;
+        if (qok && k < K) {
+          const int ci = k / 9, r9 = k - ci * 9, ky = r9 / 3, kx = r9 - ky * 3;
+          const int iy = y + ky - 1, ix = xx + kx - 1;
+          if (iy >= 0 && iy < h && ix >= 0 && ix < w) v = xn[(size_t)ci * P + iy * w + ix];
+        }
+        Bs[qq][c + j] = v;
+      }
+    }
+    __syncthreads();
+    mfma_step(As, Bs, wave, lane, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co0 + 16 * wave + 4 * (lane >> 4) + j, k = k0 + 16 * s + (lane & 15);
+      if (co < cout && k < K) part[((size_t)split * cout + co) * K + k] = acc[s][j];
+    }
+}
+
+// dw[i] = sum over splits (fixed order).
+__global__ void __launch_bounds__(BS) split_sum_kernel(const float *__restrict__ part, int splits, int64_t m,
+                                                      float *__restrict__ dw) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= m) return;
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[(size_t)k * m + i];
+  dw[i] = s;
+}
+
+// db[co] = sum_q dz[co][q]; one workgroup per channel.
+__global__ void __launch_bounds__(BS) bias_grad_kernel(int64_t P, const uint16_t *__restrict__ dz,
+                                                      float *__restrict__ db) {
+  __shared__ double lds[BS / 64];
+  const int co = blockIdx.x;
+  double v = 0;
+  for (int64_t q = threadIdx.x; q < P; q += BS) v += bf2f(dz[(size_t)co * P + q]);
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) db[co] = (float)s;
+}
+
+// wrot[ci][co][ky][kx] = w[co][ci][2-ky][2-kx]: the data gradient is the
+// forward convolution of dz with these weights.
+__global__ void __launch_bounds__(BS) rot_kernel(int cin, int cout, const uint16_t *__restrict__ w,
+                                                uint16_t *__restrict__ wrot) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= (int64_t)cin * cout * 9) return;
+  const int r = (int)(i % 9), ci = (int)((i / 9) % cin), co = (int)(i / (9 * (int64_t)cin));
+  wrot[((size_t)ci * cout + co) * 9 + (8 - r)] = w[i];
+}
+
+__global__ void __launch_bounds__(BS) relu_kernel(int64_t n, const float *__restrict__ z, uint16_t *__restrict__ a) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) a[i] = f2bf(fmaxf(z[i], 0.f));
+}
+
+__global__ void __launch_bounds__(BS) relu_back_kernel(int64_t n, const uint16_t *__restrict__ a,
+                                                      const float *__restrict__ da, uint16_t *__restrict__ dz) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) dz[i] = f2bf(bf2f(a[i]) > 0.f ? da[i] : 0.f);
+}
+
+__global__ void __launch_bounds__(BS) to_bf16_kernel(int64_t n, const float *__restrict__ x, uint16_t *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ void __launch_bounds__(BS) from_bf16_kernel(int64_t n, const uint16_t *__restrict__ x, float *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) y[i] = bf2f(x[i]);
+}
+
+// y[plane][i][j] = mean of x[plane][2i..2i+1][2j..2j+1]
+__global__ void __launch_bounds__(BS) pool2_kernel(int64_t planes, int h, int w, const uint16_t *__restrict__ x,
+                                                  uint16_t *__restrict__ y) {
+  const int ho = h / 2, wo = w / 2;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * ho * wo) return;
+  const int64_t pl = i / ((int64_t)ho * wo);
+  const int r = (int)(i % ((int64_t)ho * wo)), yi = r / wo, xi = r - yi * wo;
+  const uint16_t *b = x + (size_t)pl * h * w + (size_t)(2 * yi) * w + 2 * xi;
+  y[i] = f2bf(0.25f * (bf2f(b[0]) + bf2f(b[1]) + bf2f(b[w]) + bf2f(b[w + 1])));
+}
+
+__global__ void __launch_bounds__(BS) pool2_back_kernel(int64_t planes, int h, int w, const float *__restrict__ dy,
+                                                       float *__restrict__ dx) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * h * w) return;
+  const int64_t pl = i / ((int64_t)h * w);
+  const int r = (int)(i % ((int64_t)h * w)), yi = r / w, xi = r - yi * w;
+  dx[i] = 0.25f * dy[(size_t)pl * (h / 2) * (w / 2) + (size_t)(yi / 2) * (w / 2) + xi / 2];
+}
+
+// y[plane][2i+a][2j+b] = x[plane][i][j]
+__global__ void __launch_bounds__(BS) up2_kernel(int64_t planes, int h, int w, const uint16_t *__restrict__ x,
+                                                uint16_t *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * 4 * h * w) return;
+  const int64_t pl = i / (4 * (int64_t)h * w);
+  const int r = (int)(i % (4 * (int64_t)h * w)), yi = r / (2 * w), xi = r - yi * (2 * w);
+  y[i] = x[(size_t)pl * h * w + (size_t)(yi / 2) * w + xi / 2];
+}
+
+__global__ void __launch_bounds__(BS) up2_back_kernel(int64_t planes, int h, int w, const float *__restrict__ dy,
+                                                     float *__restrict__ dx) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * h * w) return;
+  const int64_t pl = i / ((int64_t)h * w);
+  const int r = (int)(i % ((int64_t)h * w)), yi = r / w, xi = r - yi * w;
+  const float *b = dy + (size_t)pl * 4 * h * w + (size_t)(2 * yi) * (2 * w) + 2 * xi;
+  dx[i] = b[0] + b[1] + b[2 * w] + b[2 * w + 1];
+}
+
+__global__ void __launch_bounds__(BS) adam_kernel(int64_t n, float *__restrict__ p, float *__restrict__ m,
+                                                 float *__restrict__ v, const float *__restrict__ g,
+                                                 uint16_t *__restrict__ pb, float lr, float b1, float b2, float eps,
+                                                 float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  if (pb) pb[i] = f2bf(pi);
+}
+
+__global__ void __launch_bounds__(BS) axpy_kernel(int64_t n, float a, const float *__restrict__ x, float *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+// grad = 2 (pred - target) * scale; partial sums of (pred - target)^2
+__global__ void __launch_bounds__(BS) mse_kernel(int64_t n, const float *__restrict__ pred,
+                                                const float *__restrict__ target, float scale,
+                                                float *__restrict__ grad, double *__restrict__ part) {
+  __shared__ double lds[BS / 64];
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double e2 = 0;
+  if (i < n) {
+    const float d = pred[i] - target[i];
+    if (grad) grad[i] = 2.f * d * scale;
+    e2 = (double)d * d;
+  }
+  const double s = block_sum(e2, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(BS) sum_kernel(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  __shared__ double lds[BS / 64];
+  double v = 0;
+  for (int b = threadIdx.x; b < nb; b += BS) v += part[b];
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// out[n] = bl + sum_c wl[c] mean_p a[c][n][p]; one workgroup per image.
+__global__ void __launch_bounds__(BS) gap_linear_kernel(int nimg, int c, int hw, const uint16_t *__restrict__ a,
+                                                       const float *__restrict__ wl, const float *__restrict__ bl,
+                                                       float *__restrict__ out) {
+  __shared__ double lds[BS / 64];
+  const int n = blockIdx.x;
+  double v = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)c * hw; i += BS) {
+    const int ch = (int)(i / hw), p = (int)(i - (int64_t)ch * hw);
+    v += (double)wl[ch] * bf2f(a[((size_t)ch * nimg + n) * hw + p]);
+  }
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) out[n] = (float)(s / hw + bl[0]);
+}
+
+// da[c][n][p] = dout[n] wl[c] / hw
+__global__ void __launch_bounds__(BS) gap_linear_back_a_kernel(int nimg, int c, int hw, const float *__restrict__ dout,
+                                                              const float *__restrict__ wl, float *__restrict__ da) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= (int64_t)c * nimg * hw) return;
+  const int64_t cn = i / hw;
+  const int ch = (int)(cn / nimg), n = (int)(cn - (int64_t)ch * nimg);
+  da[i] = dout[n] * wl[ch] / (float)hw;
+}
+
+// dwl[c] = sum_n dout[n] mean_p a[c][n][p]; dbl = sum_n dout[n].  One workgroup per channel (+1 for the bias).
+__global__ void __launch_bounds__(BS) gap_linear_back_w_kernel(int nimg, int c, int hw, const uint16_t *__restrict__ a,
+                                                              const float *__restrict__ dout, float *__restrict__ dwl,
+                                                              float *__restrict__ dbl) {
+  __shared__ double lds[BS / 64];
+  const int ch = blockIdx.x;
+  double v = 0;
+  if (ch < c) {
+    for (int64_t i = threadIdx.x; i < (int64_t)nimg * hw; i += BS)
+      v += (double)dout[i / hw] * bf2f(a[(size_t)ch * nimg * hw + i]);
+  } else {
+    for (int n = threadIdx.x; n < nimg; n += BS) v += dout[n];
+  }
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) {
+    if (ch < c) dwl[ch] = (float)(s / hw);
+    else dbl[0] = (float)s;
+  }
+}
+
+int nb_of(int64_t n) { return (int)((n + BS - 1) / BS); }
+
+thread_local std::string g_err;
+
+template <typename F>
+fdtd_status nguard(F &&f) {
+  try {
+    f();
+    return FDTD_OK;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return FDTD_EDEVICE;
+  }
+}
+
+void need(bool ok) {
+  if (!ok) throw Error{FDTD_EINVAL, "invalid sizes or missing pointer"};
+}
+
+int wgrad_splits(int n, int h, int w) {
+  const int64_t P = (int64_t)n * h * w;
+  return (int)std::min<int64_t>(64, std::max<int64_t>(1, (P + 4095) / 4096));
+}
+
+}  // namespace
+
+extern "C" {
+
+fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
+                            const uint16_t *wt, const float *bias, float *z, uint16_t *a, void *stream) {
+  return nguard([&] {
+    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && wt && (z || a));
+    const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
+    hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, (hipStream_t)stream, cin, cout, h, w, x, wt, bias, z, a);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
+                                  const uint16_t *wt, uint16_t *wrot, float *dx, void *stream) {
+  return nguard([&] {
+    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && dx);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
+    const dim3 g((h * w + TN - 1) / TN, (cin + TM - 1) / TM, n);
+    hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, s, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w) {
+  if (n <= 0 || cin <= 0 || cout <= 0 || h <= 0 || w <= 0) return 0;
+  return (int64_t)wgrad_splits(n, h, w) * cout * cin * 9;
+}
+
+fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
+                                  const uint16_t *dz, float *dw, float *db, float *work, void *stream) {
+  return nguard([&] {
+    need(n > 0 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && dz && dw && work);
+    hipStream_t s = (hipStream_t)stream;
+    const int K = cin * 9, S = wgrad_splits(n, h, w);
+    const int64_t P = (int64_t)n * h * w;
+    int chunk = (int)((P + S - 1) / S);
+    chunk = (chunk + TK - 1) / TK * TK;
+    const dim3 g((K + TN - 1) / TN, (cout + TM - 1) / TM, S);
+    hipLaunchKernelGGL(conv_wgrad_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, chunk);
+    const int64_t m = (int64_t)cout * K;
+    hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(m)), dim3(BS), 0, s, work, S, m, dw);
+    if (db) hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(BS), 0, s, P, dz, db);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_relu_bf16(int64_t count, const float *z, uint16_t *a, void *stream) {
+  return nguard([&] {
+    need(count > 0 && z && a);
+    hipLaunchKernelGGL(relu_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, z, a);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_relu_bf16_backward(int64_t count, const uint16_t *a, const float *da, uint16_t *dz,
+                                       void *stream) {
+  return nguard([&] {
+    need(count > 0 && a && da && dz);
+    hipLaunchKernelGGL(relu_back_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, da, dz);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_to_bf16(int64_t count, const float *x, uint16_t *y, void *stream) {
+  return nguard([&] {
+    need(count > 0 && x && y);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, x, y);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_from_bf16(int64_t count, const uint16_t *x, float *y, void *stream) {
+  return nguard([&] {
+    need(count > 0 && x && y);
+    hipLaunchKernelGGL(from_bf16_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, x, y);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_pool2(int64_t planes, int32_t h, int32_t w, const uint16_t *x, uint16_t *y, void *stream) {
+  return nguard([&] {
+    need(planes > 0 && h > 1 && w > 1 && h % 2 == 0 && w % 2 == 0 && x && y);
+    hipLaunchKernelGGL(pool2_kernel, dim3(nb_of(planes * (h / 2) * (w / 2))), dim3(BS), 0, (hipStream_t)stream,
+                       planes, h, w, x, y);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_pool2_backward(int64_t planes, int32_t h, int32_t w, const float *dy, float *dx, void *stream) {
+  return nguard([&] {
+    need(planes > 0 && h > 1 && w > 1 && h % 2 == 0 && w % 2 == 0 && dy && dx);
+    hipLaunchKernelGGL(pool2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h,
+                       w, dy, dx);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_up2(int64_t planes, int32_t h, int32_t w, const uint16_t *x, uint16_t *y, void *stream) {
+  return nguard([&] {
+    need(planes > 0 && h > 0 && w > 0 && x && y);
+    hipLaunchKernelGGL(up2_kernel, dim3(nb_of(planes * 4 * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h, w,
+                       x, y);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_up2_backward(int64_t planes, int32_t h, int32_t w, const float *dy, float *dx, void *stream) {
+  return nguard([&] {
+    need(planes > 0 && h > 0 && w > 0 && dy && dx);
+    hipLaunchKernelGGL(up2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h, w,
+                       dy, dx);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_adam(int64_t count, float *p, float *m, float *v, const float *g, uint16_t *pb, float lr,
+                         float beta1, float beta2, float eps, int32_t t, void *stream) {
+  return nguard([&] {
+    need(count > 0 && p && m && v && g && t >= 1);
+    const float c1 = 1.f - std::pow(beta1, (float)t), c2 = 1.f - std::pow(beta2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, p, m, v, g, pb, lr,
+                       beta1, beta2, eps, c1, c2);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_axpy(int64_t count, float a, const float *x, float *y, void *stream) {
+  return nguard([&] {
+    need(count > 0 && x && y);
+    hipLaunchKernelGGL(axpy_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, x, y);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+int64_t fdtd_nn_mse_work(int64_t count) { return count > 0 ? nb_of(count) : 0; }
+
+fdtd_status fdtd_nn_mse(int64_t count, const float *pred, const float *target, float scale, float *grad,
+                        double *work, double *sum_sq, void *stream) {
+  return nguard([&] {
+    need(count > 0 && pred && target && work && sum_sq);
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = nb_of(count);
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(BS), 0, s, count, pred, target, scale, grad, work);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(BS), 0, s, work, nb, sum_sq);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_gap_linear(int32_t n, int32_t c, int32_t hw, const uint16_t *a, const float *wl, const float *bl,
+                               float *out, void *stream) {
+  return nguard([&] {
+    need(n > 0 && c > 0 && hw > 0 && a && wl && bl && out);
+    hipLaunchKernelGGL(gap_linear_kernel, dim3(n), dim3(BS), 0, (hipStream_t)stream, n, c, hw, a, wl, bl, out);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_gap_linear_backward(int32_t n, int32_t c, int32_t hw, const uint16_t *a, const float *wl,
+                                        const float *dout, float *da, float *dwl, float *dbl, void *stream) {
+  return nguard([&] {
+    need(n > 0 && c > 0 && hw > 0 && a && wl && dout && da && dwl && dbl);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t total = (int64_t)n * c * hw;
+    hipLaunchKernelGGL(gap_linear_back_a_kernel, dim3(nb_of(total)), dim3(BS), 0, s, n, c, hw, dout, wl, da);
+    hipLaunchKernelGGL(gap_linear_back_w_kernel, dim3(c + 1), dim3(BS), 0, s, n, c, hw, a, dout, dwl, dbl);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+const char *fdtd_nn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

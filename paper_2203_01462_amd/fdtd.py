@@ -72,7 +72,13 @@ EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward"
            # include/fdtd_design.h
            "fdtd_filter_create", "fdtd_filter_apply", "fdtd_filter_transpose", "fdtd_filter_destroy",
            "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
-           "fdtd_design_stats", "fdtd_design_last_error"]
+           "fdtd_design_stats", "fdtd_design_last_error",
+           # include/fdtd_nn.h
+           "fdtd_nn_conv3x3", "fdtd_nn_conv3x3_dgrad", "fdtd_nn_wgrad_work", "fdtd_nn_conv3x3_wgrad",
+           "fdtd_nn_relu_bf16", "fdtd_nn_relu_bf16_backward", "fdtd_nn_to_bf16", "fdtd_nn_from_bf16",
+           "fdtd_nn_pool2", "fdtd_nn_pool2_backward", "fdtd_nn_up2", "fdtd_nn_up2_backward", "fdtd_nn_adam",
+           "fdtd_nn_axpy", "fdtd_nn_gap_linear", "fdtd_nn_gap_linear_backward", "fdtd_nn_mse_work", "fdtd_nn_mse",
+           "fdtd_nn_last_error"]
 
 _lib = None
 
@@ -127,6 +133,34 @@ def load_library(path=LIB_PATH):
                "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
                "fdtd_design_stats"):
         getattr(L, fn).restype = C.c_int
+    I32, I64, F = C.c_int32, C.c_int64, C.c_float
+    nn = {
+        "fdtd_nn_conv3x3": [I32, I32, I32, I32, I32, P, P, P, P, P, P],
+        "fdtd_nn_conv3x3_dgrad": [I32, I32, I32, I32, I32, P, P, P, P, P],
+        "fdtd_nn_conv3x3_wgrad": [I32, I32, I32, I32, I32, P, P, P, P, P, P],
+        "fdtd_nn_relu_bf16": [I64, P, P, P],
+        "fdtd_nn_relu_bf16_backward": [I64, P, P, P, P],
+        "fdtd_nn_to_bf16": [I64, P, P, P],
+        "fdtd_nn_from_bf16": [I64, P, P, P],
+        "fdtd_nn_pool2": [I64, I32, I32, P, P, P],
+        "fdtd_nn_pool2_backward": [I64, I32, I32, P, P, P],
+        "fdtd_nn_up2": [I64, I32, I32, P, P, P],
+        "fdtd_nn_up2_backward": [I64, I32, I32, P, P, P],
+        "fdtd_nn_adam": [I64, P, P, P, P, P, F, F, F, F, I32, P],
+        "fdtd_nn_axpy": [I64, F, P, P, P],
+        "fdtd_nn_gap_linear": [I32, I32, I32, P, P, P, P, P],
+        "fdtd_nn_gap_linear_backward": [I32, I32, I32, P, P, P, P, P, P, P],
+        "fdtd_nn_mse": [I64, P, P, F, P, P, P, P],
+    }
+    for fn, a in nn.items():
+        getattr(L, fn).argtypes = a
+        getattr(L, fn).restype = C.c_int
+    L.fdtd_nn_wgrad_work.argtypes = [I32, I32, I32, I32, I32]
+    L.fdtd_nn_wgrad_work.restype = I64
+    L.fdtd_nn_mse_work.argtypes = [I64]
+    L.fdtd_nn_mse_work.restype = I64
+    L.fdtd_nn_last_error.argtypes = []
+    L.fdtd_nn_last_error.restype = C.c_char_p
     for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
                "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_batch_create", "fdtd_batch_set_density",
                "fdtd_batch_forward", "fdtd_batch_adjoint", "fdtd_batch_gradient", "fdtd_batch_info",
