@@ -166,8 +166,49 @@ def c4(count=64, n_steps=5000, seed=0, sides=(128, 256, 512, 1024)):
     return out
 
 
+def c5(n_steps=5000):
+    """Surrogate workload: one 512x512 TMz FP32 instance with the 2048^2
+    workload's physics (m_gamma = 1, 500-1000 nm band, 8 frequencies) and a
+    128x128 design box, the size the surrogate network maps."""
+    return instance2d(512, 1.0, 500e-9, 1000e-9, n_steps, name="tmz2d_512_c5")
+
+
+def _logistic(z):
+    return 0.5 * (1.0 + np.tanh(0.5 * z))
+
+
+def random_designs(count, shape, seed):
+    """`count` seeded design-variable maps in [0, 1] of `shape` (float32), a
+    mix of the kinds an optimizer visits: near-uniform fields with weak
+    structure, smooth fields of random correlation length (2-24 cells) and
+    contrast, and sharpened, nearly binary ones.  Gaussian smoothing of white
+    noise in the Fourier domain, then a logistic map of random slope and
+    offset; one generator draws every number."""
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    ky = np.fft.fftfreq(ny)[:, None]
+    kx = np.fft.fftfreq(nx)[None, :]
+    k2 = ky * ky + kx * kx
+    out = np.empty((count, ny, nx), np.float32)
+    for i in range(count):
+        ell = rng.uniform(2.0, 24.0)
+        noise = rng.standard_normal((ny, nx))
+        f = np.real(np.fft.ifft2(np.fft.fft2(noise) * np.exp(-2.0 * (np.pi * ell) ** 2 * k2)))
+        f -= f.mean()
+        f /= max(f.std(), 1e-12)
+        kind = rng.random()
+        if kind < 0.3:      # near-uniform start region
+            x = 0.5 + rng.uniform(0.0, 0.25) * np.tanh(f) + rng.uniform(-0.2, 0.2)
+        elif kind < 0.75:   # smooth, intermediate contrast
+            x = _logistic(rng.uniform(0.5, 3.0) * f + rng.uniform(-1.5, 1.5))
+        else:               # nearly binary
+            x = _logistic(rng.uniform(6.0, 30.0) * f + rng.uniform(-3.0, 3.0))
+        out[i] = np.clip(x, 0.0, 1.0)
+    return out
+
+
 PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "medium3d": medium3d, "tiny2d": tiny2d,
-           "tiny3d": tiny3d}
+           "tiny3d": tiny3d, "c5": c5}
 
 
 def with_(w, **over):

@@ -121,7 +121,9 @@ __global__ void __launch_bounds__(BS) stage_kernel(const TI *__restrict__ x, TO 
         s += w / (u + alpha);
       }
   const double e = 1.0 / (s * winv[i]) - alpha;
-  y[i] = (TO)(dual ? 1.0 - e : e);
+  // an fW-mean of values in [0,1] lies in [0,1]; clamp off the rounding
+  // (all-void or all-metal neighbourhoods land within an ulp of the bounds)
+  y[i] = (TO)fmin(fmax(dual ? 1.0 - e : e, 0.0), 1.0);
 }
 
 // Transpose of one stage at input x, output y: with e = (dual ? 1-y : y),

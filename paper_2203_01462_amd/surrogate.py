@@ -1,0 +1,453 @@
+"""Surrogate-guided design on the 512x512 TMz workload (128x128 design box).
+
+Pipeline (all device work in the HIP library: FDTD solves, filter, MMA,
+network layers; this module moves tensors and holds the control flow):
+
+1. ``generate``: seeded synthetic design variables -> open-close filter ->
+   batched forward + adjoint FDTD solves (one batch of identical instances,
+   fdtd_batch_*) -> triples (rho_f, log F, dlogF/drho_f).  The network works
+   in log space: F spans orders of magnitude across designs, and the
+   log-derivative S/F has a far more uniform scale than S itself.
+2. ``train``: the U-Net (nn.UNet) regresses normalized log F and the
+   normalized log-derivative map with Adam on random minibatches.
+3. ``guided``: from the current design, ``inner`` MMA steps are taken on the
+   surrogate alone (its gradient corrected by the difference between the
+   exact and the predicted gradient at the last FDTD-checked design), then one
+   forward + adjoint FDTD solve checks the proposal.  A proposal that raises F
+   is accepted; otherwise one exact GCMMA step is taken from the checked
+   design.  Every checked design is added to the training set and the network
+   is tuned on it for a few steps.
+4. ``plain``: the design loop alone (design.optimize at the same filter
+   nonlinearity and physics) as the reference; ``compare`` reports the
+   wall-clock time both take to reach within 1% of the plain run's best F.
+"""
+from __future__ import annotations
+
+import argparse
+import copy
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+import fdtd_workloads as W
+
+from . import design
+from .fdtd import FDTD, Batch
+from .nn import UNet
+
+
+class Dataset:
+    """Training triples on the device: rho [N][s][s] (filtered densities),
+    logF [N], G [N][s][s] = dlogF/drho_f; normalization constants."""
+
+    def __init__(self, side, cap, device):
+        self.rho = torch.empty(cap, side, side, device=device)
+        self.logF = torch.empty(cap, device=device)
+        self.G = torch.empty(cap, side, side, device=device)
+        self.n = 0
+        self.mu, self.sd, self.gsd = 0.0, 1.0, 1.0
+
+    def add(self, rho, F, g):
+        """rho, g: device [s][s] FP32 (g = dF/drho_f); F: host float."""
+        i = self.n
+        if i >= self.rho.shape[0]:
+            raise RuntimeError("dataset capacity exceeded")
+        self.rho[i].copy_(rho)
+        self.logF[i] = math.log(F)
+        self.G[i].copy_(g / F)
+        self.n += 1
+
+    def set_norms(self):
+        lf = self.logF[:self.n]
+        self.mu = float(lf.mean())
+        self.sd = float(lf.std().clamp_min(1e-6))
+        self.gsd = float(self.G[:self.n].pow(2).mean().sqrt().clamp_min(1e-30))
+
+    def batch(self, idx):
+        return (self.rho[idx].contiguous(), ((self.logF[idx] - self.mu) / self.sd).contiguous(),
+                (self.G[idx] / self.gsd).contiguous())
+
+
+def _stream_handle():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def generate(w, count, alpha=1.0, radius=2.5, seed=0, batch=64, data=None, log=None):
+    """Solve forward + adjoint for `count` seeded designs; returns a Dataset.
+    Runs on torch's current stream (must not be the default stream)."""
+    shape = W.design_shape(w)
+    side = shape[0]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    data = Dataset(side, count, dev) if data is None else data
+    filt = design.Filter(shape, radius, torch.float32)
+    nb = min(batch, count)
+    B = Batch([w] * nb, stream=_stream_handle())
+    x = torch.empty(nb, *shape, device=dev)
+    rf = torch.empty(nb, *shape, device=dev)
+    g = torch.empty(nb, *shape, device=dev)
+    done, chunk = 0, 0
+    t0 = time.perf_counter()
+    while done < count:
+        m = min(nb, count - done)
+        x.copy_(torch.from_numpy(W.random_designs(nb, shape, seed * 100003 + chunk)))
+        for k in range(nb):
+            filt.apply(x[k], alpha, out=rf[k])
+            B.set_density(k, rf[k])
+        F = B.forward()
+        B.adjoint()
+        for k in range(m):
+            if not (np.isfinite(F[k]) and F[k] > 0.0):
+                raise RuntimeError(f"non-positive objective {F[k]} for design {done + k}")
+            B.gradient(k, out=g[k])
+            data.add(rf[k], float(F[k]), g[k])
+        done += m
+        chunk += 1
+        if log:
+            log(f"generate: {done}/{count} triples, {time.perf_counter() - t0:.1f} s")
+    B.close()
+    filt.close()
+    torch.cuda.synchronize()
+    return data
+
+
+def view(net, batch):
+    """A U-Net sharing `net`'s parameters with buffers for another batch size."""
+    v = copy.copy(net)
+    v.batch = batch
+    v._alloc(batch)
+    return v
+
+
+def train(net, data, steps, lr=1e-3, lr_min=1e-5, wF=1.0, wS=1.0, seed=0, val=None, log=None, log_every=200):
+    """Adam on random minibatches of data[:n] (val: index tensor held out);
+    cosine learning-rate decay from lr to lr_min."""
+    gen = torch.Generator(device=net.dev).manual_seed(seed)
+    n = data.n
+    pool = torch.arange(n, device=net.dev)
+    if val is not None:
+        mask = torch.ones(n, dtype=torch.bool, device=net.dev)
+        mask[val] = False
+        pool = pool[mask]
+    hist = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = pool[torch.randint(0, pool.numel(), (net.batch,), generator=gen, device=net.dev)]
+        rho, lf, G = data.batch(idx)
+        net.forward(rho)
+        dF, dS = net.loss_grad(lf, G, wF, wS)
+        net.backward(dF, dS)
+        cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(steps, 1)))
+        net.step(cur)
+        if log and (it % log_every == 0 or it == steps - 1):
+            l = net.loss.cpu()
+            lF = float(l[0]) / net.batch
+            lS = float(l[1]) / (net.batch * net.side * net.side)
+            hist.append(dict(step=it, lossF=lF, lossS=lS, t=time.perf_counter() - t0))
+            log(f"train: step {it} lossF {lF:.4f} lossS {lS:.4f} lr {cur:.2e} {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    return hist
+
+
+def evaluate_net(net, data, idx):
+    """Held-out metrics: RMSE of normalized log F, R^2 of log F, mean cosine
+    similarity between predicted and exact log-derivative maps."""
+    v = view(net, 1)
+    errs, lfs, coss = [], [], []
+    for i in idx.tolist():
+        rho, lf, G = data.batch(torch.tensor([i], device=net.dev))
+        Fh, Sh = v.forward(rho)
+        errs.append(float(Fh[0]) - float(lf[0]))
+        lfs.append(float(lf[0]))
+        a, b = Sh.reshape(-1).double(), G.reshape(-1).double()
+        coss.append(float(a @ b / (a.norm() * b.norm() + 1e-30)))
+    errs, lfs = np.array(errs), np.array(lfs)
+    r2 = 1.0 - (errs ** 2).sum() / max(((lfs - lfs.mean()) ** 2).sum(), 1e-30)
+    return dict(rmse_logF_norm=float(np.sqrt((errs ** 2).mean())), r2_logF=float(r2),
+                grad_cos_mean=float(np.mean(coss)), grad_cos_median=float(np.median(coss)), n=len(idx))
+
+
+class _Exact:
+    """Forward + adjoint FDTD on the filtered density of x."""
+
+    def __init__(self, w, alpha, radius):
+        shape = W.design_shape(w)
+        self.sol = FDTD(w, stream=_stream_handle())
+        self.filt = design.Filter(shape, radius, torch.float32)
+        self.alpha = alpha
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.rf = torch.empty(shape, device=dev)
+        self.gt = torch.empty(shape, device=dev)
+        self.gx = torch.empty(shape, device=dev)
+        self.solves = 0
+
+    def __call__(self, x, grad=True):
+        self.filt.apply(x, self.alpha, out=self.rf)
+        self.sol.set_density(self.rf)
+        F = self.sol.forward()
+        self.solves += 1
+        if grad:
+            self.sol.adjoint()
+            self.sol.gradient(out=self.gt)
+            self.filt.transpose(self.gt, out=self.gx)
+            self.solves += 1
+        return F
+
+    def gradient_only(self):
+        """Adjoint and gradient for the density of the last forward solve."""
+        self.sol.adjoint()
+        self.sol.gradient(out=self.gt)
+        self.filt.transpose(self.gt, out=self.gx)
+        self.solves += 1
+
+    def close(self):
+        self.sol.close()
+        self.filt.close()
+
+
+def plain(w, alpha=1.0, radius=2.5, max_iter=60, max_inner=40):
+    """The design loop alone at one level; returns [(t, F)] per outer iteration."""
+    trace = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def cb(h):
+        trace.append((time.perf_counter() - t0, h["F"]))
+
+    res = design.optimize(w, alphas=(alpha,), gamma_levels=(w["gamma_mult"],), max_iter=max_iter, zeta_min=0.0,
+                          radius=radius, max_inner=max_inner, callback=cb)
+    return trace, res
+
+
+def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=10, move=0.1, tune_steps=2, tune_batch=8,
+           tune_lr=2e-4, max_inner=40, log=None):
+    """Surrogate-guided loop; returns [(t, F of the current design)] per FDTD
+    check and counters.
+
+    A proposal: `inner` MMA steps (move limit `move`) on the surrogate, whose
+    log F and log-derivative are shifted by the exact-minus-predicted
+    difference at the current design (so its first step is the exact MMA
+    step); the iterate with the best shifted prediction is checked."""
+    shape = W.design_shape(w)
+    dev = net.dev
+    nd = int(np.prod(shape))
+    net1 = view(net, 1)
+    tnet = view(net, tune_batch) if tune_steps else None
+    if tnet is not None:
+        tnet.t = net.t
+    ex = _Exact(w, alpha, radius)
+    mma = design.MMA(nd, torch.float32)
+    x = torch.full(shape, 0.5, device=dev)
+    xs = torch.empty_like(x)
+    xbest = torch.empty_like(x)
+    xnew = torch.empty_like(x)
+    rs = torch.empty_like(x)
+    gs = torch.empty_like(x)
+    filt = design.Filter(shape, radius, torch.float32)
+    trace = []
+    clock = dict(surrogate=0.0, check=0.0, fallback=0.0, tune=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = ex(x)
+    gx = ex.gx.clone()
+    rf = ex.rf.clone()
+    gt = ex.gt.clone()
+    trace.append((time.perf_counter() - t0, F))
+    stats = dict(accepted=0, fallback=0, checks=0, best_step=[])
+
+    def predict(xv):
+        filt.apply(xv, alpha, out=rs)
+        Fh, Sh = net1.forward(rs.reshape(1, *shape))
+        return float(Fh[0]) * data.sd + data.mu, Sh[0] * data.gsd
+
+    while stats["checks"] < checks:
+        ta = time.perf_counter()
+        lf0, S0 = predict(x)
+        dlf = math.log(F) - lf0          # value shift
+        corr = gt / F - S0               # log-derivative shift
+        xs.copy_(x)
+        ms = design.MMA(nd, torch.float32, move=move)
+        best, kbest = -math.inf, 0
+        for k in range(inner + 1):
+            lf, S = predict(xs) if k else (lf0, S0)
+            val = lf + dlf
+            if k and val > best:
+                best, kbest = val, k
+                xbest.copy_(xs)
+            if k == inner:
+                break
+            torch.add(S, corr, out=gs)
+            filt.transpose(gs, out=xnew)              # dlogF/dx
+            xnew.neg_()
+            r0 = ms.begin(xs, -val, xnew)
+            ms.solve(r0, xnew)
+            ms.accept(xnew)
+            xs.copy_(xnew)
+        ms.close()
+        stats["best_step"].append(kbest)
+        tb = time.perf_counter()
+        clock["surrogate"] += tb - ta
+        Fs = ex(xbest)
+        stats["checks"] += 1
+        data.add(ex.rf, Fs, ex.gt)
+        tc = time.perf_counter()
+        clock["check"] += tc - tb
+        if Fs > F:
+            stats["accepted"] += 1
+            # record the step in the exact MMA's iterate history (its
+            # asymptotes adapt to the sequence of accepted designs)
+            mma.begin(x, -1.0, gx * (-1.0 / F))
+            mma.accept(xbest)
+            x.copy_(xbest)
+            F = Fs
+            gx.copy_(ex.gx)
+            rf.copy_(ex.rf)
+            gt.copy_(ex.gt)
+        else:
+            # one exact GCMMA step from x (as in the plain loop)
+            stats["fallback"] += 1
+            rho_m = mma.begin(x, -1.0, gx * (-1.0 / F))
+            Fn = None
+            for _ in range(max_inner):
+                approx, dist = mma.solve(rho_m, xnew)
+                Fn = ex(xnew, grad=False)
+                f0n = -Fn / F
+                if f0n <= approx + 1e-12 * max(1.0, abs(approx)):
+                    break
+                rho_m = min(1.1 * (rho_m + (f0n - approx) / max(dist, 1e-300)), 10.0 * rho_m)
+            if Fn is not None and Fn > F:
+                mma.accept(xnew)
+                x.copy_(xnew)
+                F = Fn
+                ex.gradient_only()  # the forward solve at xnew is still in the context
+                gx.copy_(ex.gx)
+                rf.copy_(ex.rf)
+                gt.copy_(ex.gt)
+                data.add(ex.rf, F, ex.gt)
+        td = time.perf_counter()
+        clock["fallback"] += td - tc
+        if tnet is not None:
+            _tune(tnet, data, tune_steps, tune_lr)
+        clock["tune"] += time.perf_counter() - td
+        trace.append((time.perf_counter() - t0, F))
+        if log:
+            log(f"guided: check {stats['checks']} F {F:.6g} proposal {Fs:.6g} (step {kbest}) "
+                f"t {trace[-1][0]:.2f} s")
+    torch.cuda.synchronize()
+    stats["solves"] = ex.solves
+    stats["clock"] = clock
+    ex.close()
+    mma.close()
+    filt.close()
+    return trace, stats
+
+
+def _tune(net, data, steps, lr):
+    """A few Adam steps on minibatches holding the newest triple (`net` is a
+    view sharing the trained parameters and Adam state)."""
+    n = data.n
+    for _ in range(steps):
+        idx = torch.randint(0, n, (net.batch,), device=net.dev)
+        idx[0] = n - 1
+        rho, lf, G = data.batch(idx)
+        net.forward(rho)
+        dF, dS = net.loss_grad(lf, G)
+        net.backward(dF, dS)
+        net.step(lr)
+
+
+def time_to(trace, target):
+    for t, F in trace:
+        if F >= target:
+            return t
+    return None
+
+
+def _from_first(trace):
+    """Times relative to the first point (the evaluation of the start design),
+    so that context set-up is not counted for either loop."""
+    t0 = trace[0][0]
+    return [(t - t0, F) for t, F in trace]
+
+
+def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60, checks=30, inner=10, seed=0,
+            n_steps=5000, w=None, settings=((0.1, 2),), log=print):
+    """Plain loop vs surrogate-guided loop from the same start design; one
+    guided run per (move limit, tuning steps) in `settings`."""
+    w = W.c5(n_steps) if w is None else w
+    out = dict(workload=w["name"], samples=samples, train_steps=train_steps, batch=batch, alpha=alpha,
+               inner=inner, n_steps=n_steps)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t = time.perf_counter()
+        data = Dataset(W.design_shape(w)[0], samples + 4 * checks + 8, torch.device("cuda"))
+        generate(w, samples, alpha=alpha, seed=seed, data=data, log=log)
+        out["generate_s"] = time.perf_counter() - t
+        data.set_norms()
+        nval = max(samples // 20, 1)
+        val = torch.arange(samples - nval, samples, device="cuda")
+        net = UNet(W.design_shape(w)[0], batch, seed=seed, stream=None)
+        t = time.perf_counter()
+        out["train_hist"] = train(net, data, train_steps, val=val, log=log)
+        out["train_s"] = time.perf_counter() - t
+        out["val"] = evaluate_net(net, data, val)
+        log(f"validation: {out['val']}")
+        ptrace, pres = plain(w, alpha=alpha, max_iter=plain_iters)
+        ptrace = _from_first(ptrace)
+        Fbest = max(F for _, F in ptrace)
+        target = 0.99 * Fbest
+        log(f"plain: best F {Fbest:.6g} after {len(ptrace) - 1} iterations, {ptrace[-1][0]:.2f} s")
+        out.update(plain_trace=ptrace, plain_best=Fbest, target=target, plain_time_to_target=time_to(ptrace, target),
+                   plain_iters_to_target=next(i for i, (_, F) in enumerate(ptrace) if F >= target))
+        # every setting starts from the same trained network and dataset
+        saved = (net.p.clone(), net.m.clone(), net.v.clone(), net.t, data.n)
+        runs = []
+        for mv, tune in settings:
+            net.p.copy_(saved[0])
+            net.m.copy_(saved[1])
+            net.v.copy_(saved[2])
+            net.t, data.n = saved[3], saved[4]
+            net.load(net.p)
+            gtrace, gstats = guided(w, net, data, alpha=alpha, checks=checks, inner=inner, move=mv, tune_steps=tune,
+                                    log=log)
+            gtrace = _from_first(gtrace)
+            hit = [i for i, (_, F) in enumerate(gtrace) if F >= target]
+            runs.append(dict(move=mv, tune_steps=tune, trace=gtrace, stats=gstats,
+                             time_to_target=time_to(gtrace, target), checks_to_target=hit[0] if hit else None,
+                             best=max(F for _, F in gtrace)))
+            log(f"guided move {mv} tune {tune}: time to target {runs[-1]['time_to_target']}, "
+                f"plain {out['plain_time_to_target']}")
+    torch.cuda.synchronize()
+    out["guided"] = runs
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--samples", type=int, default=4096)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--plain-iters", type=int, default=60)
+    ap.add_argument("--checks", type=int, default=30)
+    ap.add_argument("--inner", type=int, default=10)
+    ap.add_argument("--n-steps", type=int, default=5000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--settings", default="0.1:2", help="comma-separated move:tune_steps pairs")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    settings = [(float(m), int(t)) for m, t in (p.split(":") for p in a.settings.split(","))]
+    res = compare(a.samples, a.train_steps, a.batch, a.alpha, a.plain_iters, a.checks, a.inner, a.seed, a.n_steps,
+                  settings=settings, log=lambda m: print(m, flush=True))
+    summary = {k: v for k, v in res.items() if not k.endswith("_trace") and k not in ("train_hist", "guided")}
+    summary["guided"] = [{k: v for k, v in r.items() if k != "trace"} for r in res["guided"]]
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f)
+
+
+if __name__ == "__main__":
+    main()
