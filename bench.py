@@ -108,12 +108,65 @@ def cpu_baseline(w, steps):
                       f"FP64, {dt:.1f} s wall"}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_unet(args, batch=32, side=128, inner=20):
+    """Training steps of the surrogate U-Net (forward, backward, Adam) on
+    seeded synthetic 128x128 densities and targets; one bench step = `inner`
+    training steps.  Roofline: the convolutions' FLOPs (forward, data and
+    weight gradients: 3x the forward) over the wall time of the whole step,
+    against the dense BF16 matrix-core peak."""
+    import torch
+    from paper_2203_01462_amd.nn import UNet, layer_plan
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    g = torch.Generator().manual_seed(0)
+    with torch.cuda.stream(stream):
+        net = UNet(side, batch, seed=0)
+        rho = torch.rand(batch, side, side, generator=g).cuda()
+        Ft = torch.randn(batch, generator=g).cuda()
+        St = torch.randn(batch, side, side, generator=g).cuda()
+
+        def step():
+            for _ in range(inner):
+                net.forward(rho)
+                dF, dS = net.loss_grad(Ft, St)
+                net.backward(dF, dS)
+                net.step(1e-4)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    per_train_step = wall / (args.steps * inner)
+    fwd_flops = sum(2 * ci * 9 * co * (side >> lvl) ** 2 for ci, co, lvl in layer_plan()) * batch
+    tflops = 3 * fwd_flops / per_train_step / 1e12
+    out = {"metric": "surrogate U-Net training samples/s (BF16 matrix cores)", "value": round(batch / per_train_step, 1),
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"unet_{side}_b{batch}", "channels": [32, 64, 128, 256], "batch": batch,
+                      "input": [side, side], "train_steps_per_step": inner, "parallelism": "single GPU"},
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "whole training step (convolution FLOPs / step time)",
+                        "ms_per_train_step": round(per_train_step * 1e3, 3)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "unet"],
+                    help="unet: training steps of the surrogate network (BF16 matrix cores) instead of FDTD")
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
     ap.add_argument("--ckpt-every", type=int, default=0,
@@ -139,6 +192,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read_per_dispatch": src.numel() * 4,
                           "copy_probe_bytes_written_per_dispatch": dst.numel() * 4}), flush=True)
+        return
+    if args.workload == "unet":
+        bench_unet(args)
         return
     base = W.PRESETS[args.workload]()
     if args.n_steps:

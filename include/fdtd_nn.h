@@ -23,7 +23,8 @@
  *
  * Layout: activations channel-major [C][N][H][W] (a channel concatenation is
  * two writes into one buffer; for one image this is NCHW); weights
- * [cout][cin][3][3].  BF16 data
+ * [cout][3][3][cin] (eight input channels of one tap are one 16-byte load).
+ * BF16 data
  * are passed as uint16_t (bits of the IEEE binary32 high half, rounded to
  * nearest even).  All pointers are device pointers; work runs in order on
  * `stream` (NULL: the default stream).  Functions return an fdtd_status and
@@ -42,19 +43,19 @@
 extern "C" {
 #endif
 
-/* z[co][n][y][x] = b[co] + sum_{ci,ky,kx} w[co][ci][ky][kx] x[ci][n][y+ky-1][x+kx-1]
+/* z[co][n][y][x] = b[co] + sum_{ci,ky,kx} w[co][ky][kx][ci] x[ci][n][y+ky-1][x+kx-1]
  * (x outside the image = 0; bias may be NULL).  Writes z (FP32) if z is not
  * NULL and a = bf16(max(z, 0)) if a is not NULL (at least one of them).
  * n <= 65535. */
 fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
                             const uint16_t *wt, const float *bias, float *z, uint16_t *a, void *stream);
 
-/* dx[ci][n][y][x] = sum_{co,ky,kx} w[co][ci][ky][kx] dz[co][n][y-ky+1][x-kx+1];
+/* dx[ci][n][y][x] = sum_{co,ky,kx} w[co][ky][kx][ci] dz[co][n][y-ky+1][x-kx+1];
  * wrot: caller workspace of cout*cin*9 BF16 values. */
 fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
                                   const uint16_t *wt, uint16_t *wrot, float *dx, void *stream);
 
-/* dw[co][ci][ky][kx] = sum_{n,y,x} dz[co][n][y][x] x[ci][n][y+ky-1][x+kx-1];
+/* dw[co][ky][kx][ci] = sum_{n,y,x} dz[co][n][y][x] x[ci][n][y+ky-1][x+kx-1];
  * db[co] = sum_{n,y,x} dz; work: caller workspace of fdtd_nn_wgrad_work(...)
  * floats. */
 int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w);

@@ -21,6 +21,7 @@ namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int BS = 256;
 constexpr int TM = 64, TN = 64, TK = 16, PAD = 4;
@@ -61,7 +62,7 @@ __device__ __forceinline__ void mfma_step(const uint16_t (*As)[TK + PAD], const 
   }
 }
 
-// z[co][n][p] = bias[co] + sum_k w[co][k] xhat[k][n][p], k = (ci, ky, kx),
+// z[co][n][p] = bias[co] + sum_k w[co][k] xhat[k][n][p], k = (ky, kx, ci),
 // xhat = the zero-padded 3x3 window of x[ci][n].  Writes z (FP32) and/or
 // a = bf16(max(z, 0)).  grid (ceil(HW/64), ceil(cout/64), n).
 __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, int w, const uint16_t *__restrict__ x,
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, 
     }
     {
       const int kk = t >> 4, c = (t & 15) * 4, k = k0 + kk;
-      const int ci = k / 9, r9 = k - ci * 9, ky = r9 / 3, kx = r9 - ky * 3;
+      const int tap = k / cin, ci = k - tap * cin, ky = tap / 3, kx = tap - ky * 3;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = p0 + c + j;
@@ -116,6 +117,114 @@ __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, 
         if (a) a[o] = f2bf(fmaxf(v, 0.f));
       }
     }
+}
+
+// The same convolution, LDS-tiled for cin % 32 == 0 and h, w multiples of 16,
+// on v_mfma_f32_16x16x32_bf16.  A workgroup owns 16*MT output channels x a
+// 16 x 16 pixel tile of one image; per chunk of 32 input channels it stages
+// the 18 x 18 halo tile channel-last in LDS (eight channels of one pixel are
+// one 16-byte LDS read) and the weights of all nine taps, then each
+// wavefront (four pixel rows) runs nine taps x MT x 4 matrix instructions.
+// grid ((h/16) * (w/16), ceil(cout / (16*MT)), n).
+constexpr int CC = 32;                  // input channels per chunk
+constexpr int XST = 40;                 // LDS stride between staged pixels (80 B: conflict-free 16 B reads)
+constexpr int WST = 40;                 // LDS stride between staged (tap, co) weight rows
+constexpr int TT = 16, HT = TT + 2;     // output tile side, halo tile side
+
+template <int MT>
+__global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, int h, int w,
+                                                          const uint16_t *__restrict__ x,
+                                                          const uint16_t *__restrict__ wt,
+                                                          const float *__restrict__ bias, float *__restrict__ z,
+                                                          uint16_t *__restrict__ a) {
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[HT * HT * XST];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * 16 * MT * WST];
+  const int n = blockIdx.z, nimg = gridDim.z, HW = h * w;
+  const int tilesx = w / TT;
+  const int y0 = (blockIdx.x / tilesx) * TT, x0 = (blockIdx.x % tilesx) * TT;
+  const int co0 = blockIdx.y * 16 * MT;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
+  const size_t cs = (size_t)nimg * HW;
+  const uint16_t *xn = x + (size_t)n * HW;
+  f4 acc[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < cin; c0 += CC) {
+    for (int v = t; v < 9 * 16 * MT * 4; v += BS) {
+      const int part = v & 3, row = v >> 2;
+      const int tap = row / (16 * MT), col = row - tap * (16 * MT), co = co0 + col;
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (co < cout) val = *(const uint4 *)(wt + ((size_t)co * 9 + tap) * cin + c0 + 8 * part);
+      *(uint4 *)(Ws + row * WST + 8 * part) = val;
+    }
+    // one halo pixel per thread: its 32 channels, packed into 16-byte LDS writes
+    for (int pos = t; pos < HT * HT; pos += BS) {
+      const int r = pos / HT, q = pos - r * HT;
+      const int iy = y0 - 1 + r, ix = x0 - 1 + q;
+      const bool ok = iy >= 0 && iy < h && ix >= 0 && ix < w;
+      const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
+#pragma unroll
+      for (int c8 = 0; c8 < CC; c8 += 8) {
+        uint32_t pk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t lo = ok ? src[(size_t)(c8 + 2 * j) * cs] : 0u;
+          const uint32_t hi = ok ? src[(size_t)(c8 + 2 * j + 1) * cs] : 0u;
+          pk[j] = lo | (hi << 16);
+        }
+        *(uint4 *)(Xs + pos * XST + c8) = uint4{pk[0], pk[1], pk[2], pk[3]};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap - 3 * ky;
+      bf8 av[MT], bv[4];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) av[m] = *(const bf8 *)(Ws + (tap * 16 * MT + 16 * m + l16) * WST + 8 * kq);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[s] = *(const bf8 *)(Xs + ((4 * wave + s + ky) * HT + l16 + kx) * XST + 8 * kq);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[s], acc[m][s], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = co0 + 16 * m + 4 * kq + j;
+        if (co < cout) {
+          const float v = acc[m][s][j] + (bias ? bias[co] : 0.f);
+          const size_t o = (size_t)co * cs + (size_t)n * HW + (size_t)(y0 + 4 * wave + s) * w + x0 + l16;
+          if (z) z[o] = v;
+          if (a) a[o] = f2bf(fmaxf(v, 0.f));
+        }
+      }
+}
+
+// One forward convolution launch: the LDS-tiled kernel where the shape and
+// the weight alignment allow it, else the generic one.
+void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, const uint16_t *wt, const float *bias,
+                 float *z, uint16_t *a, hipStream_t s) {
+  if (cin % CC == 0 && h % TT == 0 && w % TT == 0 && ((uintptr_t)wt & 15) == 0) {
+    if (cout <= 32) {
+      const dim3 g((h / TT) * (w / TT), (cout + 31) / 32, n);
+      hipLaunchKernelGGL(conv_fwd_mfma_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+    } else {
+      const dim3 g((h / TT) * (w / TT), (cout + 63) / 64, n);
+      hipLaunchKernelGGL(conv_fwd_mfma_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+    }
+    return;
+  }
+  const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
+  hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
 }
 
 // Partial weight gradients over one range of pixels q = (n, p) of the batch:
@@ -155,7 +264,7 @@ __global__ void __launch_bounds__(BS) conv_wgrad_kernel(int nimg, int cin, int c
         const int k = k0 + c + j;
         uint16_t v = 0;
         if (qok && k < K) {
-          const int ci = k / 9, r9 = k - ci * 9, ky = r9 / 3, kx = r9 - ky * 3;
+          const int tap = k / cin, ci = k - tap * cin, ky = tap / 3, kx = tap - ky * 3;
           const int iy = y + ky - 1, ix = xx + kx - 1;
           if (iy >= 0 && iy < h && ix >= 0 && ix < w) v = xn[(size_t)ci * P + iy * w + ix];
         }
@@ -175,35 +284,178 @@ __global__ void __launch_bounds__(BS) conv_wgrad_kernel(int nimg, int cin, int c
     }
 }
 
-// dw[i] = sum over splits (fixed order).
+// Weight gradient, LDS-tiled for cin % 32 == 0, h % 8 == 0, w % 16 == 0 and
+// 16-byte aligned x and dz:
+// part[split][co][tap][ci] = sum over the split's pixel tiles of
+// dz[co][q] x[ci][q shifted by tap].  A workgroup owns 64 output channels x 32
+// input channels x 9 taps and walks 8 x 16 pixel tiles; the reduction runs
+// over pixels (32 per matrix instruction), so both operands are staged
+// pixel-contiguous: dz rows as they are, and the input tile three times,
+// shifted by kx = 0, 1, 2, so every 16-byte fragment read stays aligned.
+// Wavefront w owns output channels 16w..16w+15 (2 x 9 accumulator tiles).
+// grid (ceil(cout/64), cin/32, splits).
+constexpr int GY = 8, GX = 16, GP = GY * GX;  // pixel tile
+constexpr int DST = GP + 8;                   // LDS stride of staged dz rows
+constexpr int XCI = (GY + 2) * GX + 8;        // LDS stride per input channel of a shifted copy
+
+__global__ void __launch_bounds__(BS) conv_wgrad_mfma_kernel(int nimg, int cin, int cout, int h, int w,
+                                                            const uint16_t *__restrict__ x,
+                                                            const uint16_t *__restrict__ dz,
+                                                            float *__restrict__ part, int tiles_per_split) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ds[64 * DST];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[3 * 32 * XCI];
+  const int HW = h * w;
+  const size_t P = (size_t)nimg * HW;
+  const int co0 = blockIdx.x * 64, ci0 = blockIdx.y * 32, split = blockIdx.z;
+  const int tx_n = w / GX, tiles_img = (h / GY) * tx_n, tiles = nimg * tiles_img;
+  const int T0 = split * tiles_per_split, T1 = min(tiles, T0 + tiles_per_split);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
+  f4 acc[2][9];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) acc[nt][tp] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int T = T0; T < T1; ++T) {
+    const int n = T / tiles_img, rem = T - n * tiles_img;
+    const int y0 = (rem / tx_n) * GY, x0 = (rem % tx_n) * GX;
+    // dz rows: 64 channels x 8 rows x 16 pixels as 16-byte vectors
+    for (int v = t; v < 64 * GY * 2; v += BS) {
+      const int half = v & 1, r = (v >> 1) & (GY - 1), c = v >> 4, co = co0 + c;
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (co < cout) val = *(const uint4 *)(dz + (size_t)co * P + (size_t)n * HW + (size_t)(y0 + r) * w + x0 + 8 * half);
+      *(uint4 *)(Ds + c * DST + r * GX + 8 * half) = val;
+    }
+    // input halo rows y0-1 .. y0+8 (one per thread and channel): the 16
+    // interior pixels as two 16-byte loads plus the two halo pixels, stored as
+    // three copies shifted by kx (copy kx, pixel q = input column x0 - 1 + q + kx)
+    for (int rr = t; rr < 32 * (GY + 2); rr += BS) {
+      const int c = rr / (GY + 2), r = rr - c * (GY + 2);
+      const int iy = y0 - 1 + r;
+      uint32_t W[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}, hl = 0u, hr = 0u;
+      if (iy >= 0 && iy < h) {
+        const uint16_t *row = x + (size_t)(ci0 + c) * P + (size_t)n * HW + (size_t)iy * w;
+        const uint4 a0 = *(const uint4 *)(row + x0), a1 = *(const uint4 *)(row + x0 + 8);
+        W[0] = a0.x; W[1] = a0.y; W[2] = a0.z; W[3] = a0.w;
+        W[4] = a1.x; W[5] = a1.y; W[6] = a1.z; W[7] = a1.w;
+        if (x0 > 0) hl = row[x0 - 1];
+        if (x0 + GX < w) hr = row[x0 + GX];
+      }
+      uint32_t S0[8], S2[8];
+      S0[0] = hl | (W[0] << 16);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) S0[k] = (W[k - 1] >> 16) | (W[k] << 16);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) S2[k] = (W[k] >> 16) | (W[k + 1] << 16);
+      S2[7] = (W[7] >> 16) | (hr << 16);
+      uint16_t *d0 = Xs + (0 * 32 + c) * XCI + r * GX;
+      uint16_t *d1 = Xs + (1 * 32 + c) * XCI + r * GX;
+      uint16_t *d2 = Xs + (2 * 32 + c) * XCI + r * GX;
+      *(uint4 *)d0 = uint4{S0[0], S0[1], S0[2], S0[3]};
+      *(uint4 *)(d0 + 8) = uint4{S0[4], S0[5], S0[6], S0[7]};
+      *(uint4 *)d1 = uint4{W[0], W[1], W[2], W[3]};
+      *(uint4 *)(d1 + 8) = uint4{W[4], W[5], W[6], W[7]};
+      *(uint4 *)d2 = uint4{S2[0], S2[1], S2[2], S2[3]};
+      *(uint4 *)(d2 + 8) = uint4{S2[4], S2[5], S2[6], S2[7]};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GP / 32; ++ks) {
+      const int py = 2 * ks + (kq >> 1), px = 8 * (kq & 1);
+      const bf8 av = *(const bf8 *)(Ds + (16 * wave + l16) * DST + 32 * ks + 8 * kq);
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) {
+        const int ky = tp / 3, kx = tp - 3 * ky;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const bf8 bv = *(const bf8 *)(Xs + (kx * 32 + 16 * nt + l16) * XCI + (py + ky) * GX + px);
+          acc[nt][tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt][tp], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = co0 + 16 * wave + 4 * kq + j, ci = ci0 + 16 * nt + l16;
+        if (co < cout) part[(((size_t)split * cout + co) * 9 + tp) * cin + ci] = acc[nt][tp][j];
+      }
+}
+
+// Split plan of the weight gradient: which kernel, how many partial sums,
+// pixels (generic) or pixel tiles (tiled) per split.
+struct WgradPlan {
+  bool tiled;
+  int splits, chunk;
+};
+
+// About 768 workgroups in flight (three per CU), at least two pixel tiles
+// per tiled workgroup so the partial sums stay few.
+WgradPlan wgrad_plan(int n, int cin, int cout, int h, int w) {
+  WgradPlan pl{};
+  if (cin % 32 == 0 && h % GY == 0 && w % GX == 0) {
+    const int groups = ((cout + 63) / 64) * (cin / 32);
+    const int tiles = n * (h / GY) * (w / GX);
+    const int want = std::max(1, (768 + groups - 1) / groups);
+    const int per = std::max(std::min(2, tiles), (tiles + want - 1) / want);
+    pl.tiled = true;
+    pl.chunk = per;
+    pl.splits = (tiles + per - 1) / per;
+    return pl;
+  }
+  const int64_t P = (int64_t)n * h * w;
+  const int64_t groups = (int64_t)((cin * 9 + TN - 1) / TN) * ((cout + TM - 1) / TM);
+  const int64_t want = std::max<int64_t>(1, (768 + groups - 1) / groups);
+  pl.tiled = false;
+  pl.splits = (int)std::min<int64_t>(want, std::max<int64_t>(1, (P + 255) / 256));
+  int64_t chunk = (P + pl.splits - 1) / pl.splits;
+  chunk = (chunk + TK - 1) / TK * TK;
+  pl.chunk = (int)chunk;
+  pl.splits = (int)((P + chunk - 1) / chunk);
+  return pl;
+}
+
+// Pixel ranges of the bias-gradient reduction.
+int64_t bias_ranges(int64_t P) { return std::min<int64_t>(64, std::max<int64_t>(1, (P + 16383) / 16384)); }
+
+// dw[i] = sum over splits, in split order (the unrolled loads are issued
+// ahead; the additions keep their order).
 __global__ void __launch_bounds__(BS) split_sum_kernel(const float *__restrict__ part, int splits, int64_t m,
                                                       float *__restrict__ dw) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= m) return;
   float s = 0.f;
+#pragma unroll 8
   for (int k = 0; k < splits; ++k) s += part[(size_t)k * m + i];
   dw[i] = s;
 }
 
-// db[co] = sum_q dz[co][q]; one workgroup per channel.
-__global__ void __launch_bounds__(BS) bias_grad_kernel(int64_t P, const uint16_t *__restrict__ dz,
-                                                      float *__restrict__ db) {
+// Partial bias gradients: part[b][co] = sum of dz[co][q] over pixel range b
+// (FP64 within the range).  grid (cout, ranges).
+__global__ void __launch_bounds__(BS) bias_grad_kernel(int64_t P, int64_t chunk, const uint16_t *__restrict__ dz,
+                                                      float *__restrict__ part) {
   __shared__ double lds[BS / 64];
-  const int co = blockIdx.x;
+  const int co = blockIdx.x, b = blockIdx.y;
+  const int64_t q0 = (int64_t)b * chunk, q1 = min(P, q0 + chunk);
+  const uint16_t *row = dz + (size_t)co * P;
   double v = 0;
-  for (int64_t q = threadIdx.x; q < P; q += BS) v += bf2f(dz[(size_t)co * P + q]);
+#pragma unroll 8
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += BS) v += bf2f(row[q]);
   const double s = block_sum(v, lds);
-  if (threadIdx.x == 0) db[co] = (float)s;
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + co] = (float)s;
 }
 
-// wrot[ci][co][ky][kx] = w[co][ci][2-ky][2-kx]: the data gradient is the
+// wrot[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]: the data gradient is the
 // forward convolution of dz with these weights.
 __global__ void __launch_bounds__(BS) rot_kernel(int cin, int cout, const uint16_t *__restrict__ w,
                                                 uint16_t *__restrict__ wrot) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= (int64_t)cin * cout * 9) return;
-  const int r = (int)(i % 9), ci = (int)((i / 9) % cin), co = (int)(i / (9 * (int64_t)cin));
-  wrot[((size_t)ci * cout + co) * 9 + (8 - r)] = w[i];
+  const int ci = (int)(i % cin), tap = (int)((i / cin) % 9), co = (int)(i / (9 * (int64_t)cin));
+  wrot[((size_t)ci * 9 + (8 - tap)) * cout + co] = w[i];
 }
 
 __global__ void __launch_bounds__(BS) relu_kernel(int64_t n, const float *__restrict__ z, uint16_t *__restrict__ a) {
@@ -380,10 +632,6 @@ void need(bool ok) {
   if (!ok) throw Error{FDTD_EINVAL, "invalid sizes or missing pointer"};
 }
 
-int wgrad_splits(int n, int h, int w) {
-  const int64_t P = (int64_t)n * h * w;
-  return (int)std::min<int64_t>(64, std::max<int64_t>(1, (P + 4095) / 4096));
-}
 
 }  // namespace
 
@@ -393,8 +641,7 @@ fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int
                             const uint16_t *wt, const float *bias, float *z, uint16_t *a, void *stream) {
   return nguard([&] {
     need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && wt && (z || a));
-    const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
-    hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, (hipStream_t)stream, cin, cout, h, w, x, wt, bias, z, a);
+    launch_conv(n, cin, cout, h, w, x, wt, bias, z, a, (hipStream_t)stream);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -405,15 +652,15 @@ fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t 
     need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && dx);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
-    const dim3 g((h * w + TN - 1) / TN, (cin + TM - 1) / TM, n);
-    hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, s, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr);
+    launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr, s);
     FDTD_HIP(hipGetLastError());
   });
 }
 
 int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w) {
   if (n <= 0 || cin <= 0 || cout <= 0 || h <= 0 || w <= 0) return 0;
-  return (int64_t)wgrad_splits(n, h, w) * cout * cin * 9;
+  const int64_t P = (int64_t)n * h * w;
+  return (int64_t)wgrad_plan(n, cin, cout, h, w).splits * cout * cin * 9 + bias_ranges(P) * cout;
 }
 
 fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
@@ -421,15 +668,29 @@ fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t 
   return nguard([&] {
     need(n > 0 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && dz && dw && work);
     hipStream_t s = (hipStream_t)stream;
-    const int K = cin * 9, S = wgrad_splits(n, h, w);
+    const int K = cin * 9;
     const int64_t P = (int64_t)n * h * w;
-    int chunk = (int)((P + S - 1) / S);
-    chunk = (chunk + TK - 1) / TK * TK;
-    const dim3 g((K + TN - 1) / TN, (cout + TM - 1) / TM, S);
-    hipLaunchKernelGGL(conv_wgrad_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, chunk);
+    const WgradPlan pl = wgrad_plan(n, cin, cout, h, w);
     const int64_t m = (int64_t)cout * K;
+    int S = pl.splits;
+    if (pl.tiled && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0) {
+      const dim3 g((cout + 63) / 64, cin / 32, pl.splits);
+      hipLaunchKernelGGL(conv_wgrad_mfma_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, pl.chunk);
+    } else {
+      // generic kernel, at most as many pixel ranges as the plan has partial sums
+      int64_t chunk = (P + pl.splits - 1) / pl.splits;
+      chunk = (chunk + TK - 1) / TK * TK;
+      S = (int)((P + chunk - 1) / chunk);
+      const dim3 g((K + TN - 1) / TN, (cout + TM - 1) / TM, S);
+      hipLaunchKernelGGL(conv_wgrad_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, (int)chunk);
+    }
     hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(m)), dim3(BS), 0, s, work, S, m, dw);
-    if (db) hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(BS), 0, s, P, dz, db);
+    if (db) {
+      float *pb = work + (size_t)pl.splits * m;
+      const int64_t nr = bias_ranges(P), chunk = (P + nr - 1) / nr;
+      hipLaunchKernelGGL(bias_grad_kernel, dim3(cout, (unsigned)nr), dim3(BS), 0, s, P, chunk, dz, pb);
+      hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(cout)), dim3(BS), 0, s, pb, (int)nr, (int64_t)cout, db);
+    }
     FDTD_HIP(hipGetLastError());
   });
 }

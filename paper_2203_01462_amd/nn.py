@@ -159,9 +159,12 @@ class UNet:
         self.dev = torch.device(device)
         self.stream = stream
         self.plan = layer_plan(channels)
-        # flat parameter layout: per conv w [cout][cin*9] then b [cout]; then the linear head
+        # flat parameter layout: per conv w [cout][3][3][cin] (starting at a
+        # multiple of 8 elements: 16-byte aligned BF16 rows) then b [cout];
+        # then the linear head
         offs, o = [], 0
         for cin, cout, _ in self.plan:
+            o = (o + 7) // 8 * 8
             offs.append((o, o + cout * cin * 9))
             o += cout * cin * 9 + cout
         self.lin_off = o

@@ -373,9 +373,9 @@ def _from_first(trace):
 
 
 def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60, checks=30, inner=10, seed=0,
-            n_steps=5000, w=None, settings=((0.1, 2),), log=print):
+            n_steps=5000, w=None, settings=((0.2, 2),), log=print):
     """Plain loop vs surrogate-guided loop from the same start design; one
-    guided run per (move limit, tuning steps) in `settings`."""
+    guided run per (move limit, tuning steps[, inner steps]) in `settings`."""
     w = W.c5(n_steps) if w is None else w
     out = dict(workload=w["name"], samples=samples, train_steps=train_steps, batch=batch, alpha=alpha,
                inner=inner, n_steps=n_steps)
@@ -404,20 +404,22 @@ def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60,
         # every setting starts from the same trained network and dataset
         saved = (net.p.clone(), net.m.clone(), net.v.clone(), net.t, data.n)
         runs = []
-        for mv, tune in settings:
+        for st in settings:
+            mv, tune = st[0], st[1]
+            inn = st[2] if len(st) > 2 else inner
             net.p.copy_(saved[0])
             net.m.copy_(saved[1])
             net.v.copy_(saved[2])
             net.t, data.n = saved[3], saved[4]
             net.load(net.p)
-            gtrace, gstats = guided(w, net, data, alpha=alpha, checks=checks, inner=inner, move=mv, tune_steps=tune,
+            gtrace, gstats = guided(w, net, data, alpha=alpha, checks=checks, inner=inn, move=mv, tune_steps=tune,
                                     log=log)
             gtrace = _from_first(gtrace)
             hit = [i for i, (_, F) in enumerate(gtrace) if F >= target]
-            runs.append(dict(move=mv, tune_steps=tune, trace=gtrace, stats=gstats,
+            runs.append(dict(move=mv, tune_steps=tune, inner=inn, trace=gtrace, stats=gstats,
                              time_to_target=time_to(gtrace, target), checks_to_target=hit[0] if hit else None,
                              best=max(F for _, F in gtrace)))
-            log(f"guided move {mv} tune {tune}: time to target {runs[-1]['time_to_target']}, "
+            log(f"guided move {mv} tune {tune} inner {inn}: time to target {runs[-1]['time_to_target']}, "
                 f"plain {out['plain_time_to_target']}")
     torch.cuda.synchronize()
     out["guided"] = runs
@@ -435,10 +437,13 @@ def main(argv=None):
     ap.add_argument("--inner", type=int, default=10)
     ap.add_argument("--n-steps", type=int, default=5000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--settings", default="0.1:2", help="comma-separated move:tune_steps pairs")
+    ap.add_argument("--settings", default="0.2:2", help="comma-separated move:tune_steps[:inner] settings")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    settings = [(float(m), int(t)) for m, t in (p.split(":") for p in a.settings.split(","))]
+    settings = []
+    for item in a.settings.split(","):
+        f = item.split(":")
+        settings.append((float(f[0]), int(f[1])) + ((int(f[2]),) if len(f) > 2 else ()))
     res = compare(a.samples, a.train_steps, a.batch, a.alpha, a.plain_iters, a.checks, a.inner, a.seed, a.n_steps,
                   settings=settings, log=lambda m: print(m, flush=True))
     summary = {k: v for k, v in res.items() if not k.endswith("_trace") and k not in ("train_hist", "guided")}

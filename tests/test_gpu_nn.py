@@ -48,12 +48,28 @@ def to_cn(x):  # [N][C][H][W] -> [C][N][H][W]
     return x.permute(1, 0, 2, 3).contiguous()
 
 
+def to_krsc(wt):  # torch [cout][cin][3][3] -> the library's [cout][3][3][cin], flattened per cout
+    return wt.permute(0, 2, 3, 1).reshape(wt.shape[0], -1).contiguous()
+
+
+def from_krsc(flat, cout, cin):
+    return flat.view(cout, 3, 3, cin).permute(0, 3, 1, 2)
+
+
 CONV_CASES = [
-    # n, cin, cout, h, w: ragged pixel tiles, cout across two 64-tiles, K not a multiple of 16
+    # generic kernel: ragged pixel tiles, cout across two 64-tiles, K not a multiple of 16
     (3, 5, 70, 13, 11),
     (2, 40, 33, 16, 16),
     (1, 1, 32, 8, 8),
     (4, 96, 32, 24, 24),
+    # LDS-tiled matrix-core kernel (cin % 32 == 0, h and w multiples of 16):
+    # 32- and 64-channel output tiles, ragged cout, several channel chunks,
+    # non-square images, the U-Net's deepest shape
+    (2, 32, 64, 16, 16),
+    (3, 64, 70, 32, 16),
+    (2, 96, 32, 16, 48),
+    (1, 32, 20, 16, 16),
+    (2, 256, 256, 16, 16),
 ]
 
 
@@ -66,7 +82,7 @@ def test_conv_forward(nn, n, cin, cout, h, w):
     ref = Fn.conv2d(x.double(), wt.double(), b.double(), padding=1)
     z = torch.empty(cout * n * h * w, dtype=torch.float32, device="cuda")
     a = torch.empty(cout * n * h * w, dtype=torch.int16, device="cuda")
-    nn.conv3x3(bits(to_cn(x)), bits(wt.reshape(cout, -1)), b.cuda(), n, cin, cout, h, w, z=z, a=a)
+    nn.conv3x3(bits(to_cn(x)), bits(to_krsc(wt)), b.cuda(), n, cin, cout, h, w, z=z, a=a)
     torch.cuda.synchronize()
     zc = z.cpu().view(cout, n, h, w).permute(1, 0, 2, 3)
     err = (zc.double() - ref).abs().max().item()
@@ -84,7 +100,7 @@ def test_conv_only_activation_output(nn):
     z = torch.empty(cout * n * h * w, device="cuda")
     a1 = torch.empty(cout * n * h * w, dtype=torch.int16, device="cuda")
     a2 = torch.empty_like(a1)
-    xb, wb = bits(to_cn(x)), bits(wt.reshape(cout, -1))
+    xb, wb = bits(to_cn(x)), bits(to_krsc(wt))
     nn.conv3x3(xb, wb, None, n, cin, cout, h, w, z=z, a=a1)
     nn.conv3x3(xb, wb, None, n, cin, cout, h, w, a=a2)
     torch.cuda.synchronize()
@@ -106,7 +122,7 @@ def test_conv_backward(nn, n, cin, cout, h, w):
     db = torch.empty(cout, device="cuda")
     wrot = torch.empty(cout * cin * 9, dtype=torch.int16, device="cuda")
     work = torch.empty(nn.wgrad_work(n, cin, cout, h, w), device="cuda")
-    xb, dzb, wb = bits(to_cn(x)), bits(to_cn(dz)), bits(wt.reshape(cout, -1))
+    xb, dzb, wb = bits(to_cn(x)), bits(to_cn(dz)), bits(to_krsc(wt))
     nn.conv3x3_dgrad(dzb, wb, wrot, dx, n, cin, cout, h, w)
     nn.conv3x3_wgrad(xb, dzb, dw, db, work, n, cin, cout, h, w)
     torch.cuda.synchronize()
@@ -114,25 +130,60 @@ def test_conv_backward(nn, n, cin, cout, h, w):
     sx = Fn.conv_transpose2d(dz.abs().double(), wt.abs().double(), padding=1).max().item()
     assert (dxc - xd.grad).abs().max().item() <= 2e-6 * sx
     sw = (dz.abs().sum() * x.abs().max()).item()
-    assert (dw.cpu().view(cout, cin, 3, 3).double() - wd.grad).abs().max().item() <= 2e-6 * sw
+    assert (from_krsc(dw.cpu(), cout, cin).double() - wd.grad).abs().max().item() <= 2e-6 * sw
     assert np.allclose(db.cpu().double().numpy(), bd.grad.numpy(), rtol=1e-6, atol=1e-5)
 
 
-def test_wgrad_many_splits(nn):
-    # enough pixels for several split-K partitions, a ragged last one
-    n, cin, cout, h, w = 9, 3, 5, 40, 40
-    g = torch.Generator().manual_seed(3)
+@pytest.mark.parametrize("n,cin,cout,h,w,shift", [
+    (9, 3, 5, 40, 40, 0),     # generic kernel, several pixel ranges, a ragged last one
+    (5, 32, 16, 32, 32, 0),   # tiled kernel, one pixel tile per partial sum
+    (7, 64, 96, 24, 48, 0),   # tiled, ragged output-channel tile, 24 = 3 x 8 rows
+    (5, 32, 16, 32, 32, 1),   # dz not 16-byte aligned: the generic kernel with the tiled plan's split count
+])
+def test_wgrad_many_splits(nn, n, cin, cout, h, w, shift):
+    g = torch.Generator().manual_seed(3 + cin)
     x = bf16_round(torch.randn(n, cin, h, w, generator=g))
     dz = bf16_round(torch.randn(n, cout, h, w, generator=g))
     wd = torch.zeros(cout, cin, 3, 3, dtype=torch.float64, requires_grad=True)
-    Fn.conv2d(x.double(), wd, padding=1).backward(dz.double())
+    bd = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    Fn.conv2d(x.double(), wd, bd, padding=1).backward(dz.double())
     assert nn.wgrad_work(n, cin, cout, h, w) >= 2 * cout * cin * 9
     dw = torch.empty(cout * cin * 9, device="cuda")
+    db = torch.empty(cout, device="cuda")
     work = torch.empty(nn.wgrad_work(n, cin, cout, h, w), device="cuda")
-    nn.conv3x3_wgrad(bits(to_cn(x)), bits(to_cn(dz)), dw, None, work, n, cin, cout, h, w)
+    dzb = bits(to_cn(dz)).reshape(-1)
+    if shift:
+        buf = torch.zeros(dzb.numel() + shift, dtype=torch.int16, device="cuda")
+        buf[shift:] = dzb
+        dzb = buf[shift:]
+    nn.conv3x3_wgrad(bits(to_cn(x)), dzb, dw, db, work, n, cin, cout, h, w)
     torch.cuda.synchronize()
     sw = (dz.abs().sum() * x.abs().max()).item()
-    assert (dw.cpu().view(cout, cin, 3, 3).double() - wd.grad).abs().max().item() <= 2e-6 * sw
+    assert (from_krsc(dw.cpu(), cout, cin).double() - wd.grad).abs().max().item() <= 2e-6 * sw
+    assert np.allclose(db.cpu().double().numpy(), bd.grad.numpy(), rtol=1e-6, atol=1e-4)
+
+
+def test_misaligned_weights_take_the_generic_kernel(nn):
+    """A weight pointer that is not 16-byte aligned must still give the same
+    convolution (the tiled kernel needs aligned 16-byte weight rows)."""
+    n, cin, cout, h, w = 2, 32, 48, 16, 16
+    g = torch.Generator().manual_seed(21)
+    x = bf16_round(torch.randn(n, cin, h, w, generator=g))
+    wt = bf16_round(torch.randn(cout, cin, 3, 3, generator=g) / math.sqrt(cin * 9))
+    flat = bits(to_krsc(wt)).reshape(-1)
+    shifted = torch.zeros(flat.numel() + 1, dtype=torch.int16, device="cuda")
+    shifted[1:] = flat
+    za = torch.empty(cout * n * h * w, device="cuda")
+    zb = torch.empty_like(za)
+    xb = bits(to_cn(x))
+    nn.conv3x3(xb, flat, None, n, cin, cout, h, w, z=za)
+    nn.conv3x3(xb, shifted[1:], None, n, cin, cout, h, w, z=zb)
+    torch.cuda.synchronize()
+    ref = Fn.conv2d(x.double(), wt.double(), padding=1)
+    scale = Fn.conv2d(x.abs().double(), wt.abs().double(), padding=1).max().item()
+    for z in (za, zb):
+        zc = z.cpu().view(cout, n, h, w).permute(1, 0, 2, 3).double()
+        assert (zc - ref).abs().max().item() <= 2e-6 * scale
 
 
 def test_bf16_conversions_bit_exact(nn):
@@ -284,7 +335,7 @@ def ref_unet(nn, net, p, rho):
     def W(i):
         cin, cout, _ = plan[i]
         ow, ob = net.offs[i]
-        return rnd(p[ow:ob]).view(cout, cin, 3, 3), p[ob:ob + cout]
+        return rnd(p[ow:ob]).view(cout, 3, 3, cin).permute(0, 3, 1, 2), p[ob:ob + cout]
 
     def conv(x, i, relu=True):
         w, b = W(i)
