@@ -28,6 +28,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include <algorithm>
+
 #include "fdtd_3d.hpp"
 
 namespace fdtd {
@@ -75,6 +77,10 @@ __device__ __forceinline__ void block_of(int bid, int nbx, int nby, int nbz, int
   bz = bid / per;
 }
 
+struct TileBox {
+  int o[3], e[3];
+};
+
 struct Tile {
   int i0, j0, kb, ke;
   bool xy_plain;     // x/y reach holds no absorber, wall or injection face
@@ -103,17 +109,32 @@ __device__ __forceinline__ Tile tile_xy(const Step3D<T> &p, int i0, int j0) {
   return t;
 }
 
-// Tile of a workgroup of the general kernel.
+// Tile of a workgroup of the general kernel: over the whole grid (XCD-aware
+// order), or, for the design launch, over the box of tiles `box` (origin
+// box[0..2], extent box[3..5], x fastest).
 template <typename T>
-__device__ __forceinline__ Tile tile_of(const Step3D<T> &p) {
+__device__ __forceinline__ Tile tile_of(const Step3D<T> &p, const bool in_box, const TileBox &box) {
   const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
   const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY, nbz = (nz + KC - 1) / KC;
   int bx, by, bz;
-  block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
+  if (in_box) {
+    const int b = blockIdx.x;
+    bx = box.o[0] + b % box.e[0];
+    by = box.o[1] + (b / box.e[0]) % box.e[1];
+    bz = box.o[2] + b / (box.e[0] * box.e[1]);
+  } else {
+    block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
+  }
   Tile t = tile_xy(p, bx * TX, by * TY);
   t.kb = bz * KC;
   t.ke = min(t.kb + KC, nz);
   return t;
+}
+
+// Does the tile's z-chunk meet the design or the gap box?
+template <typename T>
+__device__ __forceinline__ bool design_chunk(const Step3D<T> &p, const Tile &t) {
+  return (t.dxy && t.ke > p.d0[2] && t.kb < p.d0[2] + p.dn[2]) || (t.gxy && t.ke > p.g0[2] && t.kb < p.g0[2] + p.gn[2]);
 }
 
 // Plane k of tile t takes the plain update: x/y reach plain, k and its two z
@@ -164,13 +185,20 @@ __device__ __forceinline__ T gr(T v, T m, const Ax<T> &x, T &mn) {
 }
 
 // ---------------------------------------------------------------- general
-// The FP32 forward variant fits 4 waves per SIMD without spills; the others
-// need more registers and run at the compiler's choice.
-template <typename T, bool ADJ>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(!ADJ && sizeof(T) == 4 ? 4 : 1)))
-step3d_general(const Step3D<T> p, const int n) {
+// MODE 0: every general tile-plane (the forward).  MODE 1: the tile-chunks
+// that miss the design and gap boxes, with the design and gap code compiled
+// out; MODE 2: the others, launched over the box of tiles around them.  The
+// adjoint runs MODE 1 then MODE 2: without the FP64 sensitivity sums the
+// absorber tiles need fewer registers (FP32: 3 waves per SIMD instead of 2).
+// Both read only the read copy and write disjoint tile-chunks.
+// The FP32 forward variant fits 4 waves per SIMD without spills.
+template <typename T, bool ADJ, int MODE>
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (!ADJ ? 4 : (MODE == 1 ? 3 : 1)) : 1)))
+step3d_general(const Step3D<T> p, const int n, const TileBox box) {
   const int nx = p.n[0], ny = p.n[1], nz = p.n[2], P = p.P;
-  const Tile tl = tile_of(p);
+  const Tile tl = tile_of(p, MODE == 2, box);
+  if (MODE != 0 && design_chunk(p, tl) != (MODE == 2)) return;  // the other launch's tile-chunk
   const int i = tl.i0 + (threadIdx.x % TX), j = tl.j0 + (threadIdx.x / TX);
   if (i >= nx || j >= ny) return;  // no barriers in this kernel
   const T *__restrict__ R = p.A[0];
@@ -258,8 +286,8 @@ step3d_general(const Step3D<T> p, const int n) {
     // injection, design and gap at this tile-plane (uniform)
     const bool tfp = tl.tf_meet && k >= p.lo[2] - 1 && k <= p.hi[2] &&
                      (tl.tf_hit || k == p.lo[2] - 1 || k == p.lo[2] || k == p.hi[2]);
-    const bool dp = tl.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2];
-    const bool gp = tl.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2];
+    const bool dp = MODE != 1 && tl.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2];
+    const bool gp = MODE != 1 && tl.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2];
     const bool des = dp && dcol, gap = gp && gcol, drude = des && !gap;
     const uint32_t d = des ? (uint32_t)(((k - p.d0[2]) * p.dn[1] + dj) * p.dn[0] + di) : 0u;
     const uint32_t g = gap ? (uint32_t)(((k - p.g0[2]) * p.gn[1] + gj) * p.gn[0] + gi) : 0u;
@@ -665,10 +693,35 @@ void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t
   q.A[1] = p.A[par ^ 1];
   const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + KC - 1) / KC;
   const dim3 grid(nbx * nby * nbz);
-  if (adjoint)
-    hipLaunchKernelGGL((step3d_general<T, true>), grid, dim3(NT), 0, s, q, n);
-  else
-    hipLaunchKernelGGL((step3d_general<T, false>), grid, dim3(NT), 0, s, q, n);
+  TileBox all{};
+  if (adjoint) {
+    hipLaunchKernelGGL((step3d_general<T, true, 1>), grid, dim3(NT), 0, s, q, n, all);
+    // tiles around the design and gap boxes (their union's bounding box)
+    TileBox b{};
+    int lo[3], hi[3];
+    bool any = false;
+    auto add = [&](const int *o, const int *e) {
+      if (e[0] <= 0 || e[1] <= 0 || e[2] <= 0) return;
+      const int l[3] = {o[0] / TX, o[1] / TY, o[2] / KC};
+      const int h[3] = {(o[0] + e[0] - 1) / TX, (o[1] + e[1] - 1) / TY, (o[2] + e[2] - 1) / KC};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = any ? std::min(lo[a], l[a]) : l[a];
+        hi[a] = any ? std::max(hi[a], h[a]) : h[a];
+      }
+      any = true;
+    };
+    add(p.d0, p.dn);
+    add(p.g0, p.gn);
+    if (any) {
+      for (int a = 0; a < 3; ++a) {
+        b.o[a] = lo[a];
+        b.e[a] = hi[a] - lo[a] + 1;
+      }
+      hipLaunchKernelGGL((step3d_general<T, true, 2>), dim3(b.e[0] * b.e[1] * b.e[2]), dim3(NT), 0, s, q, n, b);
+    }
+  } else {
+    hipLaunchKernelGGL((step3d_general<T, false, 0>), grid, dim3(NT), 0, s, q, n, all);
+  }
   const int pbx = (p.n[0] + PTX - 1) / PTX, pby = (p.n[1] + PTY - 1) / PTY, pbz = (p.n[2] + PKC - 1) / PKC;
   hipLaunchKernelGGL(step3d_plain<T>, dim3(pbx * pby * pbz), dim3(PNT), 0, s, q);
 }

@@ -221,7 +221,7 @@ def plain(w, alpha=1.0, radius=2.5, max_iter=60, max_inner=40):
     return trace, res
 
 
-def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=10, move=0.1, tune_steps=2, tune_batch=8,
+def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tune_steps=2, tune_batch=8,
            tune_lr=2e-4, max_inner=40, log=None):
     """Surrogate-guided loop; returns [(t, F of the current design)] per FDTD
     check and counters.
@@ -372,7 +372,7 @@ def _from_first(trace):
     return [(t - t0, F) for t, F in trace]
 
 
-def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60, checks=30, inner=10, seed=0,
+def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60, checks=30, inner=4, seed=0,
             n_steps=5000, w=None, settings=((0.2, 2),), log=print):
     """Plain loop vs surrogate-guided loop from the same start design; one
     guided run per (move limit, tuning steps[, inner steps]) in `settings`."""
@@ -434,10 +434,10 @@ def main(argv=None):
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--plain-iters", type=int, default=60)
     ap.add_argument("--checks", type=int, default=30)
-    ap.add_argument("--inner", type=int, default=10)
+    ap.add_argument("--inner", type=int, default=4)
     ap.add_argument("--n-steps", type=int, default=5000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--settings", default="0.2:2", help="comma-separated move:tune_steps[:inner] settings")
+    ap.add_argument("--settings", default="0.2:2:4", help="comma-separated move:tune_steps[:inner] settings")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     settings = []
