@@ -9,7 +9,7 @@ multiplier through {1, 4, 16} (damping continuation).
 
 Prints ONE JSON line: the metric in Gcell-updates/s (grid cells x time steps x
 2 solves / wall time of the step), the roofline of the time-step kernel
-(algorithmic HBM bytes per launch / average launch time from HIP events on the
+(algorithmic HBM bytes per time step / average time per step from HIP events on the
 library stream), and the CPU oracle timed on a bounded sample of the same
 workload on the host cores.
 """
@@ -29,14 +29,14 @@ import fdtd_workloads as W  # noqa: E402
 METRIC = "Drude-FDTD fwd+adjoint Gcell-updates/s, % HBM roofline; time-to-design vs plain"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# HBM bytes per time step of the step kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (scaled by the copy-probe factors: fetch x2, write x1), recorded with
 # the kernel source they were taken on.  Reported only while that source is
 # unchanged; the summaries live in profiles/.
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "9eb03e25f5136a69",
-                        "fwd": 116.1e6, "adj": 120.3e6,
-                        "profile": "profiles/step2d_kernel_tmz2d_2048_fp32.md"},
+    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "83cf517e18c837ed",
+                        "fwd": 104.9e6, "adj": 109.1e6,
+                        "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step = step3d_general (adjoint: two launches) + step3d_plain
     "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "5f6dfb781096d875",
                        "fwd": 1237.3e6, "adj": 1271.0e6,
@@ -245,11 +245,12 @@ def main():
     trec, traffic = measured_traffic(base["name"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_per_launch_fwd_adj": [trec["fwd"], trec["adj"]] if trec else None,
-                "kernel": "step2d_kernel" if base["dims"] == 2 else "step3d_general+step3d_plain (one time step)",
-                "bytes_per_launch_fwd": bf, "bytes_per_launch_adj": ba,
-                "avg_launch_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
-                "avg_launch_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}
+                "traffic_per_step_fwd_adj": [trec["fwd"], trec["adj"]] if trec else None,
+                "kernel": ("step2d_mix_kernel (two launches per two time steps)" if base["dims"] == 2
+                           else "step3d_general+step3d_plain (one time step)"),
+                "bytes_per_step_fwd": bf, "bytes_per_step_adj": ba,
+                "avg_step_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
+                "avg_step_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}
     nx, ny, nz = base["n"]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,

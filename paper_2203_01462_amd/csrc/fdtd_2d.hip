@@ -1,5 +1,7 @@
 // fdtd_2d.hip -- fused time step of the 2D TMz Drude-FDTD solve and of its
-// adjoint, one launch per time step.
+// adjoint: one launch per time step (step2d_kernel), or, with two-step
+// blocking of the plain background, two launches per two time steps
+// (step2d_mix_kernel, see the two-step section below).
 //
 // Per step (Sec. 3.2 staggering: E, J at integer steps, H at half steps):
 //   H^{n+1/2} = H^{n-1/2} - dt/mu0 curl E^n                 (eq. (10c), CPML, TFSF)
@@ -467,7 +469,13 @@ __device__ __forceinline__ void step2d_block(const Step2D<T> &p, const int n, co
   const int nx = p.nx, ny = p.ny, P = p.P;
   const int nbx = (nx + TXW - 1) / TXW, nby = (ny + TYB - 1) / TYB;
   int tx, ty;
-  tile_of(bid, nbx, nby, tx, ty);
+  if (p.tlist) {
+    const int t = p.tlist[bid];
+    tx = t % nbx;
+    ty = t / nbx;
+  } else {
+    tile_of(bid, nbx, nby, tx, ty);
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i0 = tx * TXW;
   const int i = i0 + lane;
@@ -532,6 +540,122 @@ __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
   step2d_block<T, ADJ, R>(p, n, 0, b - f[lo]);
 }
 
+// ---------------------------------------------------------------- two-step
+// Background update (as in step_bulk) applied twice to a TBX x TBY
+// super-tile from an LDS copy of its region with a TBH = 2 node halo (LDS
+// rows 0..TLY-1, columns 0..TLX-1; the super-tile is rows 2..TLY-3,
+// columns 2..TLX-3).  Each phase updates in place over the nodes whose
+// inputs the previous phases made valid:
+//   H^{n+1/2}: H_x rows 0..TLY-2, H_y columns 0..TLX-2
+//   E^{n+1}:   rows 1..TLY-2, columns 1..TLX-2
+//   H^{n+3/2}: H_x rows 1..TLY-3 (columns 1..TLX-2), H_y rows 1..TLY-2 (columns 1..TLX-3)
+//   E^{n+2}:   the super-tile
+// The expressions are those of step_bulk, so the result is the per-step
+// update's to the last bit.  64 x 16 super-tiles (17 KB of LDS in FP32)
+// measured faster than 64 x 32 (more LDS per workgroup, fewer resident) and
+// 64 x 8 (more halo).
+constexpr int TBX = 64, TBY = 16, TBH = 2;
+constexpr int TLX = TBX + 2 * TBH, TLY = TBY + 2 * TBH;  // 68 x 20
+constexpr int TLS = TLX + 1;                               // LDS row stride
+
+template <typename T>
+__device__ __forceinline__ void tb_block(const Step2D<T> &p, const int code, T *ezo, T *hxo, T *hyo, T *E, T *HX,
+                                         T *HY) {
+  const int nbx = (p.nx + TXW - 1) / TXW;
+  const bool mid = code & 1;
+  const int st = code >> 1, sx = st % nbx, sy = st / nbx;
+  const int x0 = sx * TBX - TBH, y0 = sy * TBY - TBH;  // global origin of LDS (0, 0)
+  const int pitch = p.pitch;
+  const T *__restrict__ ez = p.ez[0];
+  const T *__restrict__ hx = p.hx[0];
+  const T *__restrict__ hy = p.hy[0];
+  const T ch = p.chx, ce = p.ce_s;
+  const int t = threadIdx.x;
+  // all of a thread's loads in flight before the first LDS store
+  constexpr int NL = (TLY * TLX + NT - 1) / NT;
+  T ve[NL], vx[NL], vy[NL];
+#pragma unroll
+  for (int it = 0; it < NL; ++it) {
+    const int e = t + it * NT;
+    const int r = e / TLX, c = e - r * TLX;
+    const bool on = e < TLY * TLX;
+    const size_t q = on ? (size_t)(y0 + r) * pitch + (x0 + c) : (size_t)(y0 * pitch + x0);
+    ve[it] = ez[q];
+    vx[it] = hx[q];
+    vy[it] = hy[q];
+  }
+#pragma unroll
+  for (int it = 0; it < NL; ++it) {
+    const int e = t + it * NT;
+    if (e < TLY * TLX) {
+      const int r = e / TLX, c = e - r * TLX;
+      E[r * TLS + c] = ve[it];
+      HX[r * TLS + c] = vx[it];
+      HY[r * TLS + c] = vy[it];
+    }
+  }
+  __syncthreads();
+  // H^{n+1/2}
+  for (int e = t; e < TLY * TLX; e += NT) {
+    const int r = e / TLX, c = e - r * TLX, k = r * TLS + c;
+    if (r < TLY - 1) HX[k] = HX[k] - ch * (E[k + TLS] - E[k]);
+    if (c < TLX - 1) HY[k] = HY[k] + ch * (E[k + 1] - E[k]);
+  }
+  __syncthreads();
+  // E^{n+1}
+  for (int e = t; e < (TLY - 2) * (TLX - 2); e += NT) {
+    const int r = 1 + e / (TLX - 2), c = 1 + e % (TLX - 2), k = r * TLS + c;
+    E[k] = E[k] + ce * ((HY[k] - HY[k - 1]) - (HX[k] - HX[k - TLS]));
+  }
+  __syncthreads();
+  if (mid) {  // the intermediate state of the super-tile, for the per-step neighbours
+    T *__restrict__ ezm = p.ez[1];
+    T *__restrict__ hxm = p.hx[1];
+    T *__restrict__ hym = p.hy[1];
+    for (int e = t; e < TBY * TBX; e += NT) {
+      const int r = TBH + e / TBX, c = TBH + e % TBX, k = r * TLS + c;
+      const size_t q = (size_t)(y0 + r) * pitch + (x0 + c);
+      ezm[q] = E[k];
+      hxm[q] = HX[k];
+      hym[q] = HY[k];
+    }
+    __syncthreads();
+  }
+  // H^{n+3/2}
+  for (int e = t; e < (TLY - 2) * (TLX - 2); e += NT) {
+    const int r = 1 + e / (TLX - 2), c = 1 + e % (TLX - 2), k = r * TLS + c;
+    if (r < TLY - 2) HX[k] = HX[k] - ch * (E[k + TLS] - E[k]);
+    if (c < TLX - 2) HY[k] = HY[k] + ch * (E[k + 1] - E[k]);
+  }
+  __syncthreads();
+  // E^{n+2} on the super-tile, stored with the new H
+  for (int e = t; e < TBY * TBX; e += NT) {
+    const int r = TBH + e / TBX, c = TBH + e % TBX, k = r * TLS + c;
+    const size_t q = (size_t)(y0 + r) * pitch + (x0 + c);
+    ezo[q] = E[k] + ce * ((HY[k] - HY[k - 1]) - (HX[k] - HX[k - TLS]));
+    hxo[q] = HX[k];
+    hyo[q] = HY[k];
+  }
+}
+// One launch of the blocked schedule: workgroups [0, nrest) take one
+// per-step update of the tiles in ps.tlist (step n), the others two steps of
+// the super-tiles tiles[0, ntb) of the pair described by pt.
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
+    step2d_mix_kernel(const Step2D<T> ps, const int n, const int nrest, const Step2D<T> pt,
+                      const int *__restrict__ tiles, T *ezo, T *hxo, T *hyo) {
+  __shared__ T E[TLY * TLS], HX[TLY * TLS], HY[TLY * TLS];
+  const int b = blockIdx.x;
+  // per-step workgroups first: their slow design and absorber tiles start
+  // early and the two-step workgroups fill the machine around them
+  if (b < nrest) {
+    step2d_block<T, ADJ, RDEF>(ps, n, 0, b);
+    return;
+  }
+  tb_block<T>(pt, tiles[b - nrest], ezo, hxo, hyo, E, HX, HY);
+}
+
+
 }  // namespace
 
 int step2d_blocks(int nx, int ny, int rows) {
@@ -559,6 +683,50 @@ static void launch_one(const Step2D<T> &p0, int n, int par, int rows, hipStream_
   else hipLaunchKernelGGL((step2d_kernel<T, ADJ, 2>), grid, dim3(NT), 0, s, p, n);
 }
 
+Tb2dPlan tb2d_plan(int nx, int ny, int P, int ia, int ib, int ja, int jb, const int dbox[4], const int gbox[4]) {
+  Tb2dPlan pl;
+  const int nbx = (nx + TXW - 1) / TXW, nsy = ny / TBY;
+  const int tyb = WAVES * RDEF, nby = (ny + tyb - 1) / tyb;
+  std::vector<char> ok((size_t)nbx * std::max(nsy, 1), 0);
+  auto meets = [](int a0, int a1, int b0, int bn) { return bn > 0 && a1 >= b0 && a0 <= b0 + bn - 1; };
+  for (int sy = 0; sy < nsy; ++sy)
+    for (int tx = 0; tx < nbx; ++tx) {
+      // reach: the super-tile grown by three nodes
+      const int x0 = tx * TBX - 3, x1 = tx * TBX + TBX + 2, y0 = sy * TBY - 3, y1 = sy * TBY + TBY + 2;
+      bool g = tx * TBX + TBX <= nx && x0 >= P + 2 && x1 <= nx - 3 - P && y0 >= P + 2 && y1 <= ny - 3 - P;
+      for (int v : {ia - 1, ia, ib, ib + 1}) g = g && !(v >= x0 && v <= x1);
+      for (int v : {ja - 1, ja, jb, jb + 1}) g = g && !(v >= y0 && v <= y1);
+      g = g && !(meets(x0, x1, dbox[0], dbox[2]) && meets(y0, y1, dbox[1], dbox[3]));
+      g = g && !(meets(x0, x1, gbox[0], gbox[2]) && meets(y0, y1, gbox[1], gbox[3]));
+      ok[(size_t)sy * nbx + tx] = g;
+    }
+  auto at = [&](int sy, int tx) { return sy >= 0 && sy < nsy && tx >= 0 && tx < nbx && ok[(size_t)sy * nbx + tx]; };
+  for (int sy = 0; sy < nsy; ++sy)
+    for (int tx = 0; tx < nbx; ++tx) {
+      if (!at(sy, tx)) continue;
+      bool inner = true;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) inner = inner && at(sy + dy, tx + dx);
+      pl.tb.push_back(((sy * nbx + tx) << 1) | (inner ? 0 : 1));
+    }
+  static_assert(TBY % (WAVES * RDEF) == 0, "super-tiles are whole workgroup tiles");
+  for (int ty = 0; ty < nby; ++ty)
+    for (int tx = 0; tx < nbx; ++tx)
+      if (!at(ty * tyb / TBY, tx) || (ty + 1) * tyb > nsy * TBY) pl.rest.push_back(ty * nbx + tx);
+  return pl;
+}
+
+template <typename T>
+void launch_step2d_mix(const Step2D<T> &ps, int n, int nrest, const Step2D<T> &pt, const int *tiles, int ntb, T *ezo,
+                       T *hxo, T *hyo, bool adjoint, hipStream_t s) {
+  const int nb = nrest + ntb;
+  if (nb <= 0) return;
+  if (adjoint)
+    hipLaunchKernelGGL((step2d_mix_kernel<T, true>), dim3(nb), dim3(NT), 0, s, ps, n, nrest, pt, tiles, ezo, hxo, hyo);
+  else
+    hipLaunchKernelGGL((step2d_mix_kernel<T, false>), dim3(nb), dim3(NT), 0, s, ps, n, nrest, pt, tiles, ezo, hxo, hyo);
+}
+
 template <typename T>
 void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows) {
   if (rows <= 0) rows = RDEF;
@@ -582,6 +750,10 @@ void launch_step2d_batch(const Step2D<T> *ps, const int *first, int ninst, int n
   else launch_batch<T, false>(ps, first, ninst, nblocks, n, par, rows, s);
 }
 
+template void launch_step2d_mix<float>(const Step2D<float> &, int, int, const Step2D<float> &, const int *, int,
+                                       float *, float *, float *, bool, hipStream_t);
+template void launch_step2d_mix<double>(const Step2D<double> &, int, int, const Step2D<double> &, const int *, int,
+                                        double *, double *, double *, bool, hipStream_t);
 template void launch_step2d<float>(const Step2D<float> &, int, int, bool, hipStream_t, int);
 template void launch_step2d<double>(const Step2D<double> &, int, int, bool, hipStream_t, int);
 template void launch_step2d_batch<float>(const Step2D<float> *, const int *, int, int, int, int, bool, int, hipStream_t);

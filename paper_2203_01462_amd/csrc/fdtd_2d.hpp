@@ -1,6 +1,8 @@
 // fdtd_2d.hpp -- parameters of the 2D TMz step kernel.
 #pragma once
 
+#include <vector>
+
 #include "fdtd_internal.hpp"
 
 namespace fdtd {
@@ -36,6 +38,7 @@ struct Step2D {
   T dt_, dtdx, dthJ, kp;
   T ga, gsm, rs;  // sensitivity: ga = -(eps0/dt)(eps_inf - eps_s); gsm = -sigma_max/2; rs = psi_s/psi
   double dt;
+  const int *tlist;  // per-step launch over these workgroup tiles (ty * nbx + tx), or all when null
 };
 
 // One time step; rows = nodes per thread along y (1, 2 or 4; 0 = default).
@@ -44,6 +47,30 @@ void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t
 
 // Workgroups of one instance's step launch.
 int step2d_blocks(int nx, int ny, int rows);
+
+// Two-step blocking of the plain background.  Super-tiles of 64 x 16 nodes
+// whose reach (three nodes around them) holds only background dielectric --
+// no absorber, wall, injection line, design or gap -- advance two time steps
+// at once from an LDS copy of their tile with a two-node halo; the other
+// workgroup tiles of the default tiling (the "rest") take the per-step
+// update.  Super-tiles next to a rest tile (border) also store their
+// intermediate state, which the rest tiles' second step reads.
+struct Tb2dPlan {
+  std::vector<int> tb;    // super-tiles: ((sy * nbx + tx) << 1) | border
+  std::vector<int> rest;  // per-step workgroup tiles (ty * nbx + tx) outside the super-tiles
+};
+Tb2dPlan tb2d_plan(int nx, int ny, int P, int ia, int ib, int ja, int jb, const int dbox[4], const int gbox[4]);
+
+// One launch of the blocked schedule: nrest workgroups update the rest
+// tiles listed in ps.tlist by one step (step n; copy 0 read, copy 1 written),
+// ntb workgroups advance the super-tiles tiles[0..ntb) by two steps of the
+// pair described by pt (copy 0: E^m, H^{m-1/2}; copy 1 receives the border
+// super-tiles' intermediate state; ezo, hxo, hyo the state after the pair).
+// Either count may be zero.  The two-step update is the background update,
+// identical in the forward and the adjoint.
+template <typename T>
+void launch_step2d_mix(const Step2D<T> &ps, int n, int nrest, const Step2D<T> &pt, const int *tiles, int ntb, T *ezo,
+                       T *hxo, T *hyo, bool adjoint, hipStream_t s);
 
 // One time step of several instances (device array `ps` of their parameters,
 // `first[k]` = first workgroup of instance k, blocks of each instance padded

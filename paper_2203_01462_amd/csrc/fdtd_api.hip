@@ -36,6 +36,10 @@ struct fdtd_ctx {
   // checkpointed adjoint: a second state (both copies and J) for re-running
   // forward segments, and the snapshots [nseg-1][state copy + J]
   DevBuf fldR[2][6], pmlR[2][12], arenaR[2], JR, snap;
+  // 2D two-step blocking of the plain background: a third copy of the fields
+  // (main and re-run state), the super-tiles and the per-step tiles
+  DevBuf fld3[3], fld3R[3], tbTiles, tbRest;
+  int nTb = 0, nRest = 0, nEarly = 0;  // tbTiles = [early interior super-tiles | border and other interior]
   int ck = 0, nseg = 1;  // segment length (steps) and count; nseg = 1: full history
   size_t snap_bytes = 0;
   Step2D<float> p2f{}, p2fR{};
@@ -168,6 +172,41 @@ void create_2d(fdtd_ctx *c) {
     }
   }
   if (c->prec == 32) build_axis_tables<float>(c); else build_axis_tables<double>(c);
+  const int dbox[4] = {g.design_lo[0], g.design_lo[1], g.design_n[0], g.design_n[1]};
+  const int gbox[4] = {g.gap_lo[0], g.gap_lo[1], g.gap_n[0], g.gap_n[1]};
+  const Tb2dPlan pl = tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox);
+  if (!pl.tb.empty()) {
+    // up to half of the super-tiles, all interior ones, run one launch early
+    // (beside the rest tiles' second step of the previous pair)
+    std::vector<int> order;
+    for (int code : pl.tb)
+      if (!(code & 1) && (int)order.size() < (int)pl.tb.size() / 2) order.push_back(code);
+    c->nEarly = (int)order.size();
+    for (int code : pl.tb)
+      if (std::find(order.begin(), order.begin() + c->nEarly, code) == order.begin() + c->nEarly) order.push_back(code);
+    c->nTb = (int)order.size();
+    c->nRest = (int)pl.rest.size();
+    c->tbTiles.alloc(order.size() * sizeof(int));
+    c->tbRest.alloc(std::max<size_t>(pl.rest.size(), 1) * sizeof(int));
+    FDTD_HIP(hipMemcpy(c->tbTiles.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!pl.rest.empty())
+      FDTD_HIP(hipMemcpy(c->tbRest.p, pl.rest.data(), pl.rest.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int k = 0; k < 3; ++k) {
+      c->fld3[k].alloc(n2);
+      if (c->nseg > 1) c->fld3R[k].alloc(n2);
+    }
+  }
+}
+
+// Field copy holding the state after `s` steps of a solve: with two-step
+// blocking three copies rotate (a pair of steps reads copy s and writes
+// copy s+2, as two single steps would), else two.  Absorber memories always
+// alternate between two copies.
+int fcopy(const fdtd_ctx *c, int s) { return c->nTb > 0 ? s % 3 : s & 1; }
+
+DevBuf *field_buf(fdtd_ctx *c, bool rerun, int copy, int k) {
+  if (copy == 2) return rerun ? &c->fld3R[k] : &c->fld3[k];
+  return rerun ? &c->fldR[copy][k] : &c->fld[copy][k];
 }
 
 template <typename T>
@@ -340,6 +379,7 @@ void zero_state(fdtd_ctx *c) {
     for (int k = 0; k < 12; ++k) if (c->pml[b][k].p) zero(c, c->pml[b][k]);
     if (c->arena3[b].p) zero(c, c->arena3[b]);
   }
+  for (int k = 0; k < 3; ++k) if (c->fld3[k].p) zero(c, c->fld3[k]);
   zero(c, c->J);
 }
 
@@ -356,63 +396,128 @@ Step3D<float> &params3d<float>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3fR
 template <>
 Step3D<double> &params3d<double>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3dR : c->p3d; }
 
-// One time step on the main state (rerun = false) or the re-run state.
+// 2D parameters of the step that follows `s` steps of a solve: copy 0 read,
+// copy 1 written, parities resolved.
 template <typename T>
-void launch_step(fdtd_ctx *c, bool rerun, int n, int par, bool adjoint, int hist_base, bool hist_on) {
+Step2D<T> params2d_at(fdtd_ctx *c, bool rerun, int s, int hist_base, bool hist_on) {
+  Step2D<T> p = params2d<T>(c, rerun);
+  const int fr = fcopy(c, s), fw = fcopy(c, s + 1);
+  p.ez[0] = field_buf(c, rerun, fr, 0)->as<T>(); p.ez[1] = field_buf(c, rerun, fw, 0)->as<T>();
+  p.hx[0] = field_buf(c, rerun, fr, 1)->as<T>(); p.hx[1] = field_buf(c, rerun, fw, 1)->as<T>();
+  p.hy[0] = field_buf(c, rerun, fr, 2)->as<T>(); p.hy[1] = field_buf(c, rerun, fw, 2)->as<T>();
+  const int mr = s & 1, mw = mr ^ 1;
+  DevBuf *m0 = rerun ? c->pmlR[mr] : c->pml[mr], *m1 = rerun ? c->pmlR[mw] : c->pml[mw];
+  p.pex[0] = m0[0].as<T>(); p.pex[1] = m1[0].as<T>();
+  p.pey[0] = m0[1].as<T>(); p.pey[1] = m1[1].as<T>();
+  p.phx[0] = m0[2].as<T>(); p.phx[1] = m1[2].as<T>();
+  p.phy[0] = m0[3].as<T>(); p.phy[1] = m1[3].as<T>();
+  p.hist_base = hist_base;
+  p.hist_on = hist_on;
+  return p;
+}
+
+// One time step (step number n, the (s+1)-th of its solve) on the main state
+// (rerun = false) or the re-run state.
+template <typename T>
+void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_base, bool hist_on) {
   if (c->dims == 2) {
-    Step2D<T> p = params2d<T>(c, rerun);
-    p.hist_base = hist_base;
-    p.hist_on = hist_on;
-    launch_step2d<T>(p, n, par, adjoint, c->stream);
+    // a single step updates every tile (the super-tiles take the background
+    // update of the per-step kernel)
+    launch_step2d<T>(params2d_at<T>(c, rerun, s, hist_base, hist_on), n, 0, adjoint, c->stream);
   } else {
     Step3D<T> p = params3d<T>(c, rerun);
     p.hist_base = hist_base;
     p.hist_on = hist_on;
-    launch_step3d<T>(p, n, par, adjoint, c->stream);
+    launch_step3d<T>(p, n, s & 1, adjoint, c->stream);
   }
 }
 
-// The buffers of state copy b (fields and absorber memories) followed by J.
-std::vector<DevBuf *> state_bufs(fdtd_ctx *c, int b, bool rerun) {
+// `count` consecutive time steps of a solve, the first one the (s0+1)-th:
+// step j has step number nof(j), history base hbase and history flag hon(j).
+// With two-step blocking (2D, nTb > 0) the steps go in pairs, pipelined two
+// launches per pair: launch A of pair q = the rest tiles' first step of q and
+// the late super-tiles of q (all super-tiles for the first pair); launch B =
+// the rest tiles' second step of q and the early super-tiles of pair q+1.
+// The early super-tiles reach only other super-tiles, whose state after the
+// pair is already written, and write their output into the copy that the
+// rest tiles read in that launch only outside the super-tiles.  An odd last
+// step is a full-grid single step.
+template <typename T, typename NOF, typename HON>
+void run_block(fdtd_ctx *c, bool rerun, bool adjoint, int s0, int count, NOF nof, int hbase, HON hon) {
+  if (c->dims != 2 || c->nTb == 0) {
+    for (int j = 0; j < count; ++j) launch_step<T>(c, rerun, nof(j), s0 + j, adjoint, hbase, hon(j));
+    return;
+  }
+  const int P = count / 2;
+  const int *tiles = c->tbTiles.as<int>();
+  auto step = [&](int j) {
+    Step2D<T> p = params2d_at<T>(c, rerun, s0 + j, hbase, hon(j));
+    p.tlist = c->tbRest.as<int>();
+    return p;
+  };
+  auto out = [&](int q, int k) { return field_buf(c, rerun, fcopy(c, s0 + 2 * q + 2), k)->as<T>(); };
+  for (int q = 0; q < P; ++q) {
+    // launch A of pair q
+    const Step2D<T> pa = step(2 * q), pt = params2d_at<T>(c, rerun, s0 + 2 * q, hbase, hon(2 * q));
+    const int first = q == 0 ? 0 : c->nEarly;
+    launch_step2d_mix<T>(pa, nof(2 * q), c->nRest, pt, tiles + first, c->nTb - first, out(q, 0), out(q, 1),
+                         out(q, 2), adjoint, c->stream);
+    // launch B of pair q (+ the early super-tiles of pair q+1)
+    const Step2D<T> pb = step(2 * q + 1);
+    const bool next = q + 1 < P;
+    const Step2D<T> pn = next ? params2d_at<T>(c, rerun, s0 + 2 * q + 2, hbase, hon(2 * q + 2)) : pt;
+    launch_step2d_mix<T>(pb, nof(2 * q + 1), c->nRest, pn, tiles, next ? c->nEarly : 0,
+                         next ? out(q + 1, 0) : nullptr, next ? out(q + 1, 1) : nullptr,
+                         next ? out(q + 1, 2) : nullptr, adjoint, c->stream);
+  }
+  if (count & 1) launch_step<T>(c, rerun, nof(count - 1), s0 + count - 1, adjoint, hbase, hon(count - 1));
+}
+
+// The buffers holding the state after `st` steps of a solve (fields and
+// absorber memories) followed by J.
+std::vector<DevBuf *> state_bufs(fdtd_ctx *c, int st, bool rerun) {
   std::vector<DevBuf *> v;
   if (c->dims == 2) {
-    for (int k = 0; k < 3; ++k) v.push_back(rerun ? &c->fldR[b][k] : &c->fld[b][k]);
-    for (int k = 0; k < 4; ++k) v.push_back(rerun ? &c->pmlR[b][k] : &c->pml[b][k]);
+    for (int k = 0; k < 3; ++k) v.push_back(field_buf(c, rerun, fcopy(c, st), k));
+    for (int k = 0; k < 4; ++k) v.push_back(rerun ? &c->pmlR[st & 1][k] : &c->pml[st & 1][k]);
   } else {
-    v.push_back(rerun ? &c->arenaR[b] : &c->arena3[b]);
+    v.push_back(rerun ? &c->arenaR[st & 1] : &c->arena3[st & 1]);
   }
   v.push_back(rerun ? &c->JR : &c->J);
   return v;
 }
 
-// Snapshot s <- main copy b (the state at the start of segment s).
-void snap_save(fdtd_ctx *c, int b, int s) {
+// Snapshot s <- the main state after `st` steps (the start of segment s).
+void snap_save(fdtd_ctx *c, int st, int s) {
   char *dst = (char *)c->snap.p + (size_t)s * c->snap_bytes;
-  for (DevBuf *d : state_bufs(c, b, false)) {
+  for (DevBuf *d : state_bufs(c, st, false)) {
     FDTD_HIP(hipMemcpyAsync(dst, d->p, d->bytes, hipMemcpyDeviceToDevice, c->stream));
     dst += d->bytes;
   }
 }
 
-// Re-run copy b <- snapshot s.
-void snap_load(fdtd_ctx *c, int b, int s) {
+// Re-run state after `st` steps <- snapshot s.
+void snap_load(fdtd_ctx *c, int st, int s) {
   const char *src = (const char *)c->snap.p + (size_t)s * c->snap_bytes;
-  for (DevBuf *d : state_bufs(c, b, true)) {
+  for (DevBuf *d : state_bufs(c, st, true)) {
     FDTD_HIP(hipMemcpyAsync(d->p, src, d->bytes, hipMemcpyDeviceToDevice, c->stream));
     src += d->bytes;
   }
 }
 
-// Forward solve: step n reads copy n&1 and writes copy n&1^1.  With
-// checkpoints the state entering each segment but the last is saved, and only
-// the last segment's history is kept.
+// Forward solve: step n reads the state after n steps and writes the state
+// after n+1.  With checkpoints the state entering each segment but the last is
+// saved, and only the last segment's history is kept.  With two-step
+// blocking, steps go in pairs that never straddle a saved state.
 template <typename T>
 void run_forward(fdtd_ctx *c) {
   FDTD_HIP(hipEventRecord(c->ev[0], c->stream));
-  const int K = c->ck, S = c->nseg, last = (S - 1) * K;
-  for (int n = 0; n < c->N; ++n) {
-    if (S > 1 && n % K == 0 && n < last) snap_save(c, n & 1, n / K);
-    launch_step<T>(c, false, n, n & 1, false, last, n >= last);
+  const int K = c->ck, S = c->nseg, last = (S - 1) * K, N = c->N;
+  const int seglen = S > 1 ? K : N;
+  for (int a = 0; a < N; a += seglen) {
+    const int b = std::min(a + seglen, N);
+    if (S > 1 && a < last) snap_save(c, a, a / K);
+    run_block<T>(c, false, false, a, b - a, [=](int j) { return a + j; }, last, [=](int j) { return a + j >= last; });
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[1], c->stream));
@@ -426,16 +531,16 @@ template <typename T>
 void run_adjoint(fdtd_ctx *c) {
   FDTD_HIP(hipEventRecord(c->ev[2], c->stream));
   const int K = c->ck, S = c->nseg, N = c->N;
-  int held = S - 1;
-  for (int m = N; m >= 1; --m) {
-    const int s = S > 1 ? (m - 1) / K : 0;
-    if (s != held) {
-      const int a = s * K, b = std::min(a + K, N);
-      snap_load(c, a & 1, s);
-      for (int n = a; n < b; ++n) launch_step<T>(c, true, n, n & 1, false, a, true);
-      held = s;
+  const int seglen = S > 1 ? K : N;
+  const int nseg = (N + seglen - 1) / seglen;
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int a = s * seglen, b = std::min(a + seglen, N);
+    if (S > 1 && s != S - 1) {
+      snap_load(c, a, s);
+      run_block<T>(c, true, false, a, b - a, [=](int j) { return a + j; }, a, [](int) { return true; });
     }
-    launch_step<T>(c, false, m, (N - m) & 1, true, s * K, false);
+    // adjoint steps m = b .. a+1 (the (N-b+1)-th .. (N-a)-th of the adjoint solve)
+    run_block<T>(c, false, true, N - b, b - a, [=](int j) { return b - j; }, a, [](int) { return false; });
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[3], c->stream));
