@@ -235,6 +235,7 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
     nd = int(np.prod(shape))
     net1 = view(net, 1)
     tnet = view(net, tune_batch) if tune_steps else None
+    tgen = torch.Generator(device=dev).manual_seed(1234)
     if tnet is not None:
         tnet.t = net.t
     ex = _Exact(w, alpha, radius)
@@ -329,7 +330,7 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
         td = time.perf_counter()
         clock["fallback"] += td - tc
         if tnet is not None:
-            _tune(tnet, data, tune_steps, tune_lr)
+            _tune(tnet, data, tune_steps, tune_lr, tgen)
         clock["tune"] += time.perf_counter() - td
         trace.append((time.perf_counter() - t0, F))
         if log:
@@ -344,12 +345,13 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
     return trace, stats
 
 
-def _tune(net, data, steps, lr):
+def _tune(net, data, steps, lr, gen=None):
     """A few Adam steps on minibatches holding the newest triple (`net` is a
-    view sharing the trained parameters and Adam state)."""
+    view sharing the trained parameters and Adam state; `gen` a seeded
+    generator, so runs repeat)."""
     n = data.n
     for _ in range(steps):
-        idx = torch.randint(0, n, (net.batch,), device=net.dev)
+        idx = torch.randint(0, n, (net.batch,), device=net.dev, generator=gen)
         idx[0] = n - 1
         rho, lf, G = data.batch(idx)
         net.forward(rho)
