@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, 
 // one 16-byte LDS read) and the weights of all nine taps, then each
 // wavefront (four pixel rows) runs nine taps x MT x 4 matrix instructions.
 // grid ((h/16) * (w/16), ceil(cout / (16*MT)), n).
+// Pipelined variant: a workgroup walks `tpw` pixel tiles; the next (tile,
+// chunk)'s input (and, with several chunks, its weights) is loaded into
+// registers before the current chunk's matrix instructions and written to
+// LDS after them; grid (ceil(tiles / tpw), ceil(cout / (16*MT)), n).
 constexpr int CC = 32;                  // input channels per chunk
 constexpr int XST = 40;                 // LDS stride between staged pixels (80 B: conflict-free 16 B reads)
 constexpr int WST = 40;                 // LDS stride between staged (tap, co) weight rows
@@ -209,18 +213,147 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
       }
 }
 
+// The same with the staging software-pipelined (see above): faster on the
+// deep layers with a few pixel tiles and several channel chunks, slower on
+// the wide ones (its prefetch registers leave one wavefront per SIMD).
+template <int MT>
+__global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cout, int h, int w,
+                                                               const uint16_t *__restrict__ x,
+                                                               const uint16_t *__restrict__ wt,
+                                                               const float *__restrict__ bias,
+                                                               float *__restrict__ z, uint16_t *__restrict__ a,
+                                                               const int tpw) {
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[HT * HT * XST];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * 16 * MT * WST];
+  constexpr int NXP = (HT * HT + BS - 1) / BS;           // halo pixels per thread (2)
+  constexpr int NWV = (9 * 16 * MT * 4 + BS - 1) / BS;   // 16-byte weight vectors per thread
+  const int n = blockIdx.z, nimg = gridDim.z, HW = h * w;
+  const int tilesx = w / TT, tiles = (h / TT) * tilesx;
+  const int tb = blockIdx.x * tpw, te = min(tiles, tb + tpw);
+  const int nch = cin / CC, steps = (te - tb) * nch;  // (pixel tile, channel chunk), chunk fastest
+  const int co0 = blockIdx.y * 16 * MT;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
+  const size_t cs = (size_t)nimg * HW;
+  const uint16_t *xn = x + (size_t)n * HW;
+  uint32_t xr[NXP][CC / 2];
+  uint4 wr[NWV];
+  // global -> registers for step (tile, c0); registers -> LDS after the barrier
+  auto load_x = [&](int tile, int c0) {
+    const int y0 = (tile / tilesx) * TT, x0 = (tile % tilesx) * TT;
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      const int pos = t + k * BS;
+      const int r = pos / HT, q = pos - r * HT;
+      const int iy = y0 - 1 + r, ix = x0 - 1 + q;
+      const bool ok = pos < HT * HT && iy >= 0 && iy < h && ix >= 0 && ix < w;
+      const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
+#pragma unroll
+      for (int j = 0; j < CC / 2; ++j) {
+        const uint32_t lo = ok ? src[(size_t)(2 * j) * cs] : 0u;
+        const uint32_t hi = ok ? src[(size_t)(2 * j + 1) * cs] : 0u;
+        xr[k][j] = lo | (hi << 16);
+      }
+    }
+  };
+  auto store_x = [&]() {
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      const int pos = t + k * BS;
+      if (pos < HT * HT) {
+#pragma unroll
+        for (int c8 = 0; c8 < CC / 8; ++c8)
+          *(uint4 *)(Xs + pos * XST + 8 * c8) = uint4{xr[k][4 * c8], xr[k][4 * c8 + 1], xr[k][4 * c8 + 2], xr[k][4 * c8 + 3]};
+      }
+    }
+  };
+  auto load_w = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < NWV; ++k) {
+      const int v = t + k * BS;
+      const int part = v & 3, row = v >> 2;
+      const int tap = row / (16 * MT), col = row - tap * (16 * MT), co = co0 + col;
+      wr[k] = uint4{0u, 0u, 0u, 0u};
+      if (v < 9 * 16 * MT * 4 && co < cout) wr[k] = *(const uint4 *)(wt + ((size_t)co * 9 + tap) * cin + c0 + 8 * part);
+    }
+  };
+  auto store_w = [&]() {
+#pragma unroll
+    for (int k = 0; k < NWV; ++k) {
+      const int v = t + k * BS;
+      if (v < 9 * 16 * MT * 4) *(uint4 *)(Ws + (v >> 2) * WST + 8 * (v & 3)) = wr[k];
+    }
+  };
+  if (steps <= 0) return;
+  f4 acc[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
+  load_w(0);
+  load_x(tb, 0);
+  for (int st = 0; st < steps; ++st) {
+    const int tile = tb + st / nch, ch = st - (st / nch) * nch;
+    if (st == 0 || nch > 1) store_w();  // one chunk: the weights stay for every tile
+    store_x();
+    __syncthreads();
+    if (st + 1 < steps) {  // the next step's loads fly while the matrix cores work
+      const int nt = tb + (st + 1) / nch, nc = (st + 1) - ((st + 1) / nch) * nch;
+      if (nch > 1) load_w(nc * CC);
+      load_x(nt, nc * CC);
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap - 3 * ky;
+      bf8 av[MT], bv[4];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) av[m] = *(const bf8 *)(Ws + (tap * 16 * MT + 16 * m + l16) * WST + 8 * kq);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[s] = *(const bf8 *)(Xs + ((4 * wave + s + ky) * HT + l16 + kx) * XST + 8 * kq);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[s], acc[m][s], 0, 0, 0);
+    }
+    if (ch == nch - 1) {  // the tile's last chunk: write it out
+      const int y0 = (tile / tilesx) * TT, x0 = (tile % tilesx) * TT;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int co = co0 + 16 * m + 4 * kq + j;
+            if (co < cout) {
+              const float v = acc[m][s][j] + (bias ? bias[co] : 0.f);
+              const size_t o = (size_t)co * cs + (size_t)n * HW + (size_t)(y0 + 4 * wave + s) * w + x0 + l16;
+              if (z) z[o] = v;
+              if (a) a[o] = f2bf(fmaxf(v, 0.f));
+            }
+          }
+          acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    __syncthreads();
+  }
+}
+
 // One forward convolution launch: the LDS-tiled kernel where the shape and
 // the weight alignment allow it, else the generic one.
 void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, const uint16_t *wt, const float *bias,
                  float *z, uint16_t *a, hipStream_t s) {
   if (cin % CC == 0 && h % TT == 0 && w % TT == 0 && ((uintptr_t)wt & 15) == 0) {
-    if (cout <= 32) {
-      const dim3 g((h / TT) * (w / TT), (cout + 31) / 32, n);
-      hipLaunchKernelGGL(conv_fwd_mfma_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
-    } else {
-      const dim3 g((h / TT) * (w / TT), (cout + 63) / 64, n);
-      hipLaunchKernelGGL(conv_fwd_mfma_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+    const int tiles = (h / TT) * (w / TT), cot = cout <= 32 ? (cout + 31) / 32 : (cout + 63) / 64;
+    if (tiles <= 4 && cin > CC) {  // deep layers: pipelined staging, one tile per workgroup (measured)
+      const dim3 g(tiles, cot, n);
+      if (cout <= 32)
+        hipLaunchKernelGGL(conv_fwd_mfma_pipe_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a, 1);
+      else
+        hipLaunchKernelGGL(conv_fwd_mfma_pipe_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a, 1);
+      return;
     }
+    const dim3 g(tiles, cot, n);
+    if (cout <= 32) hipLaunchKernelGGL(conv_fwd_mfma_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+    else hipLaunchKernelGGL(conv_fwd_mfma_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
     return;
   }
   const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
