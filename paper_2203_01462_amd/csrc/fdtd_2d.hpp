@@ -7,10 +7,12 @@
 
 namespace fdtd {
 
-// Everything one launch of the fused 2D step reads.  Field, absorber-memory
-// and H arrays come in two copies (index par = read copy, par^1 = write copy)
-// because a tile recomputes its halo of H from the previous step's values
-// while neighbouring tiles are already writing theirs.
+// Everything one launch of the fused 2D step reads.  Field and
+// absorber-memory arrays are given as a read copy [par] and a write copy
+// [par^1] because a tile recomputes its halo of H from the previous step's
+// values while neighbouring tiles are already writing theirs (the host
+// resolves which physical copies these are: two rotating copies, or three
+// for the fields under two-step blocking).
 template <typename T>
 struct Step2D {
   int nx, ny, pitch, P;
