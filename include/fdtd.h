@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 3
+#define FDTD_ABI_VERSION 4
 
 typedef enum {
   FDTD_OK = 0,
@@ -172,11 +172,14 @@ fdtd_status fdtd_destroy(fdtd_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Batches of 2D instances.  Uneven TMz problems (own grid size, density,
- * damping, band, objective) advance together: each time step of all
- * instances is one launch per tile depth in use, and the N steps of a forward
- * (or adjoint) solve are captured once into a HIP graph and replayed.  Every
- * instance computes exactly what a single context with the same config and
- * tile depth computes.
+ * damping, band, objective) advance together: at temporal-block depth 1 each
+ * time step of all instances is one launch per tile depth in use; at depth 2
+ * the instances follow the blocked schedule of a single context (plain
+ * background super-tiles advance two steps per pass, everything else one
+ * step per launch, two launches per pair of steps for all instances
+ * together).  The N steps of a forward (or adjoint) solve are captured once
+ * into a HIP graph and replayed.  Every instance computes exactly what a
+ * single context with the same config and tile depth computes.
  */
 typedef struct fdtd_batch fdtd_batch; /* opaque */
 
@@ -187,13 +190,21 @@ typedef struct {
                          then try the other depths for each grid size in turn
                          and keep what is faster */
   int32_t use_graph;  /* 1: replay the captured step sequence; 0: launch eagerly */
+  int32_t depth;      /* temporal-block depth: 1 = one step per launch; 2 = the
+                         blocked schedule for every instance that has
+                         plain-background super-tiles (needs rows 0 or 2; the
+                         tile depth is then 2); 0 = tune at creation: time the
+                         best depth-1 choice against depth 2, try depth 1 for
+                         each grid size in turn inside the blocked schedule,
+                         keep what is faster */
 } fdtd_batch_options;
 
 /* Create `count` >= 1 instances from cfgs[0..count-1]: all dims = 2, the same
  * precision and n_steps, ckpt_every = 0.  All instances run on one stream:
  * cfgs[0].stream (the other streams are ignored) or one the library creates.
- * opt may be NULL (rows = 0, use_graph = 1).  Fails like fdtd_create (the
- * message names the instance), or EINVAL for mixed precision / step counts. */
+ * opt may be NULL (rows = 0, use_graph = 1, depth = 0).  Fails like
+ * fdtd_create (the message names the instance), or EINVAL for mixed
+ * precision / step counts or options out of range. */
 fdtd_status fdtd_batch_create(const fdtd_config *cfgs, int32_t count, const fdtd_batch_options *opt,
                               fdtd_batch **out);
 
@@ -213,6 +224,9 @@ fdtd_status fdtd_batch_gradient(fdtd_batch *b, int32_t index, void *grad_out, in
 /* Tile depth used for instance `index`, and the event time (ms) of the last
  * batched forward and adjoint step sequences (all instances together). */
 fdtd_status fdtd_batch_info(fdtd_batch *b, int32_t index, int32_t *rows_out, double *forward_ms, double *adjoint_ms);
+
+/* Temporal-block depth (1 or 2) used for instance `index`. */
+fdtd_status fdtd_batch_depth(fdtd_batch *b, int32_t index, int32_t *depth_out);
 
 /* Release the batch and all instances.  NULL is accepted. */
 fdtd_status fdtd_batch_destroy(fdtd_batch *b);

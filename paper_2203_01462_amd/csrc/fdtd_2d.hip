@@ -655,10 +655,54 @@ __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
   tb_block<T>(pt, tiles[b - nrest], ezo, hxo, hyo, E, HX, HY);
 }
 
+// Last k with f[k] <= b.
+__device__ __forceinline__ int owner(const cptr2<int> f, const int ninst, const int b) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (f[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The blocked schedule of several instances in one launch: the per-step
+// workgroups of every instance, then the two-step ones.  An instance's
+// descriptor part is copied into registers with scalar loads.
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
+    step2d_batch_mix_kernel(const Mix2D<T> *ds, const int *firstR, const int *firstT, const int ninst,
+                            const int nrest_total, const int n) {
+  __shared__ T E[TLY * TLS], HX[TLY * TLS], HY[TLY * TLS];
+  static_assert(sizeof(Step2D<T>) % 4 == 0, "parameter block copied as 32-bit words");
+  const int b = blockIdx.x;
+  const bool rest = b < nrest_total;
+  const cptr2<int> f = (cptr2<int>)(rest ? firstR : firstT);
+  const int bb = rest ? b : b - nrest_total;
+  const int k = owner(f, ninst, bb);
+  const int lb = bb - f[k];
+  const cptr2<Mix2D<T>> d = (cptr2<Mix2D<T>>)(ds + k);
+  Step2D<T> p;
+  int *dst = reinterpret_cast<int *>(&p);
+  if (rest) {
+    if (lb >= d->nrest) return;  // padding
+    const cptr2<int> src = (cptr2<int>)(&(ds + k)->ps);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(Step2D<T>) / 4); ++w) dst[w] = src[w];
+    step2d_block<T, ADJ, RDEF>(p, n, 0, lb);
+    return;
+  }
+  if (lb >= d->ntb) return;
+  const cptr2<int> src = (cptr2<int>)(&(ds + k)->pt);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(Step2D<T>) / 4); ++w) dst[w] = src[w];
+  tb_block<T>(p, d->tiles[lb], d->ezo, d->hxo, d->hyo, E, HX, HY);
+}
+
 
 }  // namespace
 
 int step2d_blocks(int nx, int ny, int rows) {
+  if (rows <= 0) rows = RDEF;
   const int nbx = (nx + TXW - 1) / TXW, nby = (ny + WAVES * rows - 1) / (WAVES * rows);
   return nbx * nby;
 }
@@ -728,6 +772,18 @@ void launch_step2d_mix(const Step2D<T> &ps, int n, int nrest, const Step2D<T> &p
 }
 
 template <typename T>
+void launch_step2d_batch_mix(const Mix2D<T> *ds, const int *firstR, const int *firstT, int ninst, int nrest_total,
+                             int nblocks, int n, bool adjoint, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (adjoint)
+    hipLaunchKernelGGL((step2d_batch_mix_kernel<T, true>), dim3(nblocks), dim3(NT), 0, s, ds, firstR, firstT, ninst,
+                       nrest_total, n);
+  else
+    hipLaunchKernelGGL((step2d_batch_mix_kernel<T, false>), dim3(nblocks), dim3(NT), 0, s, ds, firstR, firstT, ninst,
+                       nrest_total, n);
+}
+
+template <typename T>
 void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows) {
   if (rows <= 0) rows = RDEF;
   if (adjoint) launch_one<T, true>(p, n, par, rows, s);
@@ -754,6 +810,10 @@ template void launch_step2d_mix<float>(const Step2D<float> &, int, int, const St
                                        float *, float *, float *, bool, hipStream_t);
 template void launch_step2d_mix<double>(const Step2D<double> &, int, int, const Step2D<double> &, const int *, int,
                                         double *, double *, double *, bool, hipStream_t);
+template void launch_step2d_batch_mix<float>(const Mix2D<float> *, const int *, const int *, int, int, int, int, bool,
+                                             hipStream_t);
+template void launch_step2d_batch_mix<double>(const Mix2D<double> *, const int *, const int *, int, int, int, int,
+                                              bool, hipStream_t);
 template void launch_step2d<float>(const Step2D<float> &, int, int, bool, hipStream_t, int);
 template void launch_step2d<double>(const Step2D<double> &, int, int, bool, hipStream_t, int);
 template void launch_step2d_batch<float>(const Step2D<float> *, const int *, int, int, int, int, bool, int, hipStream_t);

@@ -47,7 +47,7 @@ struct Step2D {
 template <typename T>
 void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows = 0);
 
-// Workgroups of one instance's step launch.
+// Workgroups of one instance's step launch (rows <= 0: the default depth).
 int step2d_blocks(int nx, int ny, int rows);
 
 // Two-step blocking of the plain background.  Super-tiles of 64 x 16 nodes
@@ -73,6 +73,27 @@ Tb2dPlan tb2d_plan(int nx, int ny, int P, int ia, int ib, int ja, int jb, const 
 template <typename T>
 void launch_step2d_mix(const Step2D<T> &ps, int n, int nrest, const Step2D<T> &pt, const int *tiles, int ntb, T *ezo,
                        T *hxo, T *hyo, bool adjoint, hipStream_t s);
+
+// One instance's part of a batched launch of the blocked schedule: nrest
+// workgroups take the per-step update of the tiles in ps.tlist (the whole
+// grid when null), ntb workgroups advance tiles[0..ntb) by the pair
+// described by pt (as in launch_step2d_mix).  Parities are resolved.
+template <typename T>
+struct Mix2D {
+  Step2D<T> ps, pt;
+  T *ezo, *hxo, *hyo;
+  const int *tiles;
+  int nrest, ntb;
+};
+
+// One launch of the blocked schedule over several instances (device array
+// `ds`): the per-step workgroups of all instances first (instance k from
+// firstR[k], nrest_total in all), then their two-step workgroups (instance k
+// from nrest_total + firstT[k]); each instance's counts padded to a multiple
+// of 8.
+template <typename T>
+void launch_step2d_batch_mix(const Mix2D<T> *ds, const int *firstR, const int *firstT, int ninst, int nrest_total,
+                             int nblocks, int n, bool adjoint, hipStream_t s);
 
 // One time step of several instances (device array `ps` of their parameters,
 // `first[k]` = first workgroup of instance k, blocks of each instance padded

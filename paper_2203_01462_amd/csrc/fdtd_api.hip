@@ -602,8 +602,18 @@ struct fdtd_batch {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int prec = 64, N = 0;
-  fdtd_batch_options opt{0, 1};
+  fdtd_batch_options opt{0, 1, 0};
   std::vector<int> rows;  // tile depth per instance
+  // Two-step blocking: with `mix` every step goes through the blocked
+  // schedule (two rows per thread everywhere); tb[k] = instance k advances
+  // its plain-background super-tiles two steps per pass.
+  bool mix = false;
+  std::vector<int> tb;
+  struct MixLaunch {  // descriptor table of one launch of the blocked schedule
+    DevBuf desc, firstR, firstT;
+    int nrest = 0, nblocks = 0;
+  };
+  std::map<int, MixLaunch> mixl;  // by launch kind * 6 + (step index mod 6)
   struct Group {          // instances sharing one tile depth: one launch per step
     int R = 2, nblocks = 0;
     std::vector<int> members;
@@ -639,9 +649,91 @@ void batch_step(fdtd_batch *b, int n, int par, bool adjoint) {
                            adjoint, g.R, b->stream);
 }
 
+// Launch kinds of the blocked schedule (see run_block): the first pair's
+// launch A (every super-tile), launch A, launch B with the next pair's early
+// super-tiles, the last pair's launch B, a full-grid single step.
+enum { MIX_A0, MIX_A, MIX_B, MIX_BLAST, MIX_SINGLE };
+
+// The descriptor table of launch `kind` whose per-step part is the (s+1)-th
+// step of its solve (field copies repeat with period 3, absorber memories
+// with period 2).  Built and uploaded on first use, outside graph capture.
+template <typename T>
+fdtd_batch::MixLaunch &mix_launch(fdtd_batch *b, int kind, int s) {
+  const int key = kind * 6 + s % 6;
+  auto it = b->mixl.find(key);
+  if (it != b->mixl.end()) return it->second;
+  const int cnt = (int)b->inst.size();
+  std::vector<Mix2D<T>> ds(cnt);
+  std::vector<int> fr(cnt), ft(cnt);
+  int nr = 0, nt = 0;
+  for (int k = 0; k < cnt; ++k) {
+    fdtd_ctx *c = b->inst[k];
+    const bool on = b->tb[k] && c->nTb > 0 && kind != MIX_SINGLE;
+    Mix2D<T> d{};
+    d.ps = params2d_at<T>(c, false, s, 0, true);
+    d.ps.tlist = on ? c->tbRest.as<int>() : nullptr;
+    d.nrest = on ? c->nRest : step2d_blocks(c->nx, c->ny, 0);
+    int first = 0, count = 0, sp = s;  // super-tiles [first, first+count) of the pair entered after sp steps
+    if (on && kind == MIX_A0) count = c->nTb;
+    if (on && kind == MIX_A) {
+      first = c->nEarly;
+      count = c->nTb - c->nEarly;
+    }
+    if (on && kind == MIX_B) {
+      count = c->nEarly;
+      sp = s + 1;
+    }
+    d.pt = params2d_at<T>(c, false, sp, 0, true);
+    if (count > 0) {
+      d.tiles = c->tbTiles.as<int>() + first;
+      d.ntb = count;
+      d.ezo = field_buf(c, false, fcopy(c, sp + 2), 0)->as<T>();
+      d.hxo = field_buf(c, false, fcopy(c, sp + 2), 1)->as<T>();
+      d.hyo = field_buf(c, false, fcopy(c, sp + 2), 2)->as<T>();
+    }
+    ds[k] = d;
+    fr[k] = nr;
+    ft[k] = nt;
+    nr += (d.nrest + 7) / 8 * 8;  // keeps the XCD in the low bits of a whole-grid tile index
+    nt += (d.ntb + 7) / 8 * 8;
+  }
+  fdtd_batch::MixLaunch &m = b->mixl[key];
+  upload(b->stream, m.desc, ds);
+  upload(b->stream, m.firstR, fr);
+  upload(b->stream, m.firstT, ft);
+  FDTD_HIP(hipStreamSynchronize(b->stream));
+  m.nrest = nr;
+  m.nblocks = nr + nt;
+  return m;
+}
+
+// `count` steps of the blocked schedule from the start of a solve (forward:
+// step n = s; adjoint: m = N - s), as run_block pipelines them.  With
+// `build_only` the descriptor tables are made and nothing is launched.
+template <typename T>
+void batch_mix_steps(fdtd_batch *b, bool adjoint, int count, bool build_only = false) {
+  const int N = b->N, cnt = (int)b->inst.size();
+  auto go = [&](int kind, int s) {
+    fdtd_batch::MixLaunch &m = mix_launch<T>(b, kind, s);
+    if (!build_only)
+      launch_step2d_batch_mix<T>(m.desc.as<Mix2D<T>>(), m.firstR.as<int>(), m.firstT.as<int>(), cnt, m.nrest,
+                                 m.nblocks, adjoint ? N - s : s, adjoint, b->stream);
+  };
+  const int P = count / 2;
+  for (int q = 0; q < P; ++q) {
+    go(q == 0 ? MIX_A0 : MIX_A, 2 * q);
+    go(q + 1 < P ? MIX_B : MIX_BLAST, 2 * q + 1);
+  }
+  if (count & 1) go(MIX_SINGLE, count - 1);
+}
+
 template <typename T>
 void batch_steps(fdtd_batch *b, bool adjoint) {
   const int N = b->N;
+  if (b->mix) {
+    batch_mix_steps<T>(b, adjoint, N);
+    return;
+  }
   if (!adjoint)
     for (int n = 0; n < N; ++n) batch_step<T>(b, n, n & 1, false);
   else
@@ -712,18 +804,28 @@ float time_batch(fdtd_batch *b, int steps) {
   return ms;
 }
 
-// Tile depths: fixed, or tuned on the batch itself -- the fastest uniform
-// depth, then one pass over the grid sizes trying the other depths for all
-// instances of that size.
+// Event time of `steps` forward steps of the blocked schedule with the
+// current two-step flags (from the start of a solve; states are scratch).
 template <typename T>
-void batch_setup(fdtd_batch *b) {
+float time_mix(fdtd_batch *b, int steps) {
+  b->mixl.clear();
+  batch_mix_steps<T>(b, false, steps, true);
+  batch_mix_steps<T>(b, false, std::min(4, steps));
+  FDTD_HIP(hipEventRecord(b->ev[0], b->stream));
+  batch_mix_steps<T>(b, false, steps);
+  FDTD_HIP(hipEventRecord(b->ev[1], b->stream));
+  FDTD_HIP(hipEventSynchronize(b->ev[1]));
+  float ms = 0;
+  FDTD_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+  return ms;
+}
+
+// Per-step tile depths tuned on the batch: the fastest uniform depth, then
+// one pass over the grid sizes trying the other depths for all instances of
+// that size.  Returns the time of `steps` batched steps with the choice.
+template <typename T>
+float tune_rows(fdtd_batch *b, const std::vector<std::pair<int, int>> &sizes, int steps) {
   const int cnt = (int)b->inst.size();
-  if (b->opt.rows > 0) {
-    b->rows.assign(cnt, b->opt.rows);
-    build_groups<T>(b);
-    return;
-  }
-  const int steps = 20;
   float best = 1e30f;
   int bestR = 2;
   for (int R : {1, 2, 4}) {
@@ -735,9 +837,6 @@ void batch_setup(fdtd_batch *b) {
     }
   }
   b->rows.assign(cnt, bestR);
-  std::vector<std::pair<int, int>> sizes;
-  for (fdtd_ctx *c : b->inst)
-    if (std::find(sizes.begin(), sizes.end(), std::make_pair(c->nx, c->ny)) == sizes.end()) sizes.push_back({c->nx, c->ny});
   if (sizes.size() > 1) {
     for (auto sz : sizes) {
       for (int R : {1, 2, 4}) {
@@ -757,6 +856,71 @@ void batch_setup(fdtd_batch *b) {
       }
     }
   }
+  return best;
+}
+
+// Temporal-block depth and tile depth: fixed by the options, or tuned on the
+// batch.  Depth 1 = one launch per tile-depth group per step; depth 2 = the
+// blocked schedule, where instances with plain-background super-tiles
+// advance them two steps per pass (the others take per-step launches inside
+// it).  Tuning times the best depth-1 choice against depth 2, then tries
+// depth 1 for the instances of each grid size in turn within the blocked
+// schedule and keeps what is faster.
+template <typename T>
+void batch_setup(fdtd_batch *b) {
+  const int cnt = (int)b->inst.size();
+  const int steps = std::min(20, b->N);
+  std::vector<std::pair<int, int>> sizes;
+  bool any_tb = false;
+  for (fdtd_ctx *c : b->inst) {
+    any_tb = any_tb || c->nTb > 0;
+    if (std::find(sizes.begin(), sizes.end(), std::make_pair(c->nx, c->ny)) == sizes.end()) sizes.push_back({c->nx, c->ny});
+  }
+  b->mix = false;
+  b->tb.assign(cnt, 0);
+  const bool can_mix = any_tb && b->opt.depth != 1 && (b->opt.rows == 0 || b->opt.rows == 2);
+  if (b->opt.depth == 2 && can_mix) {
+    b->mix = true;
+  } else if (b->opt.depth == 0 && can_mix) {
+    float t1;
+    if (b->opt.rows > 0) {
+      b->rows.assign(cnt, b->opt.rows);
+      t1 = time_batch<T>(b, steps);
+    } else {
+      t1 = tune_rows<T>(b, sizes, steps);
+    }
+    for (int k = 0; k < cnt; ++k) b->tb[k] = b->inst[k]->nTb > 0;
+    float t2 = time_mix<T>(b, steps);
+    if (sizes.size() > 1) {
+      for (auto sz : sizes) {
+        const std::vector<int> keep = b->tb;
+        bool changed = false;
+        for (int k = 0; k < cnt; ++k)
+          if (b->inst[k]->nx == sz.first && b->inst[k]->ny == sz.second && b->tb[k]) {
+            b->tb[k] = 0;
+            changed = true;
+          }
+        if (!changed) continue;
+        const float t = time_mix<T>(b, steps);
+        if (t < t2) t2 = t;
+        else b->tb = keep;
+      }
+    }
+    b->mix = t2 < t1 && std::find(b->tb.begin(), b->tb.end(), 1) != b->tb.end();
+  }
+  if (b->mix) {
+    if (std::find(b->tb.begin(), b->tb.end(), 1) == b->tb.end())
+      for (int k = 0; k < cnt; ++k) b->tb[k] = b->inst[k]->nTb > 0;
+    b->rows.assign(cnt, 2);
+    b->groups.clear();
+    b->mixl.clear();
+    batch_mix_steps<T>(b, false, b->N, true);  // the adjoint uses the same tables
+    return;
+  }
+  b->tb.assign(cnt, 0);
+  b->mixl.clear();
+  if (b->opt.rows > 0) b->rows.assign(cnt, b->opt.rows);
+  else if (b->rows.size() != (size_t)cnt) tune_rows<T>(b, sizes, steps);
   build_groups<T>(b);
 }
 
@@ -965,6 +1129,9 @@ fdtd_status fdtd_batch_create(const fdtd_config *cfgs, int32_t count, const fdtd
     if (opt) b->opt = *opt;
     if (b->opt.rows != 0 && b->opt.rows != 1 && b->opt.rows != 2 && b->opt.rows != 4)
       throw einval("batch rows must be 0, 1, 2 or 4");
+    if (b->opt.depth < 0 || b->opt.depth > 2) throw einval("batch depth must be 0, 1 or 2");
+    if (b->opt.depth == 2 && b->opt.rows != 0 && b->opt.rows != 2)
+      throw einval("two-step blocking runs two rows per thread (rows 0 or 2)");
     for (int k = 0; k < count; ++k) {
       if (cfgs[k].dims != 2) throw einval("batch instance " + std::to_string(k) + ": batches hold 2D instances");
       if (cfgs[k].precision != cfgs[0].precision) throw einval("batch instances must share the precision");
@@ -1069,6 +1236,15 @@ fdtd_status fdtd_batch_info(fdtd_batch *b, int32_t index, int32_t *rows_out, dou
     if (rows_out) *rows_out = b->rows[index];
     if (forward_ms) *forward_ms = b->ms[0];
     if (adjoint_ms) *adjoint_ms = b->ms[1];
+  });
+}
+
+fdtd_status fdtd_batch_depth(fdtd_batch *b, int32_t index, int32_t *depth_out) {
+  if (!b) return FDTD_EINVAL;
+  return bguard(b, [&] {
+    fdtd_ctx *c = instance(b, index);
+    if (!depth_out) throw einval("null depth pointer");
+    *depth_out = b->mix && b->tb[index] && c->nTb > 0 ? 2 : 1;
   });
 }
 

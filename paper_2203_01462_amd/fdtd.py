@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 C0 = 299792458.0
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSTABLE"}
@@ -61,14 +61,14 @@ class Timing(C.Structure):
 
 
 class BatchOptions(C.Structure):
-    _fields_ = [("rows", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("rows", C.c_int32), ("use_graph", C.c_int32), ("depth", C.c_int32)]
 
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint",
            "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error",
            "fdtd_batch_create", "fdtd_batch_set_density", "fdtd_batch_forward", "fdtd_batch_adjoint",
-           "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_destroy", "fdtd_batch_last_error",
+           "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_depth", "fdtd_batch_destroy", "fdtd_batch_last_error",
            # include/fdtd_design.h
            "fdtd_filter_create", "fdtd_filter_apply", "fdtd_filter_transpose", "fdtd_filter_destroy",
            "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
@@ -113,6 +113,7 @@ def load_library(path=LIB_PATH):
     L.fdtd_batch_adjoint.argtypes = [P]
     L.fdtd_batch_gradient.argtypes = [P, C.c_int32, P, C.c_int64, C.c_int32]
     L.fdtd_batch_info.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.fdtd_batch_depth.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
     L.fdtd_batch_destroy.argtypes = [P]
     L.fdtd_batch_last_error.argtypes = [P]
     L.fdtd_batch_last_error.restype = C.c_char_p
@@ -164,7 +165,7 @@ def load_library(path=LIB_PATH):
     for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
                "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_batch_create", "fdtd_batch_set_density",
                "fdtd_batch_forward", "fdtd_batch_adjoint", "fdtd_batch_gradient", "fdtd_batch_info",
-               "fdtd_batch_destroy"):
+               "fdtd_batch_depth", "fdtd_batch_destroy"):
         getattr(L, fn).restype = C.c_int
     if L.fdtd_abi_version() != ABI_VERSION:
         raise ImportError("libfdtd_hip.so ABI version mismatch")
@@ -306,9 +307,11 @@ class FDTD:
 
 class Batch:
     """Uneven 2D instances advanced together (fdtd_batch_*): one launch per
-    tile depth per time step, the step sequences replayed from HIP graphs."""
+    tile depth per time step (depth 1) or the two-step blocked schedule
+    (depth 2), the step sequences replayed from HIP graphs.  rows = 0 and
+    depth = 0 tune on the batch at creation."""
 
-    def __init__(self, ws, stream=None, rows=0, use_graph=True):
+    def __init__(self, ws, stream=None, rows=0, use_graph=True, depth=0):
         L = load_library()
         self.ws = [dict(w) for w in ws]
         cfgs = (Config * len(ws))()
@@ -317,7 +320,7 @@ class Batch:
             c, kp = make_config(w, stream if k == 0 else None)
             cfgs[k] = c
             keep.append(kp)
-        opt = BatchOptions(int(rows), 1 if use_graph else 0)
+        opt = BatchOptions(int(rows), 1 if use_graph else 0, int(depth))
         h = C.c_void_p()
         rc = L.fdtd_batch_create(cfgs, len(ws), C.byref(opt), C.byref(h))
         if rc:
@@ -373,4 +376,6 @@ class Batch:
         f = C.c_double()
         a = C.c_double()
         self._check(load_library().fdtd_batch_info(self.h, k, C.byref(r), C.byref(f), C.byref(a)))
-        return {"rows": r.value, "forward_ms": f.value, "adjoint_ms": a.value}
+        d = C.c_int32()
+        self._check(load_library().fdtd_batch_depth(self.h, k, C.byref(d)))
+        return {"rows": r.value, "depth": d.value, "forward_ms": f.value, "adjoint_ms": a.value}

@@ -47,17 +47,20 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_binding_struct_layout_matches_the_header(tmp_path):
-    """The ctypes mirror of fdtd_config / fdtd_timing has the C layout
-    (sizes and every field offset, from a C program compiled against the header)."""
+    """The ctypes mirrors of fdtd_config / fdtd_timing / fdtd_batch_options
+    have the C layout (sizes and every field offset, from a C program
+    compiled against the header)."""
     import ctypes
     import subprocess
     from paper_2203_01462_amd import fdtd as F
     fields = [f for f, _ in F.Config._fields_]
     tfields = [f for f, _ in F.Timing._fields_]
+    bfields = [f for f, _ in F.BatchOptions._fields_]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "fdtd.h"', "int main(void) {",
-           'printf("%zu %zu\\n", sizeof(fdtd_config), sizeof(fdtd_timing));']
+           'printf("%zu %zu %zu\\n", sizeof(fdtd_config), sizeof(fdtd_timing), sizeof(fdtd_batch_options));']
     src += [f'printf("%zu\\n", offsetof(fdtd_config, {f}));' for f in fields]
     src += [f'printf("%zu\\n", offsetof(fdtd_timing, {f}));' for f in tfields]
+    src += [f'printf("%zu\\n", offsetof(fdtd_batch_options, {f}));' for f in bfields]
     src += ["return 0; }"]
     (tmp_path / "l.c").write_text("\n".join(src))
     exe = str(tmp_path / "l")
@@ -65,8 +68,11 @@ def test_binding_struct_layout_matches_the_header(tmp_path):
     out = subprocess.check_output([exe]).decode().split()
     vals = [int(v) for v in out]
     assert vals[0] == ctypes.sizeof(F.Config) and vals[1] == ctypes.sizeof(F.Timing)
-    assert vals[2:2 + len(fields)] == [getattr(F.Config, f).offset for f in fields]
-    assert vals[2 + len(fields):] == [getattr(F.Timing, f).offset for f in tfields]
+    assert vals[2] == ctypes.sizeof(F.BatchOptions)
+    a, b = 3 + len(fields), 3 + len(fields) + len(tfields)
+    assert vals[3:a] == [getattr(F.Config, f).offset for f in fields]
+    assert vals[a:b] == [getattr(F.Timing, f).offset for f in tfields]
+    assert vals[b:] == [getattr(F.BatchOptions, f).offset for f in bfields]
 
 
 @pytest.mark.parametrize("over,msg", [

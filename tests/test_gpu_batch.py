@@ -2,8 +2,9 @@
 gives the objective, gap DFT and gradient of a single context with the same
 config and tile depth, bit for bit, whether the step sequence runs eagerly or
 is replayed from the captured graph (several replays with eager work between
-them), for every tile depth and with the autotuned depths.  Calls go through
-the C ABI."""
+them), at temporal-block depth 1 (every tile depth) and 2 (the blocked
+schedule, odd and even step counts) and with the autotuned depths.  Calls go
+through the C ABI."""
 import numpy as np
 import pytest
 
@@ -33,8 +34,8 @@ def singles(gpu, ws, rhos):
     return out
 
 
-def run_batch(gpu, ws, rhos, rows, use_graph, repeats=1):
-    b = gpu.Batch(ws, rows=rows, use_graph=use_graph)
+def run_batch(gpu, ws, rhos, rows, use_graph, repeats=1, depth=0):
+    b = gpu.Batch(ws, rows=rows, use_graph=use_graph, depth=depth)
     for k, r in enumerate(rhos):
         b.set_density(k, r.astype(b.dtype))
     res = []
@@ -46,24 +47,34 @@ def run_batch(gpu, ws, rhos, rows, use_graph, repeats=1):
         g = gpu.FDTD(ws[0])
         g.run(rhos[0].astype(g.dtype))
         g.close()
-    depths = [b.info(k)["rows"] for k in range(len(ws))]
+    info = [b.info(k) for k in range(len(ws))]
     b.close()
-    return res, depths
+    return res, [i["rows"] for i in info], [i["depth"] for i in info]
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_batch_matches_single_contexts(gpu, prec):
+def has_super_tiles(w):
+    from test_gpu_blocking import super_tiles
+    return super_tiles(w) > 0
+
+
+@pytest.mark.parametrize("prec,depth,n_steps", [(64, 1, 400), (64, 2, 400), (64, 2, 401), (32, 1, 400),
+                                                (32, 2, 401)])
+def test_batch_matches_single_contexts(gpu, prec, depth, n_steps):
     """FP64: every instance bit-identical to its single context.  FP32: the
-    batched kernel is separately compiled code, so single-ulp rounding may
+    batched kernels are separately compiled code, so single-ulp rounding may
     differ (observed 7.5e-10 on F); bars 1e-6 on F, 1e-5 on the gradient.
     Graph replays (three, with eager work between them) are bit-identical
-    to the eager batch in both precisions."""
-    ws = uneven(400, precision=prec)
+    to the eager batch in both precisions.  At depth 2 the instances with
+    plain-background super-tiles (sides 160 and up) take the blocked schedule
+    and the small ones per-step launches inside it."""
+    ws = uneven(n_steps, precision=prec, sides=(64, 160, 256, 384))
     rhos = [W.seeded_rho(w, k) for k, w in enumerate(ws)]
     ref = singles(gpu, ws, rhos)
-    (eager,), d0 = run_batch(gpu, ws, rhos, 2, False)
-    graph, d1 = run_batch(gpu, ws, rhos, 2, True, repeats=3)
+    (eager,), d0, b0 = run_batch(gpu, ws, rhos, 2, False, depth=depth)
+    graph, d1, b1 = run_batch(gpu, ws, rhos, 2, True, repeats=3, depth=depth)
     assert d0 == d1 == [2] * len(ws)
+    expect = [2 if depth == 2 and has_super_tiles(w) else 1 for w in ws]
+    assert b0 == b1 == expect, (b0, b1, expect)
     F, grads = eager
     for k in range(len(ws)):
         if prec == 64:
@@ -76,7 +87,8 @@ def test_batch_matches_single_contexts(gpu, prec):
         assert np.array_equal(Fg, F)
         for k in range(len(ws)):
             assert np.array_equal(gg[k], grads[k])
-    say(f"[batch] prec={prec}: {len(ws)} instances match single contexts; 3 graph replays identical")
+    say(f"[batch] prec={prec} depth={depth} N={n_steps}: {len(ws)} instances match single contexts; "
+        f"3 graph replays identical")
 
 
 def test_batch_tile_depths_agree(gpu):
@@ -84,7 +96,7 @@ def test_batch_tile_depths_agree(gpu):
     rhos = [W.seeded_rho(w, k) for k, w in enumerate(ws)]
     out = {}
     for rows in (1, 2, 4):
-        res, depths = run_batch(gpu, ws, rhos, rows, True)
+        res, depths, _ = run_batch(gpu, ws, rhos, rows, True, depth=1)
         assert depths == [rows] * len(ws)
         out[rows] = res[0]
     for rows in (1, 4):
@@ -97,10 +109,14 @@ def test_batch_tile_depths_agree(gpu):
 def test_batch_autotuned_depths(gpu):
     ws = uneven(300, precision=32, sides=(128, 512), count=4)
     rhos = [W.seeded_rho(w, k) for k, w in enumerate(ws)]
-    res, depths = run_batch(gpu, ws, rhos, 0, True)
-    say(f"[batch] autotuned depths {depths}")
-    assert all(d in (1, 2, 4) for d in depths)
-    assert depths[0] == depths[2] and depths[1] == depths[3]  # one choice per grid size (tuned on the batch)
+    res, depths, blocks = run_batch(gpu, ws, rhos, 0, True)
+    say(f"[batch] autotuned tile depths {depths}, temporal-block depths {blocks}")
+    assert all(d in (1, 2, 4) for d in depths) and all(d in (1, 2) for d in blocks)
+    # one choice per grid size (tuned on the batch)
+    assert depths[0] == depths[2] and depths[1] == depths[3]
+    assert blocks[0] == blocks[2] == 1 and blocks[1] == blocks[3]  # 128^2 has no super-tiles
+    if 2 in blocks:
+        assert depths == [2] * len(ws)
     F, grads = res[0]
     assert np.all(np.isfinite(F)) and all(np.all(np.isfinite(g)) for g in grads)
 
@@ -112,6 +128,10 @@ def test_batch_validation(gpu):
     assert e.value.name == "EINVAL"
     with pytest.raises(gpu.FDTDError):
         gpu.Batch([ws[0], W.tiny3d(precision=32)])
+    for opts in (dict(depth=3), dict(depth=-1), dict(depth=2, rows=4), dict(depth=2, rows=1)):
+        with pytest.raises(gpu.FDTDError) as e:
+            gpu.Batch(ws, **opts)
+        assert e.value.name == "EINVAL", opts
     b = gpu.Batch(ws)
     with pytest.raises(gpu.FDTDError) as e:
         b.forward()
@@ -131,7 +151,8 @@ def test_c4_batch_shape(gpu):
     F = b.forward()
     b.adjoint()
     info = [b.info(k) for k in range(len(ws))]
-    say(f"[batch] C4 shape: 64 instances, depths {sorted(set(i['rows'] for i in info))}, "
+    say(f"[batch] C4 shape: 64 instances, tile depths {sorted(set(i['rows'] for i in info))}, "
+        f"temporal-block depths by side {sorted(set((w['n'][0], i['depth']) for w, i in zip(ws, info)))}, "
         f"fwd {info[0]['forward_ms']:.1f} ms adj {info[0]['adjoint_ms']:.1f} ms for 300 steps")
     for k in (0, 17, 40, 63):
         g = gpu.FDTD(ws[k])

@@ -54,8 +54,9 @@ def test_blocked_schedule_bit_identical_to_per_step(gpu, n_steps):
     assert super_tiles(w) > 100
     rho = W.seeded_rho(w, 3)
     # two rows per thread, the single context's per-step variant (the row
-    # variants form the FP64 sensitivity sums in different orders)
-    b = gpu.Batch([w], rows=2)
+    # variants form the FP64 sensitivity sums in different orders), one step
+    # per launch
+    b = gpu.Batch([w], rows=2, depth=1)
     b.set_density(0, rho)
     F_ref = float(b.forward()[0])
     b.adjoint()
