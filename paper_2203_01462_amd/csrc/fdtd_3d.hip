@@ -46,8 +46,8 @@ constexpr int KC = FDTD3D_KC;  // planes per workgroup
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
 
-__device__ __forceinline__ bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
-__device__ __forceinline__ bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
+__host__ __device__ inline bool pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
+__host__ __device__ inline bool pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
 __device__ __forceinline__ int slab(int i, int n, int P) { return i < P ? i : i - (n - 1 - 2 * P); }
 
 // Element e of an arena (32-bit byte offsets).
@@ -77,10 +77,6 @@ __device__ __forceinline__ void block_of(int bid, int nbx, int nby, int nbz, int
   bz = bid / per;
 }
 
-struct TileBox {
-  int o[3], e[3];
-};
-
 struct Tile {
   int i0, j0, kb, ke;
   bool xy_plain;     // x/y reach holds no absorber, wall or injection face
@@ -91,7 +87,7 @@ struct Tile {
 
 // x/y classification of the general kernel's tile with origin (i0, j0).
 template <typename T>
-__device__ __forceinline__ Tile tile_xy(const Step3D<T> &p, int i0, int j0) {
+__host__ __device__ inline Tile tile_xy(const Step3D<T> &p, int i0, int j0) {
   const int nx = p.n[0], ny = p.n[1], P = p.P;
   Tile t;
   t.i0 = i0;
@@ -109,32 +105,25 @@ __device__ __forceinline__ Tile tile_xy(const Step3D<T> &p, int i0, int j0) {
   return t;
 }
 
-// Tile of a workgroup of the general kernel: over the whole grid (XCD-aware
-// order), or, for the design launch, over the box of tiles `box` (origin
-// box[0..2], extent box[3..5], x fastest).
-template <typename T>
-__device__ __forceinline__ Tile tile_of(const Step3D<T> &p, const bool in_box, const TileBox &box) {
-  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY, nbz = (nz + KC - 1) / KC;
-  int bx, by, bz;
-  if (in_box) {
-    const int b = blockIdx.x;
-    bx = box.o[0] + b % box.e[0];
-    by = box.o[1] + (b / box.e[0]) % box.e[1];
-    bz = box.o[2] + b / (box.e[0] * box.e[1]);
-  } else {
-    block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
-  }
-  Tile t = tile_xy(p, bx * TX, by * TY);
-  t.kb = bz * KC;
-  t.ke = min(t.kb + KC, nz);
-  return t;
-}
-
 // Does the tile's z-chunk meet the design or the gap box?
 template <typename T>
-__device__ __forceinline__ bool design_chunk(const Step3D<T> &p, const Tile &t) {
+__host__ __device__ inline bool design_chunk(const Step3D<T> &p, const Tile &t) {
   return (t.dxy && t.ke > p.d0[2] && t.kb < p.d0[2] + p.dn[2]) || (t.gxy && t.ke > p.g0[2] && t.kb < p.g0[2] + p.gn[2]);
+}
+
+// Absorber axes whose tables and memories the general update of tile t
+// needs in x and y (bit 0: x, bit 1: y), and along z at plane k (bit 2).
+template <typename T>
+__host__ __device__ inline int tile_axes(const Step3D<T> &p, const Tile &t) {
+  const int P = p.P, nx = p.n[0], ny = p.n[1];
+  const bool tx = P > 0 && (t.i0 <= P || t.i0 + TX >= nx - 1 - P);
+  const bool ty = P > 0 && (t.j0 <= P || t.j0 + TY >= ny - 1 - P);
+  return (tx ? 1 : 0) | (ty ? 2 : 0);
+}
+template <typename T>
+__host__ __device__ inline int plane_axes(const Step3D<T> &p, int k) {
+  const int P = p.P, nz = p.n[2];
+  return pml_h(k, nz, P) || pml_e(k, nz, P) || (k + 1 < nz && pml_e(k + 1, nz, P)) ? 4 : 0;
 }
 
 // Plane k of tile t takes the plain update: x/y reach plain, k and its two z
@@ -143,7 +132,7 @@ __device__ __forceinline__ bool design_chunk(const Step3D<T> &p, const Tile &t) 
 // misses the design and gap boxes.  Every other tile-plane belongs to the
 // general kernel.
 template <typename T>
-__device__ __forceinline__ bool plane_plain(const Step3D<T> &p, const Tile &t, int k) {
+__host__ __device__ inline bool plane_plain(const Step3D<T> &p, const Tile &t, int k) {
   const int P = p.P, nz = p.n[2];
   bool pl = t.xy_plain && k >= P + 1 && k <= nz - 2 - P;
   if (p.tf_on && (k == p.lo[2] - 1 || k == p.lo[2] || k == p.hi[2])) pl = false;
@@ -185,20 +174,28 @@ __device__ __forceinline__ T gr(T v, T m, const Ax<T> &x, T &mn) {
 }
 
 // ---------------------------------------------------------------- general
-// MODE 0: every general tile-plane (the forward).  MODE 1: the tile-chunks
-// that miss the design and gap boxes, with the design and gap code compiled
-// out; MODE 2: the others, launched over the box of tiles around them.  The
-// adjoint runs MODE 1 then MODE 2: without the FP64 sensitivity sums the
-// absorber tiles need fewer registers (FP32: 3 waves per SIMD instead of 2).
-// Both read only the read copy and write disjoint tile-chunks.
-// The FP32 forward variant fits 4 waves per SIMD without spills.
-template <typename T, bool ADJ, int MODE>
-__global__ void __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (!ADJ ? 4 : (MODE == 1 ? 3 : 1)) : 1)))
-step3d_general(const Step3D<T> p, const int n, const TileBox box) {
+// One tile-chunk of the general update.  DES compiles in the design and gap
+// code; AX is the set of absorber axes compiled in (bit 0: x, 1: y, 2: z):
+// a chunk whose planes reach no absorber along an axis needs no grading,
+// memories or tables of that axis, and the variants without them hold fewer
+// registers.  The host sorts the chunks by what they need (see
+// gen3d_plan), so no variant meets a chunk it cannot update.
+template <bool G, typename T>
+__device__ __forceinline__ T grc(T v, T m, const Ax<T> &x, T &mn) {
+  if constexpr (G) {
+    return gr(v, m, x, mn);
+  } else {
+    mn = T(0);
+    return v;
+  }
+}
+
+template <typename T, bool ADJ, bool DES, int AX>
+__device__ __forceinline__ void general_chunk(const Step3D<T> &p, const int n, const Tile &tl) {
   const int nx = p.n[0], ny = p.n[1], nz = p.n[2], P = p.P;
-  const Tile tl = tile_of(p, MODE == 2, box);
-  if (MODE != 0 && design_chunk(p, tl) != (MODE == 2)) return;  // the other launch's tile-chunk
+  auto gx = [](T v, T m, const Ax<T> &x, T &mn) { return grc<(AX & 1) != 0>(v, m, x, mn); };
+  auto gy = [](T v, T m, const Ax<T> &x, T &mn) { return grc<(AX & 2) != 0>(v, m, x, mn); };
+  auto gz = [](T v, T m, const Ax<T> &x, T &mn) { return grc<(AX & 4) != 0>(v, m, x, mn); };
   const int i = tl.i0 + (threadIdx.x % TX), j = tl.j0 + (threadIdx.x / TX);
   if (i >= nx || j >= ny) return;  // no barriers in this kernel
   const T *__restrict__ R = p.A[0];
@@ -208,8 +205,9 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
   const uint32_t qxy = p.G0 + (uint32_t)j * pitch + (uint32_t)i;
 
   // absorber groups reached by this tile (uniform)
-  const bool tx = P > 0 && (tl.i0 <= P || tl.i0 + TX >= nx - 1 - P);
-  const bool ty = P > 0 && (tl.j0 <= P || tl.j0 + TY >= ny - 1 - P);
+  const int taxes = tile_axes(p, tl);
+  const bool tx = (AX & 1) && (taxes & 1);
+  const bool ty = (AX & 2) && (taxes & 2);
   // per-lane absorber flags along x and y
   const bool okL = i >= 1, okR = i + 1 < nx, okS = j >= 1, okN = j + 1 < ny;
   const bool hx_i = pml_h(i, nx, P), hx_im = okL && pml_h(i - 1, nx, P);
@@ -272,7 +270,7 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
     const bool vex = xa0 && ya1 && kz, vey = xa1 && ya0 && kz, vez = xa1 && ya1 && kh;
     // absorber along z at this plane (uniform)
     const bool hz_k = pml_h(k, nz, P), ez_k = pml_e(k, nz, P), ez_k1 = okU && pml_e(k + 1, nz, P);
-    const bool tz = hz_k || ez_k || ez_k1;
+    const bool tz = (AX & 4) && plane_axes(p, k);
     Ax<T> zh = ax_id<T>(), ze = ax_id<T>(), ze1 = ax_id<T>();
     uint32_t zb = 0, zb1 = 0;
     if (tz) {
@@ -286,8 +284,8 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
     // injection, design and gap at this tile-plane (uniform)
     const bool tfp = tl.tf_meet && k >= p.lo[2] - 1 && k <= p.hi[2] &&
                      (tl.tf_hit || k == p.lo[2] - 1 || k == p.lo[2] || k == p.hi[2]);
-    const bool dp = MODE != 1 && tl.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2];
-    const bool gp = MODE != 1 && tl.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2];
+    const bool dp = DES && tl.dxy && k >= p.d0[2] && k < p.d0[2] + p.dn[2];
+    const bool gp = DES && tl.gxy && k >= p.g0[2] && k < p.g0[2] + p.gn[2];
     const bool des = dp && dcol, gap = gp && gcol, drude = des && !gap;
     const uint32_t d = des ? (uint32_t)(((k - p.d0[2]) * p.dn[1] + dj) * p.dn[0] + di) : 0u;
     const uint32_t g = gap ? (uint32_t)(((k - p.g0[2]) * p.gn[1] + gj) * p.gn[0] + gi) : 0u;
@@ -359,13 +357,13 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
       }
       const T ch = p.ch;
       // H_x: d_y E_z - d_z E_y;  H_y: d_z E_x - d_x E_z;  H_z: d_x E_y - d_y E_x
-      hx00 = hxC - ch * (gr(ezN - ezC, s_hx00y, yh0, sn[0]) - gr(eyc1 - eyC, s_hx00z, zh, sn[1]));
-      hx0m = hxS - ch * (gr(ezC - ezS, s_hx0my, yhm, t) - gr(eys1 - eySl, s_hx0mz, zh, t));
-      hy00 = hyC - ch * (gr(exc1 - exC, s_hy00z, zh, sn[2]) - gr(ezR - ezC, s_hy00x, xh0, sn[3]));
-      hym0 = hyL - ch * (gr(exl1 - exLl, s_hym0z, zh, t) - gr(ezC - ezL, s_hym0x, xhm, t));
-      hz00 = hzC - ch * (gr(eyR - eyC, s_hz00x, xh0, sn[4]) - gr(exN - exC, s_hz00y, yh0, sn[5]));
-      hz0m = hzS - ch * (gr(eyRS - eySl, s_hz0mx, xh0, t) - gr(exC - exS, s_hz0my, yhm, t));
-      hzm0 = hzL - ch * (gr(eyC - eyL, s_hzm0x, xhm, t) - gr(exLN - exLl, s_hzm0y, yh0, t));
+      hx00 = hxC - ch * (gy(ezN - ezC, s_hx00y, yh0, sn[0]) - gz(eyc1 - eyC, s_hx00z, zh, sn[1]));
+      hx0m = hxS - ch * (gy(ezC - ezS, s_hx0my, yhm, t) - gz(eys1 - eySl, s_hx0mz, zh, t));
+      hy00 = hyC - ch * (gz(exc1 - exC, s_hy00z, zh, sn[2]) - gx(ezR - ezC, s_hy00x, xh0, sn[3]));
+      hym0 = hyL - ch * (gz(exl1 - exLl, s_hym0z, zh, t) - gx(ezC - ezL, s_hym0x, xhm, t));
+      hz00 = hzC - ch * (gx(eyR - eyC, s_hz00x, xh0, sn[4]) - gy(exN - exC, s_hz00y, yh0, sn[5]));
+      hz0m = hzS - ch * (gx(eyRS - eySl, s_hz0mx, xh0, t) - gy(exC - exS, s_hz0my, yhm, t));
+      hzm0 = hzL - ch * (gx(eyC - eyL, s_hzm0x, xhm, t) - gy(exLN - exLl, s_hzm0y, yh0, t));
       T hA = T(0), hB = T(0), hK = T(0);
       if (tfp) {
         // total-field / scattered-field corrections from the incident line
@@ -404,9 +402,9 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
       hz0m = vz0m ? hz0m : T(0);
       hzm0 = vzm0 ? hzm0 : T(0);
       // E_x: d_y H_z - d_z H_y;  E_y: d_z H_x - d_x H_z;  E_z: d_x H_y - d_y H_x
-      cx = gr(hz00 - hz0m, s_exy, ye0, sn[6]) - gr(hy00 - hyp, s_exz, ze, sn[7]);
-      cy = gr(hx00 - hxp, s_eyz, ze, sn[8]) - gr(hz00 - hzm0, s_eyx, xe0, sn[9]);
-      cz = gr(hy00 - hym0, s_ezx, xe0, sn[10]) - gr(hx00 - hx0m, s_ezy, ye0, sn[11]);
+      cx = gy(hz00 - hz0m, s_exy, ye0, sn[6]) - gz(hy00 - hyp, s_exz, ze, sn[7]);
+      cy = gz(hx00 - hxp, s_eyz, ze, sn[8]) - gx(hz00 - hzm0, s_eyx, xe0, sn[9]);
+      cz = gx(hy00 - hym0, s_ezx, xe0, sn[10]) - gy(hx00 - hx0m, s_ezy, ye0, sn[11]);
       if (tfp) {
         if (i >= p.lo[0] && i <= p.hi[0] - 1 && j >= p.lo[1] && j <= p.hi[1]) {
           if (k == p.lo[2]) cx += hA;
@@ -470,16 +468,16 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
         n_hy00z = ld(R, vy00 && hz_k ? zb + p.ZS : 0u);
       }
       // graded E*
-      const T gyEzN = gr(ezN, n_ezyN, yep, t), gyEzC = gr(ezC, n_ezyC, ye0, sn[11]), gyEzS = gr(ezS, n_ezyS, yem, t);
-      const T gzEyU = gr(eyc1, n_eyzU, ze1, t), gzEyC = gr(eyC, n_eyzC, ze, sn[8]);
-      const T gzEySU = gr(eys1, n_eyzSU, ze1, t), gzEyS = gr(eySl, n_eyzS, ze, t);
-      const T gzExU = gr(exc1, n_exzU, ze1, t), gzExC = gr(exC, n_exzC, ze, sn[7]);
-      const T gzExLU = gr(exl1, n_exzLU, ze1, t), gzExL = gr(exLl, n_exzL, ze, t);
-      const T gxEzR = gr(ezR, n_ezxR, xep, t), gxEzC = gr(ezC, n_ezxC, xe0, sn[10]), gxEzL = gr(ezL, n_ezxL, xem, t);
-      const T gxEyR = gr(eyR, n_eyxR, xep, t), gxEyC = gr(eyC, n_eyxC, xe0, sn[9]);
-      const T gxEyRS = gr(eyRS, n_eyxRS, xep, t), gxEyS = gr(eySl, n_eyxS, xe0, t), gxEyL = gr(eyL, n_eyxL, xem, t);
-      const T gyExN = gr(exN, n_exyN, yep, t), gyExC = gr(exC, n_exyC, ye0, sn[6]), gyExS = gr(exS, n_exyS, yem, t);
-      const T gyExLN = gr(exLN, n_exyLN, yep, t), gyExL = gr(exLl, n_exyL, ye0, t);
+      const T gyEzN = gy(ezN, n_ezyN, yep, t), gyEzC = gy(ezC, n_ezyC, ye0, sn[11]), gyEzS = gy(ezS, n_ezyS, yem, t);
+      const T gzEyU = gz(eyc1, n_eyzU, ze1, t), gzEyC = gz(eyC, n_eyzC, ze, sn[8]);
+      const T gzEySU = gz(eys1, n_eyzSU, ze1, t), gzEyS = gz(eySl, n_eyzS, ze, t);
+      const T gzExU = gz(exc1, n_exzU, ze1, t), gzExC = gz(exC, n_exzC, ze, sn[7]);
+      const T gzExLU = gz(exl1, n_exzLU, ze1, t), gzExL = gz(exLl, n_exzL, ze, t);
+      const T gxEzR = gx(ezR, n_ezxR, xep, t), gxEzC = gx(ezC, n_ezxC, xe0, sn[10]), gxEzL = gx(ezL, n_ezxL, xem, t);
+      const T gxEyR = gx(eyR, n_eyxR, xep, t), gxEyC = gx(eyC, n_eyxC, xe0, sn[9]);
+      const T gxEyRS = gx(eyRS, n_eyxRS, xep, t), gxEyS = gx(eySl, n_eyxS, xe0, t), gxEyL = gx(eyL, n_eyxL, xem, t);
+      const T gyExN = gy(exN, n_exyN, yep, t), gyExC = gy(exC, n_exyC, ye0, sn[6]), gyExS = gy(exS, n_exyS, yem, t);
+      const T gyExLN = gy(exLN, n_exyLN, yep, t), gyExL = gy(exLl, n_exyL, ye0, t);
       const T ch = p.ch;
       hx00 = vx00 ? hxC - ch * ((gyEzN - gyEzC) - (gzEyU - gzEyC)) : T(0);
       hx0m = vx0m ? hxS - ch * ((gyEzC - gyEzS) - (gzEySU - gzEyS)) : T(0);
@@ -489,12 +487,12 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
       hz0m = vz0m ? hzS - ch * ((gxEyRS - gxEyS) - (gyExC - gyExS)) : T(0);
       hzm0 = vzm0 ? hzL - ch * ((gxEyC - gxEyL) - (gyExLN - gyExL)) : T(0);
       // graded H* for the E* brackets
-      const T gyHx00 = gr(hx00, n_hx00y, yh0, sn[0]), gzHx00 = gr(hx00, n_hx00z, zh, sn[1]);
-      const T gyHx0m = gr(hx0m, n_hx0my, yhm, t);
-      const T gzHy00 = gr(hy00, n_hy00z, zh, sn[2]), gxHy00 = gr(hy00, n_hy00x, xh0, sn[3]);
-      const T gxHym0 = gr(hym0, n_hym0x, xhm, t);
-      const T gxHz00 = gr(hz00, n_hz00x, xh0, sn[4]), gyHz00 = gr(hz00, n_hz00y, yh0, sn[5]);
-      const T gyHz0m = gr(hz0m, n_hz0my, yhm, t), gxHzm0 = gr(hzm0, n_hzm0x, xhm, t);
+      const T gyHx00 = gy(hx00, n_hx00y, yh0, sn[0]), gzHx00 = gz(hx00, n_hx00z, zh, sn[1]);
+      const T gyHx0m = gy(hx0m, n_hx0my, yhm, t);
+      const T gzHy00 = gz(hy00, n_hy00z, zh, sn[2]), gxHy00 = gx(hy00, n_hy00x, xh0, sn[3]);
+      const T gxHym0 = gx(hym0, n_hym0x, xhm, t);
+      const T gxHz00 = gx(hz00, n_hz00x, xh0, sn[4]), gyHz00 = gy(hz00, n_hz00y, yh0, sn[5]);
+      const T gyHz0m = gy(hz0m, n_hz0my, yhm, t), gxHzm0 = gx(hzm0, n_hzm0x, xhm, t);
       cx = (gyHz00 - gyHz0m) - (gzHy00 - hyp) + src[0];
       cy = (gzHx00 - hxp) - (gxHz00 - gxHzm0) + src[1];
       cz = (gxHy00 - gxHym0) - (gyHx00 - gyHx0m) + src[2];
@@ -586,6 +584,45 @@ step3d_general(const Step3D<T> p, const int n, const TileBox box) {
     if (!have) plane(std::integral_constant<bool, false>(), k - 1);  // new H of plane k-1, not stored
     plane(std::integral_constant<bool, true>(), k);
     have = true;
+  }
+}
+
+// Workgroup b updates tile-chunk list[b] (-1: none).  Chunk code c = (bz *
+// nby + by) * nbx + bx; with AX = 8 the code is 4c + a, a = the one absorber
+// axis the chunk needs (0 x, 1 y, 2 z) or 3 for none.
+#ifndef FDTD3D_WPE_F8
+#define FDTD3D_WPE_F8 4
+#endif
+#ifndef FDTD3D_WPE_A8
+#define FDTD3D_WPE_A8 4
+#endif
+template <typename T, bool ADJ, bool DES, int AX>
+constexpr int gen_waves() {
+  if (sizeof(T) != 4) return 1;
+  if (AX == 8) return ADJ ? FDTD3D_WPE_A8 : FDTD3D_WPE_F8;
+  return 1;
+}
+
+template <typename T, bool ADJ, bool DES, int AX>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(gen_waves<T, ADJ, DES, AX>())))
+step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
+  const int code = ((cptr<int>)list)[blockIdx.x];
+  if (code < 0) return;
+  const int c = AX == 8 ? code >> 2 : code;
+  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY;
+  const int bx = c % nbx, by = (c / nbx) % nby, bz = c / (nbx * nby);
+  Tile tl = tile_xy(p, bx * TX, by * TY);
+  tl.kb = bz * KC;
+  tl.ke = min(tl.kb + KC, p.n[2]);
+  if constexpr (AX == 8) {
+    switch (code & 3) {
+      case 0: general_chunk<T, ADJ, DES, 1>(p, n, tl); break;
+      case 1: general_chunk<T, ADJ, DES, 2>(p, n, tl); break;
+      case 2: general_chunk<T, ADJ, DES, 4>(p, n, tl); break;
+      default: general_chunk<T, ADJ, DES, 0>(p, n, tl); break;
+    }
+  } else {
+    general_chunk<T, ADJ, DES, AX>(p, n, tl);
   }
 }
 
@@ -686,46 +723,125 @@ __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
 
 }  // namespace
 
+namespace {
+
+// Deal the chunks (codes in (bz, by, bx) order) to the 8 XCDs: groups of
+// neighbouring chunks (one z-chunk, four tile rows) go whole to the XCD with
+// the least work so far, largest group first, so neighbours share an L2;
+// slot b of the launch runs on XCD b mod 8.
+std::vector<int> xcd_order(const std::vector<int> &codes, const std::vector<int> &group, const std::vector<int> &work) {
+  std::vector<std::pair<int, int>> gs;  // (group, first index)
+  for (size_t i = 0; i < codes.size(); ++i)
+    if (i == 0 || group[i] != group[i - 1]) gs.push_back({group[i], (int)i});
+  std::vector<int> gw(gs.size(), 0), ge(gs.size(), 0);
+  for (size_t g = 0; g < gs.size(); ++g) {
+    ge[g] = g + 1 < gs.size() ? gs[g + 1].second : (int)codes.size();
+    for (int i = gs[g].second; i < ge[g]; ++i) gw[g] += work[i];
+  }
+  std::vector<int> ord(gs.size());
+  for (size_t g = 0; g < gs.size(); ++g) ord[g] = (int)g;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return gw[a] > gw[b]; });
+  std::vector<int> load(8, 0);
+  std::vector<std::vector<int>> per(8);
+  std::vector<std::vector<int>> mine(8);
+  for (int g : ord) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += gw[g];
+    mine[x].push_back(g);
+  }
+  size_t len = 0;
+  for (int x = 0; x < 8; ++x) {
+    std::sort(mine[x].begin(), mine[x].end());
+    for (int g : mine[x])
+      for (int i = gs[g].second; i < ge[g]; ++i) per[x].push_back(codes[i]);
+    len = std::max(len, per[x].size());
+  }
+  std::vector<int> out(len * 8, -1);
+  for (int x = 0; x < 8; ++x)
+    for (size_t t = 0; t < per[x].size(); ++t) out[t * 8 + x] = per[x][t];
+  return out;
+}
+
+}  // namespace
+
+template <typename T>
+std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &axD) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+  const int nbx = (nx + TX - 1) / TX, nby = (ny + TY - 1) / TY, nbz = (nz + KC - 1) / KC;
+  std::vector<int> cS, cM, cD, gS, gM, gD, wS, wM, wD;
+  axD = 0;
+  for (int bz = 0; bz < nbz; ++bz)
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) {
+        Tile tl = tile_xy(p, bx * TX, by * TY);
+        tl.kb = bz * KC;
+        tl.ke = std::min(tl.kb + KC, nz);
+        // the planes the chunk updates and the planes below them whose new H
+        // it recomputes (as the kernel's march does)
+        int ax = 0, planes = 0;
+        bool have = false;
+        for (int k = tl.kb; k < tl.ke; ++k) {
+          if (plane_plain(p, tl, k)) {
+            have = false;
+            continue;
+          }
+          if (!have && k >= 1) ax |= plane_axes(p, k - 1);
+          ax |= plane_axes(p, k);
+          have = true;
+          ++planes;
+        }
+        if (planes == 0) continue;
+        ax |= tile_axes(p, tl);
+        const int c = (bz * nby + by) * nbx + bx, grp = bz * ((nby + 3) / 4) + by / 4;
+        if (design_chunk(p, tl)) {
+          axD |= ax;
+          cD.push_back(c); gD.push_back(grp); wD.push_back(planes);
+        } else if (ax == 0 || ax == 1 || ax == 2 || ax == 4) {
+          const int a = ax == 1 ? 0 : ax == 2 ? 1 : ax == 4 ? 2 : 3;
+          cS.push_back(4 * c + a); gS.push_back(grp); wS.push_back(planes);
+        } else {
+          cM.push_back(c); gM.push_back(grp); wM.push_back(planes);
+        }
+      }
+  if (axD) axD = 7;
+  std::vector<int> out = xcd_order(cS, gS, wS);
+  nS = (int)out.size();
+  const std::vector<int> m = xcd_order(cM, gM, wM), d = xcd_order(cD, gD, wD);
+  nM = (int)m.size();
+  nD = (int)d.size();
+  out.insert(out.end(), m.begin(), m.end());
+  out.insert(out.end(), d.begin(), d.end());
+  return out;
+}
+
+template <typename T, bool ADJ>
+static void launch_general(const Step3D<T> &q, int n, hipStream_t s) {
+  const int *L = q.glist;
+  if (q.gS > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 8>), dim3(q.gS), dim3(NT), 0, s, q, n, L);
+  if (q.gM > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 7>), dim3(q.gM), dim3(NT), 0, s, q, n, L + q.gS);
+  if (q.gD > 0) {
+    if (q.gAxD)
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 7>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
+    else
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 0>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
+  }
+}
+
 template <typename T>
 void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s) {
   Step3D<T> q = p;  // copy 0 is read, copy 1 written
   q.A[0] = p.A[par];
   q.A[1] = p.A[par ^ 1];
-  const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY, nbz = (p.n[2] + KC - 1) / KC;
-  const dim3 grid(nbx * nby * nbz);
-  TileBox all{};
-  if (adjoint) {
-    hipLaunchKernelGGL((step3d_general<T, true, 1>), grid, dim3(NT), 0, s, q, n, all);
-    // tiles around the design and gap boxes (their union's bounding box)
-    TileBox b{};
-    int lo[3], hi[3];
-    bool any = false;
-    auto add = [&](const int *o, const int *e) {
-      if (e[0] <= 0 || e[1] <= 0 || e[2] <= 0) return;
-      const int l[3] = {o[0] / TX, o[1] / TY, o[2] / KC};
-      const int h[3] = {(o[0] + e[0] - 1) / TX, (o[1] + e[1] - 1) / TY, (o[2] + e[2] - 1) / KC};
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = any ? std::min(lo[a], l[a]) : l[a];
-        hi[a] = any ? std::max(hi[a], h[a]) : h[a];
-      }
-      any = true;
-    };
-    add(p.d0, p.dn);
-    add(p.g0, p.gn);
-    if (any) {
-      for (int a = 0; a < 3; ++a) {
-        b.o[a] = lo[a];
-        b.e[a] = hi[a] - lo[a] + 1;
-      }
-      hipLaunchKernelGGL((step3d_general<T, true, 2>), dim3(b.e[0] * b.e[1] * b.e[2]), dim3(NT), 0, s, q, n, b);
-    }
-  } else {
-    hipLaunchKernelGGL((step3d_general<T, false, 0>), grid, dim3(NT), 0, s, q, n, all);
-  }
+  // the general tile-chunks (three launches by what they need), then the
+  // plain ones, which read back the new H of a general plane below them
+  if (adjoint) launch_general<T, true>(q, n, s);
+  else launch_general<T, false>(q, n, s);
   const int pbx = (p.n[0] + PTX - 1) / PTX, pby = (p.n[1] + PTY - 1) / PTY, pbz = (p.n[2] + PKC - 1) / PKC;
   hipLaunchKernelGGL(step3d_plain<T>, dim3(pbx * pby * pbz), dim3(PNT), 0, s, q);
 }
 
+template std::vector<int> gen3d_plan<float>(const Step3D<float> &, int &, int &, int &, int &);
+template std::vector<int> gen3d_plan<double>(const Step3D<double> &, int &, int &, int &, int &);
 template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t);
 template void launch_step3d<double>(const Step3D<double> &, int, int, bool, hipStream_t);
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "fdtd_internal.hpp"
 
@@ -83,7 +84,21 @@ struct Step3D {
   T ce_s, ce_g;        // dt / (eps0 eps dx)
   T A0, A1, B0, B1, Sg, dt_, dtdx, dthJ, kp;
   T ga, gsm, rs;
+  // tile-chunk lists of the general update (device, from gen3d_plan):
+  // [single-axis | multi-axis | design], lengths gS, gM, gD; gAxD = the
+  // absorber axes the design chunks reach (0 or 7)
+  const int *glist;
+  int gS, gM, gD, gAxD;
 };
+
+// Tile-chunks of the general update, sorted by what they need: one or no
+// absorber axis (code 4c + axis, axis 3 = none), several axes, the design or
+// gap boxes (code c); chunks without a general plane are left out.  Each
+// list is ordered for the 8 XCDs (groups of neighbouring chunks dealt to
+// the XCD with the least work so far, then interleaved) and padded with -1
+// to a multiple of 8.  The geometry fields of p are read (not the pointers).
+template <typename T>
+std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &axD);
 
 template <typename T>
 void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s);

@@ -39,6 +39,8 @@ struct fdtd_ctx {
   // 2D two-step blocking of the plain background: a third copy of the fields
   // (main and re-run state), the super-tiles and the per-step tiles
   DevBuf fld3[3], fld3R[3], tbTiles, tbRest;
+  DevBuf glist3;  // 3D: tile-chunk lists of the general update
+  int gS = 0, gM = 0, gD = 0, gAxD = 0;  // lengths of the three lists in glist3
   int nTb = 0, nRest = 0, nEarly = 0;  // tbTiles = [early interior super-tiles | border and other interior]
   int ck = 0, nseg = 1;  // segment length (steps) and count; nseg = 1: full history
   size_t snap_bytes = 0;
@@ -281,6 +283,15 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
   p.gapE = c->gapE.as<double>(); p.asrc = c->asrc.as<T>(); p.einc = c->einc.as<T>(); p.hinc = c->hinc.as<T>();
   p.tab = c->tab3.as<T>();
   p.tn = c->tn3;
+  if (!c->glist3.p) {
+    int nS = 0, nM = 0, nD = 0, axD = 0;
+    const std::vector<int> lists = gen3d_plan(p, nS, nM, nD, axD);
+    upload(c->stream, c->glist3, lists);
+    FDTD_HIP(hipStreamSynchronize(c->stream));
+    c->gS = nS; c->gM = nM; c->gD = nD; c->gAxD = axD;
+  }
+  p.glist = c->glist3.as<int>();
+  p.gS = c->gS; p.gM = c->gM; p.gD = c->gD; p.gAxD = c->gAxD;
   const double dt = c->dt, dx = g.dx;
   const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
   const double gam = g.gamma_mult * g.gamma_p;
