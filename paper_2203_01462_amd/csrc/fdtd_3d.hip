@@ -37,7 +37,7 @@ namespace {
 
 constexpr int TX = 32, TY = 8, NT = TX * TY;
 #ifndef FDTD3D_KC
-#define FDTD3D_KC 8
+#define FDTD3D_KC 4
 #endif
 constexpr int KC = FDTD3D_KC;  // planes per workgroup
 
