@@ -629,31 +629,41 @@ step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
 // ---------------------------------------------------------------- plain
 // Background dielectric only, identical for the forward and the adjoint.
 // Launched after step3d_general in the same step, so where plane k-1 was
-// general its new H is read back from the write copy.  Its own tiling is
-// wider than the general kernel's (fewer halo lines per owned line); each
-// lane takes the nodes whose general-kernel tile-plane is plain.
+// general its new H is read back from the write copy.  Its own tiling
+// (64 x 8 columns, 4-plane chunks) covers the bounding box of the plain
+// tile-planes only; each lane takes the nodes whose general-kernel
+// tile-plane is plain.
 #ifndef FDTD3D_PTX
-#define FDTD3D_PTX 128
+#define FDTD3D_PTX 64
 #endif
 #ifndef FDTD3D_PTY
-#define FDTD3D_PTY 4
+#define FDTD3D_PTY 8
 #endif
 #ifndef FDTD3D_PKC
 #define FDTD3D_PKC 4
 #endif
 constexpr int PTX = FDTD3D_PTX, PTY = FDTD3D_PTY, PNT = PTX * PTY, PKC = FDTD3D_PKC;
 
+// Workgroups of the plain launch over the box pb (z-chunks rounded up to a
+// multiple of 8 for the XCD-aware order of block_of).
+__host__ __device__ inline void plain_grid(const int pb[6], int &nbx, int &nby, int &nbz) {
+  nbx = (pb[3] + PTX - 1) / PTX;
+  nby = (pb[4] + PTY - 1) / PTY;
+  nbz = (pb[5] + PKC - 1) / PKC;
+  nbz = (nbz + 7) / 8 * 8;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
-  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-  const int nbx = (nx + PTX - 1) / PTX, nby = (ny + PTY - 1) / PTY, nbz = (nz + PKC - 1) / PKC;
-  int bx, by, bz;
+  const int nx = p.n[0], ny = p.n[1];
+  int nbx, nby, nbz, bx, by, bz;
+  plain_grid(p.pb, nbx, nby, nbz);
   block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
-  const int i = bx * PTX + (threadIdx.x % PTX), j = by * PTY + (threadIdx.x / PTX);
+  const int i = p.pb[0] + bx * PTX + (threadIdx.x % PTX), j = p.pb[1] + by * PTY + (threadIdx.x / PTX);
   if (i >= nx || j >= ny) return;  // no barriers in this kernel
   const Tile tl = tile_xy(p, i - i % TX, j - j % TY);
   if (!tl.xy_plain) return;
-  const int kb = bz * PKC, ke = min(kb + PKC, nz);
+  const int kb = p.pb[2] + bz * PKC, ke = min(kb + PKC, p.pb[2] + p.pb[5]);
   const uint32_t pitch = p.pitch, PL = p.PL, S = p.S;
   const T *__restrict__ Ex = p.A[0] + p.G0;
   const T *__restrict__ Ey = Ex + S;
@@ -836,12 +846,40 @@ void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t
   // plain ones, which read back the new H of a general plane below them
   if (adjoint) launch_general<T, true>(q, n, s);
   else launch_general<T, false>(q, n, s);
-  const int pbx = (p.n[0] + PTX - 1) / PTX, pby = (p.n[1] + PTY - 1) / PTY, pbz = (p.n[2] + PKC - 1) / PKC;
-  hipLaunchKernelGGL(step3d_plain<T>, dim3(pbx * pby * pbz), dim3(PNT), 0, s, q);
+  int pbx, pby, pbz;
+  plain_grid(p.pb, pbx, pby, pbz);
+  if (p.pb[3] > 0 && p.pb[4] > 0 && p.pb[5] > 0)
+    hipLaunchKernelGGL(step3d_plain<T>, dim3(pbx * pby * pbz), dim3(PNT), 0, s, q);
+}
+
+template <typename T>
+void plain3d_box(const Step3D<T> &p, int pb[6]) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+  int lo[3] = {nx, ny, nz}, hi[3] = {0, 0, 0};
+  for (int j0 = 0; j0 < ny; j0 += TY)
+    for (int i0 = 0; i0 < nx; i0 += TX) {
+      const Tile tl = tile_xy(p, i0, j0);
+      if (!tl.xy_plain) continue;
+      for (int k = 0; k < nz; ++k) {
+        if (!plane_plain(p, tl, k)) continue;
+        lo[0] = std::min(lo[0], i0);
+        hi[0] = std::max(hi[0], std::min(i0 + TX, nx));
+        lo[1] = std::min(lo[1], j0);
+        hi[1] = std::max(hi[1], std::min(j0 + TY, ny));
+        lo[2] = std::min(lo[2], k);
+        hi[2] = std::max(hi[2], k + 1);
+      }
+    }
+  for (int a = 0; a < 3; ++a) {
+    pb[a] = hi[a] > lo[a] ? lo[a] : 0;
+    pb[3 + a] = hi[a] > lo[a] ? hi[a] - lo[a] : 0;
+  }
 }
 
 template std::vector<int> gen3d_plan<float>(const Step3D<float> &, int &, int &, int &, int &);
 template std::vector<int> gen3d_plan<double>(const Step3D<double> &, int &, int &, int &, int &);
+template void plain3d_box<float>(const Step3D<float> &, int *);
+template void plain3d_box<double>(const Step3D<double> &, int *);
 template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t);
 template void launch_step3d<double>(const Step3D<double> &, int, int, bool, hipStream_t);
 

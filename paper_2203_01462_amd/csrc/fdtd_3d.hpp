@@ -89,6 +89,7 @@ struct Step3D {
   // absorber axes the design chunks reach (0 or 7)
   const int *glist;
   int gS, gM, gD, gAxD;
+  int pb[6];  // bounding box of the plain tile-planes: origin x, y, z, extent x, y, z (from plain3d_box)
 };
 
 // Tile-chunks of the general update, sorted by what they need: one or no
@@ -99,6 +100,11 @@ struct Step3D {
 // to a multiple of 8.  The geometry fields of p are read (not the pointers).
 template <typename T>
 std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &axD);
+
+// Bounding box of the tile-planes that take the plain update (extent 0
+// when there are none); the plain launch covers only this box.
+template <typename T>
+void plain3d_box(const Step3D<T> &p, int pb[6]);
 
 template <typename T>
 void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s);

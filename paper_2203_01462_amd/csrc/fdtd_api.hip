@@ -292,6 +292,7 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
   }
   p.glist = c->glist3.as<int>();
   p.gS = c->gS; p.gM = c->gM; p.gD = c->gD; p.gAxD = c->gAxD;
+  plain3d_box(p, p.pb);
   const double dt = c->dt, dx = g.dx;
   const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
   const double gam = g.gamma_mult * g.gamma_p;
