@@ -824,28 +824,46 @@ std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &
   return out;
 }
 
+#ifndef FDTD3D_AUX
+#define FDTD3D_AUX 1
+#endif
+
+// The three general launches write disjoint tile-chunks of the write copy
+// and read only the read copy, so the multi-axis and design launches may run
+// on the second stream beside the single-axis one.
 template <typename T, bool ADJ>
-static void launch_general(const Step3D<T> &q, int n, hipStream_t s) {
+static void launch_general(const Step3D<T> &q, int n, hipStream_t s, const Aux3D &aux) {
   const int *L = q.glist;
-  if (q.gS > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 8>), dim3(q.gS), dim3(NT), 0, s, q, n, L);
-  if (q.gM > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 7>), dim3(q.gM), dim3(NT), 0, s, q, n, L + q.gS);
+  const bool two = FDTD3D_AUX && aux.stream && (q.gM > 0 || q.gD > 0);
+  hipStream_t s2 = s;
+  if (two) {
+    FDTD_HIP(hipEventRecord(aux.fork, s));
+    FDTD_HIP(hipStreamWaitEvent(aux.stream, aux.fork, 0));
+    s2 = aux.stream;
+  }
+  if (q.gM > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 7>), dim3(q.gM), dim3(NT), 0, s2, q, n, L + q.gS);
   if (q.gD > 0) {
     if (q.gAxD)
-      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 7>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 7>), dim3(q.gD), dim3(NT), 0, s2, q, n, L + q.gS + q.gM);
     else
-      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 0>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 0>), dim3(q.gD), dim3(NT), 0, s2, q, n, L + q.gS + q.gM);
+  }
+  if (q.gS > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 8>), dim3(q.gS), dim3(NT), 0, s, q, n, L);
+  if (two) {
+    FDTD_HIP(hipEventRecord(aux.join, aux.stream));
+    FDTD_HIP(hipStreamWaitEvent(s, aux.join, 0));
   }
 }
 
 template <typename T>
-void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s) {
+void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s, const Aux3D &aux) {
   Step3D<T> q = p;  // copy 0 is read, copy 1 written
   q.A[0] = p.A[par];
   q.A[1] = p.A[par ^ 1];
   // the general tile-chunks (three launches by what they need), then the
   // plain ones, which read back the new H of a general plane below them
-  if (adjoint) launch_general<T, true>(q, n, s);
-  else launch_general<T, false>(q, n, s);
+  if (adjoint) launch_general<T, true>(q, n, s, aux);
+  else launch_general<T, false>(q, n, s, aux);
   int pbx, pby, pbz;
   plain_grid(p.pb, pbx, pby, pbz);
   if (p.pb[3] > 0 && p.pb[4] > 0 && p.pb[5] > 0)
@@ -880,7 +898,7 @@ template std::vector<int> gen3d_plan<float>(const Step3D<float> &, int &, int &,
 template std::vector<int> gen3d_plan<double>(const Step3D<double> &, int &, int &, int &, int &);
 template void plain3d_box<float>(const Step3D<float> &, int *);
 template void plain3d_box<double>(const Step3D<double> &, int *);
-template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t);
-template void launch_step3d<double>(const Step3D<double> &, int, int, bool, hipStream_t);
+template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t, const Aux3D &);
+template void launch_step3d<double>(const Step3D<double> &, int, int, bool, hipStream_t, const Aux3D &);
 
 }  // namespace fdtd

@@ -52,6 +52,7 @@ struct fdtd_ctx {
   double F = 0;
   std::string err;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  Aux3D aux{nullptr, nullptr, nullptr};  // 3D: second stream and fork/join events
   fdtd_timing timing{};
 };
 
@@ -258,6 +259,17 @@ void create_3d(fdtd_ctx *c) {
     if (c->nseg > 1) c->arenaR[b].alloc((size_t)c->lay3.total * c->esz);
   }
   if (c->prec == 32) build_axis_tables3<float>(c); else build_axis_tables3<double>(c);
+  FDTD_HIP(hipStreamCreate(&c->aux.stream));
+  FDTD_HIP(hipEventCreateWithFlags(&c->aux.fork, hipEventDisableTiming));
+  FDTD_HIP(hipEventCreateWithFlags(&c->aux.join, hipEventDisableTiming));
+}
+
+void release_aux(fdtd_ctx *c) {
+  if (c->aux.stream) (void)hipStreamSynchronize(c->aux.stream);
+  if (c->aux.fork) (void)hipEventDestroy(c->aux.fork);
+  if (c->aux.join) (void)hipEventDestroy(c->aux.join);
+  if (c->aux.stream) (void)hipStreamDestroy(c->aux.stream);
+  c->aux = Aux3D{nullptr, nullptr, nullptr};
 }
 
 template <typename T>
@@ -440,7 +452,7 @@ void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_b
     Step3D<T> p = params3d<T>(c, rerun);
     p.hist_base = hist_base;
     p.hist_on = hist_on;
-    launch_step3d<T>(p, n, s & 1, adjoint, c->stream);
+    launch_step3d<T>(p, n, s & 1, adjoint, c->stream, c->aux);
   }
 }
 
@@ -1018,6 +1030,7 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
     FDTD_HIP(hipGetLastError());
   });
   if (st != FDTD_OK) {
+    release_aux(c.get());
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (int k = 0; k < 4; ++k) if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     return st;
@@ -1029,6 +1042,7 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
 fdtd_status fdtd_destroy(fdtd_ctx *ctx) {
   if (!ctx) return FDTD_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  release_aux(ctx);
   for (int k = 0; k < 4; ++k) if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
