@@ -176,7 +176,7 @@ def main():
                     help="only run 5 device copies of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path runs on a single device); "
+        print("bench.py: the solver runs on a single device and is measured on one GPU only; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
