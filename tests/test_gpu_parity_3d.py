@@ -37,6 +37,17 @@ def test_medium3d_fp64(gpu, oracle_mod):
     compare(gpu, oracle_mod, w, W.seeded_rho(w, 1), 1e-11, 1e-11, "medium3d fp64")
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_medium3d_interior_design(gpu, oracle_mod, prec):
+    """The design box inside one column of tiles that reaches no absorber:
+    its tile-chunks take the general variant with the absorber code compiled
+    out (the C3 layout; the other 3D cases put design chunks next to the
+    absorber)."""
+    w = W.medium3d(precision=prec, design_lo=(34, 30, 35), gap_lo=(43, 39, 39))
+    tol = (1e-11, 1e-11) if prec == 64 else (1e-4, 1e-3)
+    compare(gpu, oracle_mod, w, W.seeded_rho(w, 4), tol[0], tol[1], f"medium3d interior design fp{prec}")
+
+
 @pytest.mark.parametrize("kind", ["smooth", "binary"])
 def test_medium3d_fp32(gpu, oracle_mod, kind):
     w = W.medium3d(precision=32, sigma_max=5e5)

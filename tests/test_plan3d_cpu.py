@@ -16,7 +16,12 @@ CASES = {
     "small": [48, 48, 48, 8, 4, 20, 20, 20, 10, 10, 6, 24, 24, 22, 2, 2, 2],
     "no_absorber": [40, 40, 40, 0, 4, 14, 14, 14, 10, 10, 8, 18, 18, 18, 2, 2, 2],
     "ragged": [100, 72, 50, 10, 5, 30, 20, 18, 37, 29, 13, 45, 31, 23, 3, 2, 2],
+    # the GPU parity cases: design chunks next to the absorber / away from it
+    "medium3d": [80, 80, 80, 6, 3, 30, 30, 35, 20, 20, 10, 39, 39, 39, 2, 2, 2],
+    "medium3d_interior": [80, 80, 80, 6, 3, 34, 30, 35, 20, 20, 10, 43, 39, 39, 2, 2, 2],
 }
+# absorber axes compiled into the design launch (0: none, 7: all)
+AXD = {"c3": 0, "medium3d": 7, "medium3d_interior": 0}
 
 
 @pytest.fixture(scope="module")
@@ -39,3 +44,5 @@ def test_plan3d_lists(exe, case):
     fields = r.stdout.split()
     general = int(fields[fields.index("general") + 1])
     assert general > 0
+    if case in AXD:
+        assert int(fields[fields.index("axD") + 1]) == AXD[case]
