@@ -38,7 +38,7 @@ MEASURED_TRAFFIC = {
                         "fwd": 104.9e6, "adj": 109.1e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step = step3d_general (three launches) + step3d_plain
-    "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "b5a19a5bf0a80a53",
+    "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "f653f34f279470fb",
                        "fwd": 1303.1e6, "adj": 1338.6e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
 }

@@ -17,9 +17,11 @@
 // step's values, which the ping-pong copies keep intact.  A tile-plane is
 // "plain" when its whole reach is background dielectric; all others
 // (absorber, walls, injection faces, Drude design edges, gap) are "general".
-// One step is two launches on one stream: step3d_general first, then
-// step3d_plain, which reads back the general kernel's new H where a plain
-// plane sits on a general one.  The general path keeps its cost down by
+// One step is three launches of step3d_general over host-built lists of
+// tile-chunks (one absorber axis or none; several axes; design and gap),
+// the last two on a second stream beside the first, then step3d_plain,
+// which reads back the general launches' new H where a plain plane sits on
+// a general one.  The general path keeps its cost down by
 // loading each group of absorber memories only in tiles/planes that reach
 // that absorber (uniform branches), by addressing the whole state of a copy
 // through one base pointer with 32-bit offsets, and by CPML tables that are
