@@ -37,6 +37,10 @@ MEASURED_TRAFFIC = {
     "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "b435b02ff6a4150e",
                         "fwd": 104.9e6, "adj": 109.1e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
+    # one time step of all 64 instances = one step2d_batch_mix_kernel launch
+    "tmz2d_batch64_c4": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "b435b02ff6a4150e",
+                         "fwd": 596.9e6, "adj": 617.6e6,
+                         "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = step3d_general (three launches) + step3d_plain
     "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "f653f34f279470fb",
                        "fwd": 1303.1e6, "adj": 1338.6e6,
@@ -108,6 +112,105 @@ def cpu_baseline(w, steps):
                       f"FP64, {dt:.1f} s wall"}
 
 
+def bench_c4(args):
+    """The batched uneven workload: 64 2D FP32 instances (sides 128-1024, own
+    damping and band) advanced together by fdtd_batch_* with the batch-tuned
+    tile and temporal-block depths and graph replay; one bench step = set
+    every density, batched forward, batched adjoint, every gradient."""
+    import torch
+    import paper_2203_01462_amd as P
+
+    ws = W.c4(n_steps=args.n_steps or 5000)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    b = P.Batch(ws, stream=stream.cuda_stream, rows=0, use_graph=True, depth=0)
+    setup_s = time.perf_counter() - t0
+    with torch.cuda.stream(stream):
+        rhos = [torch.from_numpy(W.seeded_rho(w, k).astype(np.float32)).to("cuda") for k, w in enumerate(ws)]
+        grads = [torch.empty_like(r) for r in rhos]
+    stream.synchronize()
+
+    def step():
+        for k, r in enumerate(rhos):
+            b.set_density(k, r)
+        b.forward()
+        b.adjoint()
+        for k, g in enumerate(grads):
+            b.gradient(k, g)
+
+    for _ in range(args.warmup):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    fwd_ms = adj_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        stream.synchronize()
+        i = b.info(0)
+        fwd_ms += i["forward_ms"]
+        adj_ms += i["adjoint_ms"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = [b.info(k) for k in range(len(ws))]
+    b.close()
+    N = ws[0]["n_steps"]
+    value = sum(W.cell_updates(w) for w in ws) / (wall / args.steps) / 1e9
+    bf = sum(algorithmic_bytes(w, False) for w in ws)
+    ba = sum(algorithmic_bytes(w, True) for w in ws)
+    achieved = (bf + ba) * N * args.steps / ((fwd_ms + adj_ms) * 1e-3) / 1e9
+    trec, traffic = measured_traffic("tmz2d_batch64_c4")
+    depth_by_side = sorted({(w["n"][0], i["depth"]) for w, i in zip(ws, info)})
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tmz2d_batch64_c4", "instances": len(ws),
+                   "sides": sorted({w["n"][0] for w in ws}), "time_steps": N, "n_freq": ws[0]["n_freq"],
+                   "tile_depths": sorted({i["rows"] for i in info}),
+                   "temporal_block_depth_by_side": [list(x) for x in depth_by_side],
+                   "setup_and_tuning_s": round(setup_s, 2), "density": "seeded smoothed U[0,1), seed = index",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_per_step_fwd_adj": [trec["fwd"], trec["adj"]] if trec else None,
+                     "kernel": "step2d_batch_mix_kernel (all instances, two launches per two time steps)",
+                     "bytes_per_step_fwd": bf, "bytes_per_step_adj": ba,
+                     "avg_step_us_fwd": round(fwd_ms * 1e3 / (N * args.steps), 3),
+                     "avg_step_us_adj": round(adj_ms * 1e3 / (N * args.steps), 3)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_c4(ws, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_c4(ws, steps):
+    """The oracle as it stands on one instance of each side of the batch,
+    first `steps` steps each."""
+    import oracle
+    seen, cells_steps, dt = set(), 0, 0.0
+    for k, w in enumerate(ws):
+        side = w["n"][0]
+        if side in seen:
+            continue
+        seen.add(side)
+        ws1 = W.with_(w, n_steps=min(steps, w["n_steps"]), precision=64)
+        o = oracle.Oracle(ws1)
+        rho = W.seeded_rho(ws1, k)
+        t0 = time.perf_counter()
+        o.set_density(rho)
+        o.forward()
+        o.adjoint()
+        o.gradient()
+        dt += time.perf_counter() - t0
+        o.close()
+        cells_steps += W.cell_updates(ws1)
+    return {"value": cells_steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one instance of each side {sorted(seen)}, first {steps} steps each, forward+adjoint+"
+                      f"gradient, FP64, {dt:.1f} s wall"}
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -165,8 +268,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "unet"],
-                    help="unet: training steps of the surrogate network (BF16 matrix cores) instead of FDTD")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "unet"],
+                    help="c4: 64 uneven 2D instances batched; unet: training steps of the surrogate network "
+                         "(BF16 matrix cores) instead of FDTD")
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="time steps of the oracle sample")
     ap.add_argument("--ckpt-every", type=int, default=0,
@@ -195,6 +299,9 @@ def main():
         return
     if args.workload == "unet":
         bench_unet(args)
+        return
+    if args.workload == "c4":
+        bench_c4(args)
         return
     base = W.PRESETS[args.workload]()
     if args.n_steps:
