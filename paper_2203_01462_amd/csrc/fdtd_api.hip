@@ -53,6 +53,13 @@ struct fdtd_ctx {
   std::string err;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   Aux3D aux{nullptr, nullptr, nullptr};  // 3D: second stream and fork/join events
+  // checkpointed adjoint with the re-runs on their own stream: a second
+  // history buffer (segment s uses buffer s % 2), the re-run stream and its
+  // 3D side stream, and the events that order the two streams
+  DevBuf hist2;
+  hipStream_t rr = nullptr;
+  Aux3D auxR{nullptr, nullptr, nullptr};
+  hipEvent_t evStart = nullptr, evRerun = nullptr, evAdj[2] = {nullptr, nullptr};
   fdtd_timing timing{};
 };
 
@@ -231,6 +238,20 @@ void build_axis_tables3(fdtd_ctx *c) {
   upload(c->stream, c->tab3, all);
 }
 
+void release_one(Aux3D &a) {
+  if (a.stream) (void)hipStreamSynchronize(a.stream);
+  if (a.fork) (void)hipEventDestroy(a.fork);
+  if (a.join) (void)hipEventDestroy(a.join);
+  if (a.stream) (void)hipStreamDestroy(a.stream);
+  a = Aux3D{nullptr, nullptr, nullptr};
+}
+
+void create_one(Aux3D &a) {
+  FDTD_HIP(hipStreamCreate(&a.stream));
+  FDTD_HIP(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+  FDTD_HIP(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+}
+
 void create_3d(fdtd_ctx *c) {
   const fdtd_config &g = c->cfg;
   const int P = g.pml_cells, m = g.tfsf_margin;
@@ -259,17 +280,20 @@ void create_3d(fdtd_ctx *c) {
     if (c->nseg > 1) c->arenaR[b].alloc((size_t)c->lay3.total * c->esz);
   }
   if (c->prec == 32) build_axis_tables3<float>(c); else build_axis_tables3<double>(c);
-  FDTD_HIP(hipStreamCreate(&c->aux.stream));
-  FDTD_HIP(hipEventCreateWithFlags(&c->aux.fork, hipEventDisableTiming));
-  FDTD_HIP(hipEventCreateWithFlags(&c->aux.join, hipEventDisableTiming));
+  create_one(c->aux);
 }
 
+// Streams and events beyond the context stream (all at default priority).
 void release_aux(fdtd_ctx *c) {
-  if (c->aux.stream) (void)hipStreamSynchronize(c->aux.stream);
-  if (c->aux.fork) (void)hipEventDestroy(c->aux.fork);
-  if (c->aux.join) (void)hipEventDestroy(c->aux.join);
-  if (c->aux.stream) (void)hipStreamDestroy(c->aux.stream);
-  c->aux = Aux3D{nullptr, nullptr, nullptr};
+  release_one(c->aux);
+  release_one(c->auxR);
+  if (c->rr) (void)hipStreamSynchronize(c->rr);
+  for (hipEvent_t *e : {&c->evStart, &c->evRerun, &c->evAdj[0], &c->evAdj[1]}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  if (c->rr) (void)hipStreamDestroy(c->rr);
+  c->rr = nullptr;
 }
 
 template <typename T>
@@ -357,6 +381,16 @@ void create_common(fdtd_ctx *c) {
     throw Error{FDTD_ENOMEM, "forward history and snapshots do not fit in device memory"};
   c->hist.alloc((size_t)hist_bytes);
   if (c->nseg > 1) c->snap.alloc((size_t)snap_total);
+  // a second segment history lets the re-run of segment s-1 overlap the
+  // adjoint of segment s, where the budget and the memory allow it
+  const double two = 2 * hist_bytes + snap_total;
+  if (c->nseg > 1 && (g.history_budget_bytes <= 0 || two <= (double)g.history_budget_bytes) && two <= 0.92 * (double)fr) {
+    c->hist2.alloc((size_t)hist_bytes);
+    FDTD_HIP(hipStreamCreate(&c->rr));
+    for (hipEvent_t *e : {&c->evStart, &c->evRerun, &c->evAdj[0], &c->evAdj[1]})
+      FDTD_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    if (c->dims == 3) create_one(c->auxR);
+  }
   c->dft.alloc((size_t)c->K * c->nmon * 2 * sizeof(double));
   c->gapE.alloc((size_t)(c->N + 1) * c->nmon * sizeof(double));
   c->asrc.alloc((size_t)(c->N + 1) * c->nmon * c->esz);
@@ -420,11 +454,21 @@ Step3D<float> &params3d<float>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3fR
 template <>
 Step3D<double> &params3d<double>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3dR : c->p3d; }
 
+// Where a block of steps runs: its stream, the 3D side stream, and the
+// history buffer the design edges write (forward) or read (adjoint).
+struct Lane {
+  hipStream_t s;
+  const Aux3D *aux;
+  void *hist;
+};
+Lane main_lane(fdtd_ctx *c) { return Lane{c->stream, &c->aux, c->hist.p}; }
+
 // 2D parameters of the step that follows `s` steps of a solve: copy 0 read,
 // copy 1 written, parities resolved.
 template <typename T>
-Step2D<T> params2d_at(fdtd_ctx *c, bool rerun, int s, int hist_base, bool hist_on) {
+Step2D<T> params2d_at(fdtd_ctx *c, bool rerun, int s, int hist_base, bool hist_on, void *hist) {
   Step2D<T> p = params2d<T>(c, rerun);
+  p.hist = static_cast<T *>(hist);
   const int fr = fcopy(c, s), fw = fcopy(c, s + 1);
   p.ez[0] = field_buf(c, rerun, fr, 0)->as<T>(); p.ez[1] = field_buf(c, rerun, fw, 0)->as<T>();
   p.hx[0] = field_buf(c, rerun, fr, 1)->as<T>(); p.hx[1] = field_buf(c, rerun, fw, 1)->as<T>();
@@ -443,16 +487,17 @@ Step2D<T> params2d_at(fdtd_ctx *c, bool rerun, int s, int hist_base, bool hist_o
 // One time step (step number n, the (s+1)-th of its solve) on the main state
 // (rerun = false) or the re-run state.
 template <typename T>
-void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_base, bool hist_on) {
+void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_base, bool hist_on, const Lane &ln) {
   if (c->dims == 2) {
     // a single step updates every tile (the super-tiles take the background
     // update of the per-step kernel)
-    launch_step2d<T>(params2d_at<T>(c, rerun, s, hist_base, hist_on), n, 0, adjoint, c->stream);
+    launch_step2d<T>(params2d_at<T>(c, rerun, s, hist_base, hist_on, ln.hist), n, 0, adjoint, ln.s);
   } else {
     Step3D<T> p = params3d<T>(c, rerun);
+    p.hist = static_cast<T *>(ln.hist);
     p.hist_base = hist_base;
     p.hist_on = hist_on;
-    launch_step3d<T>(p, n, s & 1, adjoint, c->stream, c->aux);
+    launch_step3d<T>(p, n, s & 1, adjoint, ln.s, *ln.aux);
   }
 }
 
@@ -467,34 +512,35 @@ void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_b
 // rest tiles read in that launch only outside the super-tiles.  An odd last
 // step is a full-grid single step.
 template <typename T, typename NOF, typename HON>
-void run_block(fdtd_ctx *c, bool rerun, bool adjoint, int s0, int count, NOF nof, int hbase, HON hon) {
+void run_block(fdtd_ctx *c, bool rerun, bool adjoint, int s0, int count, NOF nof, int hbase, HON hon,
+               const Lane &ln) {
   if (c->dims != 2 || c->nTb == 0) {
-    for (int j = 0; j < count; ++j) launch_step<T>(c, rerun, nof(j), s0 + j, adjoint, hbase, hon(j));
+    for (int j = 0; j < count; ++j) launch_step<T>(c, rerun, nof(j), s0 + j, adjoint, hbase, hon(j), ln);
     return;
   }
   const int P = count / 2;
   const int *tiles = c->tbTiles.as<int>();
   auto step = [&](int j) {
-    Step2D<T> p = params2d_at<T>(c, rerun, s0 + j, hbase, hon(j));
+    Step2D<T> p = params2d_at<T>(c, rerun, s0 + j, hbase, hon(j), ln.hist);
     p.tlist = c->tbRest.as<int>();
     return p;
   };
   auto out = [&](int q, int k) { return field_buf(c, rerun, fcopy(c, s0 + 2 * q + 2), k)->as<T>(); };
   for (int q = 0; q < P; ++q) {
     // launch A of pair q
-    const Step2D<T> pa = step(2 * q), pt = params2d_at<T>(c, rerun, s0 + 2 * q, hbase, hon(2 * q));
+    const Step2D<T> pa = step(2 * q), pt = params2d_at<T>(c, rerun, s0 + 2 * q, hbase, hon(2 * q), ln.hist);
     const int first = q == 0 ? 0 : c->nEarly;
     launch_step2d_mix<T>(pa, nof(2 * q), c->nRest, pt, tiles + first, c->nTb - first, out(q, 0), out(q, 1),
-                         out(q, 2), adjoint, c->stream);
+                         out(q, 2), adjoint, ln.s);
     // launch B of pair q (+ the early super-tiles of pair q+1)
     const Step2D<T> pb = step(2 * q + 1);
     const bool next = q + 1 < P;
-    const Step2D<T> pn = next ? params2d_at<T>(c, rerun, s0 + 2 * q + 2, hbase, hon(2 * q + 2)) : pt;
+    const Step2D<T> pn = next ? params2d_at<T>(c, rerun, s0 + 2 * q + 2, hbase, hon(2 * q + 2), ln.hist) : pt;
     launch_step2d_mix<T>(pb, nof(2 * q + 1), c->nRest, pn, tiles, next ? c->nEarly : 0,
                          next ? out(q + 1, 0) : nullptr, next ? out(q + 1, 1) : nullptr,
-                         next ? out(q + 1, 2) : nullptr, adjoint, c->stream);
+                         next ? out(q + 1, 2) : nullptr, adjoint, ln.s);
   }
-  if (count & 1) launch_step<T>(c, rerun, nof(count - 1), s0 + count - 1, adjoint, hbase, hon(count - 1));
+  if (count & 1) launch_step<T>(c, rerun, nof(count - 1), s0 + count - 1, adjoint, hbase, hon(count - 1), ln);
 }
 
 // The buffers holding the state after `st` steps of a solve (fields and
@@ -521,13 +567,16 @@ void snap_save(fdtd_ctx *c, int st, int s) {
 }
 
 // Re-run state after `st` steps <- snapshot s.
-void snap_load(fdtd_ctx *c, int st, int s) {
+void snap_load(fdtd_ctx *c, int st, int s, hipStream_t stream) {
   const char *src = (const char *)c->snap.p + (size_t)s * c->snap_bytes;
   for (DevBuf *d : state_bufs(c, st, true)) {
-    FDTD_HIP(hipMemcpyAsync(d->p, src, d->bytes, hipMemcpyDeviceToDevice, c->stream));
+    FDTD_HIP(hipMemcpyAsync(d->p, src, d->bytes, hipMemcpyDeviceToDevice, stream));
     src += d->bytes;
   }
 }
+
+// History buffer of segment s: with a second buffer, segments alternate.
+void *seg_hist(fdtd_ctx *c, int s) { return c->hist2.p && (s & 1) ? c->hist2.p : c->hist.p; }
 
 // Forward solve: step n reads the state after n steps and writes the state
 // after n+1.  With checkpoints the state entering each segment but the last is
@@ -538,10 +587,13 @@ void run_forward(fdtd_ctx *c) {
   FDTD_HIP(hipEventRecord(c->ev[0], c->stream));
   const int K = c->ck, S = c->nseg, last = (S - 1) * K, N = c->N;
   const int seglen = S > 1 ? K : N;
+  Lane ln = main_lane(c);
   for (int a = 0; a < N; a += seglen) {
     const int b = std::min(a + seglen, N);
     if (S > 1 && a < last) snap_save(c, a, a / K);
-    run_block<T>(c, false, false, a, b - a, [=](int j) { return a + j; }, last, [=](int j) { return a + j >= last; });
+    ln.hist = seg_hist(c, a / seglen);
+    run_block<T>(c, false, false, a, b - a, [=](int j) { return a + j; }, last, [=](int j) { return a + j >= last; },
+                 ln);
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[1], c->stream));
@@ -550,21 +602,51 @@ void run_forward(fdtd_ctx *c) {
 // Adjoint solve, m = N..1 (eq. (20)); step m reads the forward E^m from the
 // history.  With checkpoints, when m enters a segment whose history is not
 // held, that segment of the forward is re-run from its snapshot on the re-run
-// state, refilling the history buffer.
+// state, refilling a history buffer.  With two history buffers the re-run of
+// segment s-1 runs on the re-run stream while the adjoint sweeps segment s
+// on the context stream: the adjoint of s waits for the re-run of s, and the
+// re-run of s-1 for the adjoint of s+1 (which read the buffer it refills).
 template <typename T>
 void run_adjoint(fdtd_ctx *c) {
   FDTD_HIP(hipEventRecord(c->ev[2], c->stream));
   const int K = c->ck, S = c->nseg, N = c->N;
   const int seglen = S > 1 ? K : N;
-  const int nseg = (N + seglen - 1) / seglen;
-  for (int s = nseg - 1; s >= 0; --s) {
+  Lane main = main_lane(c);
+  auto rerun = [&](int s, const Lane &ln) {
     const int a = s * seglen, b = std::min(a + seglen, N);
-    if (S > 1 && s != S - 1) {
-      snap_load(c, a, s);
-      run_block<T>(c, true, false, a, b - a, [=](int j) { return a + j; }, a, [](int) { return true; });
-    }
+    snap_load(c, a, s, ln.s);
+    run_block<T>(c, true, false, a, b - a, [=](int j) { return a + j; }, a, [](int) { return true; }, ln);
+  };
+  auto adjoint = [&](int s) {
+    const int a = s * seglen, b = std::min(a + seglen, N);
+    main.hist = seg_hist(c, s);
     // adjoint steps m = b .. a+1 (the (N-b+1)-th .. (N-a)-th of the adjoint solve)
-    run_block<T>(c, false, true, N - b, b - a, [=](int j) { return b - j; }, a, [](int) { return false; });
+    run_block<T>(c, false, true, N - b, b - a, [=](int j) { return b - j; }, a, [](int) { return false; }, main);
+  };
+  if (S > 1 && c->hist2.p) {
+    Lane rl{c->rr, &c->auxR, nullptr};
+    FDTD_HIP(hipEventRecord(c->evStart, c->stream));
+    FDTD_HIP(hipStreamWaitEvent(c->rr, c->evStart, 0));
+    for (int s = S - 1; s >= 0; --s) {
+      if (s != S - 1) FDTD_HIP(hipStreamWaitEvent(c->stream, c->evRerun, 0));
+      adjoint(s);
+      FDTD_HIP(hipEventRecord(c->evAdj[s & 1], c->stream));
+      if (s >= 1) {
+        if (s + 1 <= S - 1) FDTD_HIP(hipStreamWaitEvent(c->rr, c->evAdj[(s + 1) & 1], 0));
+        rl.hist = seg_hist(c, s - 1);
+        rerun(s - 1, rl);
+        FDTD_HIP(hipEventRecord(c->evRerun, c->rr));
+      }
+    }
+  } else {
+    for (int s = S - 1; s >= 0; --s) {
+      if (S > 1 && s != S - 1) {
+        Lane ln = main_lane(c);
+        ln.hist = seg_hist(c, s);
+        rerun(s, ln);
+      }
+      adjoint(s);
+    }
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[3], c->stream));
@@ -694,7 +776,7 @@ fdtd_batch::MixLaunch &mix_launch(fdtd_batch *b, int kind, int s) {
     fdtd_ctx *c = b->inst[k];
     const bool on = b->tb[k] && c->nTb > 0 && kind != MIX_SINGLE;
     Mix2D<T> d{};
-    d.ps = params2d_at<T>(c, false, s, 0, true);
+    d.ps = params2d_at<T>(c, false, s, 0, true, c->hist.p);
     d.ps.tlist = on ? c->tbRest.as<int>() : nullptr;
     d.nrest = on ? c->nRest : step2d_blocks(c->nx, c->ny, 0);
     int first = 0, count = 0, sp = s;  // super-tiles [first, first+count) of the pair entered after sp steps
@@ -707,7 +789,7 @@ fdtd_batch::MixLaunch &mix_launch(fdtd_batch *b, int kind, int s) {
       count = c->nEarly;
       sp = s + 1;
     }
-    d.pt = params2d_at<T>(c, false, sp, 0, true);
+    d.pt = params2d_at<T>(c, false, sp, 0, true, c->hist.p);
     if (count > 0) {
       d.tiles = c->tbTiles.as<int>() + first;
       d.ntb = count;
