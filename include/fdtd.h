@@ -106,8 +106,11 @@ typedef struct {
                             store only K steps of it plus a full-state snapshot
                             every K steps; the adjoint re-runs each K-step
                             segment of the forward from its snapshot, newest
-                            first, before the adjoint steps that need it.  Both
-                            give bit-identical gradients. */
+                            first, before the adjoint steps that need it (when
+                            the budget holds a second K-step history, on a
+                            stream of the context's own, beside the adjoint
+                            sweep of the segment after it).  Both give
+                            bit-identical gradients. */
   void *stream;          /* hipStream_t or NULL */
 } fdtd_config;
 
