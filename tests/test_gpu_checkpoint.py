@@ -2,8 +2,9 @@
 steps and segment re-runs in the adjoint give the same objective and the same
 gradient, bit for bit, as the stored full history (the kernels are
 deterministic and the re-run repeats the forward's arithmetic exactly), for
-ragged last segments, K = 1, K >= N, both precisions and both dimensions.
-Calls go through the C ABI."""
+ragged last segments, K = 1, K >= N, both precisions and both dimensions,
+with the re-runs overlapping the adjoint on a second stream (two history
+buffers) and without (a budget for one).  Calls go through the C ABI."""
 import numpy as np
 import pytest
 
@@ -74,6 +75,25 @@ def test_checkpoints_fit_where_the_full_history_does_not(gpu):
     F, grad = g.run(W.seeded_rho(w, 0))
     g.close()
     assert np.isfinite(F) and np.all(np.isfinite(grad))
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_checkpoint_with_one_history_buffer(gpu, dims):
+    """A budget that holds one K-step history but not two (two K-step
+    segments; the history dominates the one snapshot): the re-run stays on
+    the context stream instead of overlapping the adjoint.  Still bit for bit
+    the stored-history result."""
+    w = W.tiny2d(n_steps=4400) if dims == 2 else W.tiny3d(n_steps=3600)
+    K = w["n_steps"] // 2
+    hist = K * (1 if dims == 2 else 3) * int(np.prod(w["design_n"])) * 8
+    rho = W.seeded_rho(w, 0)
+    F0, g0, d0 = run(gpu, w, rho, 0)
+    g = gpu.FDTD(w, ckpt_every=K, history_budget_bytes=int(1.4 * hist))
+    F, grad = g.run(rho.astype(g.dtype))
+    d = g.dft()
+    g.close()
+    say(f"[ckpt] one history buffer, {dims}D, K={K}: F {F:.15e} vs {F0:.15e}")
+    assert F == F0 and np.array_equal(grad, g0) and np.array_equal(d, d0)
 
 
 def test_c3_checkpoint_every_500_matches_stored_history(gpu):
