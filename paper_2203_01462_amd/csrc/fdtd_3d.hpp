@@ -39,7 +39,7 @@ struct Arena3 {
   uint64_t total;  // elements
 };
 
-inline Arena3 arena3_layout(int nx, int ny, int nz, int pitch, int P) {
+inline Arena3 arena3_layout(int ny, int nz, int pitch, int P) {
   auto up = [](uint64_t v) { return (v + 63) & ~uint64_t(63); };
   Arena3 a{};
   const uint64_t PL = (uint64_t)pitch * ny;

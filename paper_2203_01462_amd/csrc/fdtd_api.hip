@@ -271,7 +271,7 @@ void create_3d(fdtd_ctx *c) {
   c->nmon = 3 * c->ng;
   c->jref = c->lo3[2] - 2;
   c->L = c->hi3[2] + 2 - c->jref + 1;
-  c->lay3 = arena3_layout(c->nx, c->ny, c->nz, c->pitch, P);
+  c->lay3 = arena3_layout(c->ny, c->nz, c->pitch, P);
   // kernels address a copy with 32-bit byte offsets
   if (c->lay3.total * (uint64_t)c->esz >= (uint64_t(1) << 32))
     throw einval("3D state too large for one 4 GiB arena per copy (fields + absorber memories)");
