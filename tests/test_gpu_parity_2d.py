@@ -3,7 +3,6 @@
 Bars: FP64 build <= 1e-11 relative L2 on the gap DFT, the objective and the
 gradient; FP32 build <= 1e-4 on the DFT/objective and <= 1e-3 on the gradient.
 Every call goes through the C ABI (paper_2203_01462_amd.FDTD)."""
-import os
 import sys
 
 import numpy as np
