@@ -207,6 +207,38 @@ class _Exact:
         self.filt.close()
 
 
+class _ExactBatch:
+    """Forward + adjoint FDTD of several candidate designs in one batched
+    solve (fdtd_batch_*: the instance replicated, graph replay)."""
+
+    def __init__(self, w, alpha, radius, count):
+        shape = W.design_shape(w)
+        self.b = Batch([w] * count, stream=_stream_handle())
+        self.filt = design.Filter(shape, radius, torch.float32)
+        self.alpha = alpha
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.rf = [torch.empty(shape, device=dev) for _ in range(count)]
+        self.gt = [torch.empty(shape, device=dev) for _ in range(count)]
+        self.gx = [torch.empty(shape, device=dev) for _ in range(count)]
+        self.solves = 0
+
+    def __call__(self, xs):
+        for k, x in enumerate(xs):
+            self.filt.apply(x, self.alpha, out=self.rf[k])
+            self.b.set_density(k, self.rf[k])
+        F = self.b.forward()
+        self.b.adjoint()
+        for k in range(len(xs)):
+            self.b.gradient(k, out=self.gt[k])
+            self.filt.transpose(self.gt[k], out=self.gx[k])
+        self.solves += 2 * len(xs)
+        return [float(f) for f in F]
+
+    def close(self):
+        self.b.close()
+        self.filt.close()
+
+
 def plain(w, alpha=1.0, radius=2.5, max_iter=60, max_inner=40):
     """The design loop alone at one level; returns [(t, F)] per outer iteration."""
     trace = []
@@ -229,7 +261,13 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
     A proposal: `inner` MMA steps (move limit `move`) on the surrogate, whose
     log F and log-derivative are shifted by the exact-minus-predicted
     difference at the current design (so its first step is the exact MMA
-    step); the iterate with the best shifted prediction is checked."""
+    step); the iterate with the best shifted prediction is checked.  With a
+    tuple of move limits, one proposal per limit is made and all of them are
+    checked in one batched FDTD solve; the best is accepted if it raises F,
+    and every checked design joins the training set."""
+    moves = tuple(move) if isinstance(move, (tuple, list)) else (move,)
+    if inner < 1 or not moves:
+        raise ValueError("guided: need inner >= 1 and at least one move limit")
     shape = W.design_shape(w)
     dev = net.dev
     nd = int(np.prod(shape))
@@ -239,6 +277,7 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
     if tnet is not None:
         tnet.t = net.t
     ex = _Exact(w, alpha, radius)
+    exb = _ExactBatch(w, alpha, radius, len(moves)) if len(moves) > 1 else None
     mma = design.MMA(nd, torch.float32)
     x = torch.full(shape, 0.5, device=dev)
     xs = torch.empty_like(x)
@@ -263,20 +302,18 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
         Fh, Sh = net1.forward(rs.reshape(1, *shape))
         return float(Fh[0]) * data.sd + data.mu, Sh[0] * data.gsd
 
-    while stats["checks"] < checks:
-        ta = time.perf_counter()
-        lf0, S0 = predict(x)
-        dlf = math.log(F) - lf0          # value shift
-        corr = gt / F - S0               # log-derivative shift
+    def propose(mv, lf0, S0, dlf, corr):
+        """The best shifted-prediction iterate of `inner` surrogate MMA steps
+        from x with move limit mv (into a new tensor) and its step index."""
         xs.copy_(x)
-        ms = design.MMA(nd, torch.float32, move=move)
-        best, kbest = -math.inf, 0
+        ms = design.MMA(nd, torch.float32, move=mv)
+        best, kbest, out = -math.inf, 0, torch.empty_like(x)
         for k in range(inner + 1):
             lf, S = predict(xs) if k else (lf0, S0)
             val = lf + dlf
             if k and val > best:
                 best, kbest = val, k
-                xbest.copy_(xs)
+                out.copy_(xs)
             if k == inner:
                 break
             torch.add(S, corr, out=gs)
@@ -287,12 +324,33 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
             ms.accept(xnew)
             xs.copy_(xnew)
         ms.close()
-        stats["best_step"].append(kbest)
+        return out, kbest
+
+    while stats["checks"] < checks:
+        ta = time.perf_counter()
+        lf0, S0 = predict(x)
+        dlf = math.log(F) - lf0          # value shift
+        corr = gt / F - S0               # log-derivative shift
+        cands = [propose(mv, lf0, S0, dlf, corr) for mv in moves]
         tb = time.perf_counter()
         clock["surrogate"] += tb - ta
-        Fs = ex(xbest)
+        if exb is None:
+            xbest.copy_(cands[0][0])
+            kbest = cands[0][1]
+            Fs = ex(xbest)
+            data.add(ex.rf, Fs, ex.gt)
+            new_gx, new_rf, new_gt = ex.gx, ex.rf, ex.gt
+        else:
+            Fl = exb([c[0] for c in cands])
+            for k in range(len(moves)):
+                data.add(exb.rf[k], Fl[k], exb.gt[k])
+            kb = int(np.argmax(Fl))
+            xbest.copy_(cands[kb][0])
+            kbest = cands[kb][1]
+            Fs = Fl[kb]
+            new_gx, new_rf, new_gt = exb.gx[kb], exb.rf[kb], exb.gt[kb]
+        stats["best_step"].append(kbest)
         stats["checks"] += 1
-        data.add(ex.rf, Fs, ex.gt)
         tc = time.perf_counter()
         clock["check"] += tc - tb
         if Fs > F:
@@ -303,9 +361,9 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
             mma.accept(xbest)
             x.copy_(xbest)
             F = Fs
-            gx.copy_(ex.gx)
-            rf.copy_(ex.rf)
-            gt.copy_(ex.gt)
+            gx.copy_(new_gx)
+            rf.copy_(new_rf)
+            gt.copy_(new_gt)
         else:
             # one exact GCMMA step from x (as in the plain loop)
             stats["fallback"] += 1
@@ -337,9 +395,11 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
             log(f"guided: check {stats['checks']} F {F:.6g} proposal {Fs:.6g} (step {kbest}) "
                 f"t {trace[-1][0]:.2f} s")
     torch.cuda.synchronize()
-    stats["solves"] = ex.solves
+    stats["solves"] = ex.solves + (exb.solves if exb is not None else 0)
     stats["clock"] = clock
     ex.close()
+    if exb is not None:
+        exb.close()
     mma.close()
     filt.close()
     return trace, stats
@@ -384,7 +444,8 @@ def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60,
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         t = time.perf_counter()
-        data = Dataset(W.design_shape(w)[0], samples + 4 * checks + 8, torch.device("cuda"))
+        widest = max(len(st[0]) if isinstance(st[0], (tuple, list)) else 1 for st in settings)
+        data = Dataset(W.design_shape(w)[0], samples + (widest + 3) * checks + 8, torch.device("cuda"))
         generate(w, samples, alpha=alpha, seed=seed, data=data, log=log)
         out["generate_s"] = time.perf_counter() - t
         data.set_norms()
@@ -439,13 +500,16 @@ def main(argv=None):
     ap.add_argument("--inner", type=int, default=4)
     ap.add_argument("--n-steps", type=int, default=5000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--settings", default="0.2:2:4", help="comma-separated move:tune_steps[:inner] settings")
+    ap.add_argument("--settings", default="0.2:2:4",
+                    help="comma-separated move:tune_steps[:inner] settings; move may be m1/m2/... (one proposal "
+                         "per move limit, checked together in one batched solve)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     settings = []
     for item in a.settings.split(","):
         f = item.split(":")
-        settings.append((float(f[0]), int(f[1])) + ((int(f[2]),) if len(f) > 2 else ()))
+        mv = tuple(float(m) for m in f[0].split("/"))
+        settings.append((mv if len(mv) > 1 else mv[0], int(f[1])) + ((int(f[2]),) if len(f) > 2 else ()))
     res = compare(a.samples, a.train_steps, a.batch, a.alpha, a.plain_iters, a.checks, a.inner, a.seed, a.n_steps,
                   settings=settings, log=lambda m: print(m, flush=True))
     summary = {k: v for k, v in res.items() if not k.endswith("_trace") and k not in ("train_hist", "guided")}

@@ -48,8 +48,8 @@ def test_compare_runs_and_keeps_improvements(mods):
     W, FDTD, S = mods
     w = small(W)
     res = S.compare(samples=64, train_steps=40, batch=4, plain_iters=3, checks=3, inner=3, w=w,
-                    settings=((0.1, 2), (0.2, 0)), log=lambda m: None)
-    assert len(res["guided"]) == 2
+                    settings=((0.1, 2), (0.2, 0), ((0.1, 0.2, 0.3), 2)), log=lambda m: None)
+    assert len(res["guided"]) == 3
     for run in res["guided"]:
         g = [F for _, F in run["trace"]]
         assert all(b >= a for a, b in zip(g, g[1:])), g
@@ -60,5 +60,8 @@ def test_compare_runs_and_keeps_improvements(mods):
         assert abs(res["plain_trace"][0][1] - g[0]) <= 1e-5 * abs(g[0])
     # every run checks a surrogate iterate, never the unmoved design
     assert res["guided"][0]["stats"]["best_step"][0] >= 1
+    # three proposals per check, solved together: 3 forward + 3 adjoint per check
+    # beside the start design's solves and any fallback steps
+    assert res["guided"][2]["stats"]["solves"] >= 2 + 6 * 3
     assert res["plain_trace"][0][0] == 0.0
     assert np.isfinite(res["val"]["grad_cos_mean"])
