@@ -31,30 +31,42 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per time step of the step kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (scaled by the copy-probe factors: fetch x2, write x1), recorded with
-# the kernel source they were taken on.  Reported only while that source is
-# unchanged; the summaries live in profiles/.
+# the sources they were taken on: the kernels and the library code that
+# orders their workgroups.  Reported only while those sources are unchanged;
+# the summaries live in profiles/.
+SRC_2D = ["paper_2203_01462_amd/csrc/fdtd_2d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
+SRC_3D = ["paper_2203_01462_amd/csrc/fdtd_3d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "b435b02ff6a4150e",
+    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "PENDING",
                         "fwd": 104.9e6, "adj": 109.1e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step of all 64 instances = one step2d_batch_mix_kernel launch
-    "tmz2d_batch64_c4": {"source": "paper_2203_01462_amd/csrc/fdtd_2d.hip", "sha256_16": "b435b02ff6a4150e",
+    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "PENDING",
                          "fwd": 596.9e6, "adj": 617.6e6,
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = step3d_general (three launches) + step3d_plain
-    "yee3d_256_fp32": {"source": "paper_2203_01462_amd/csrc/fdtd_3d.hip", "sha256_16": "f653f34f279470fb",
+    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "PENDING",
                        "fwd": 1303.1e6, "adj": 1338.6e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
 }
 
 
-def measured_traffic(name):
+def sources_sha(paths):
+    """First 16 hex digits of the SHA-256 of the files' bytes, concatenated in order."""
     import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
     rec = MEASURED_TRAFFIC.get(name)
     if rec is None:
         return None, None
     try:
-        h = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()[:16]
+        h = sources_sha(rec["sources"])
     except OSError:
         return None, None
     if h != rec["sha256_16"]:

@@ -730,6 +730,7 @@ static void launch_one(const Step2D<T> &p0, int n, int par, int rows, hipStream_
 Tb2dPlan tb2d_plan(int nx, int ny, int P, int ia, int ib, int ja, int jb, const int dbox[4], const int gbox[4]) {
   Tb2dPlan pl;
   const int nbx = (nx + TXW - 1) / TXW, nsy = ny / TBY;
+  pl.nbx = nbx;
   const int tyb = WAVES * RDEF, nby = (ny + tyb - 1) / tyb;
   std::vector<char> ok((size_t)nbx * std::max(nsy, 1), 0);
   auto meets = [](int a0, int a1, int b0, int bn) { return bn > 0 && a1 >= b0 && a0 <= b0 + bn - 1; };

@@ -60,6 +60,7 @@ int step2d_blocks(int nx, int ny, int rows);
 struct Tb2dPlan {
   std::vector<int> tb;    // super-tiles: ((sy * nbx + tx) << 1) | border
   std::vector<int> rest;  // per-step workgroup tiles (ty * nbx + tx) outside the super-tiles
+  int nbx = 0;            // workgroup tile columns (64 nodes wide)
 };
 Tb2dPlan tb2d_plan(int nx, int ny, int P, int ia, int ib, int ja, int jb, const int dbox[4], const int gbox[4]);
 
