@@ -41,7 +41,7 @@ struct fdtd_ctx {
   DevBuf fld3[3], fld3R[3], tbTiles, tbRest;
   DevBuf glist3;  // 3D: tile-chunk lists of the general update
   int gS = 0, gM = 0, gD = 0, gAxD = 0;  // lengths of the three lists in glist3
-  int nTb = 0, nRest = 0, nEarly = 0;  // tbTiles = [early interior super-tiles | border and other interior]
+  int nTb = 0, nRest = 0, nEarly = 0;  // tbTiles = [interior super-tiles (run early) | border ones]
   int ck = 0, nseg = 1;  // segment length (steps) and count; nseg = 1: full history
   size_t snap_bytes = 0;
   Step2D<float> p2f{}, p2fR{};
@@ -208,22 +208,23 @@ void create_2d(fdtd_ctx *c) {
   const int gbox[4] = {g.gap_lo[0], g.gap_lo[1], g.gap_n[0], g.gap_n[1]};
   Tb2dPlan pl = tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox);
   if (!pl.tb.empty()) {
-    // up to half of the super-tiles, all interior ones, run one launch early
-    // (beside the rest tiles' second step of the previous pair)
+    // the interior super-tiles run one launch early (beside the rest tiles'
+    // second step of the previous pair), the border ones after them
     std::vector<int> order;
     for (int code : pl.tb)
-      if (!(code & 1) && (int)order.size() < (int)pl.tb.size() / 2) order.push_back(code);
+      if (!(code & 1)) order.push_back(code);
     c->nEarly = (int)order.size();
     for (int code : pl.tb)
-      if (std::find(order.begin(), order.begin() + c->nEarly, code) == order.begin() + c->nEarly) order.push_back(code);
+      if (code & 1) order.push_back(code);
     c->nTb = (int)order.size();
     c->nRest = (int)pl.rest.size();
     // L2 locality: each XCD takes one contiguous band of the row-major
     // super-tiles of each launch's share (neighbours' halo lines then sit in
     // the same L2), and whole rest tile-rows, the rows dealt round-robin (the
-    // slow absorber and design rows spread over the XCDs).  Measured on the
-    // 2048^2 workload: 19.0 / 19.3 us per forward / adjoint step against
-    // 21.1 / 21.7 with both lists in row-major order.
+    // slow absorber and design rows spread over the XCDs).  On the 2048^2
+    // workload this cut the bytes fetched per step by 41% and the time per
+    // forward / adjoint step from 21.1 / 21.7 us (both lists in row-major
+    // order) to 19.1 / 19.4 us.
     const int ne = c->nEarly, nl = c->nTb - c->nEarly, nbx = pl.nbx;
     deal_to_xcds(order, 0, ne, [&](int i, int) { return (int)((int64_t)i * 8 / ne); });
     deal_to_xcds(order, ne, c->nTb, [&](int i, int) { return (int)((int64_t)i * 8 / nl); });
@@ -537,9 +538,9 @@ void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_b
 // step j has step number nof(j), history base hbase and history flag hon(j).
 // With two-step blocking (2D, nTb > 0) the steps go in pairs, pipelined two
 // launches per pair: launch A of pair q = the rest tiles' first step of q and
-// the late super-tiles of q (all super-tiles for the first pair); launch B =
-// the rest tiles' second step of q and the early super-tiles of pair q+1.
-// The early super-tiles reach only other super-tiles, whose state after the
+// the border super-tiles of q (all super-tiles for the first pair); launch B
+// = the rest tiles' second step of q and the interior super-tiles of pair
+// q+1, run early.  Those reach only other super-tiles, whose state after the
 // pair is already written, and write their output into the copy that the
 // rest tiles read in that launch only outside the super-tiles.  An odd last
 // step is a full-grid single step.
@@ -564,7 +565,7 @@ void run_block(fdtd_ctx *c, bool rerun, bool adjoint, int s0, int count, NOF nof
     const int first = q == 0 ? 0 : c->nEarly;
     launch_step2d_mix<T>(pa, nof(2 * q), c->nRest, pt, tiles + first, c->nTb - first, out(q, 0), out(q, 1),
                          out(q, 2), adjoint, ln.s);
-    // launch B of pair q (+ the early super-tiles of pair q+1)
+    // launch B of pair q (+ the interior super-tiles of pair q+1)
     const Step2D<T> pb = step(2 * q + 1);
     const bool next = q + 1 < P;
     const Step2D<T> pn = next ? params2d_at<T>(c, rerun, s0 + 2 * q + 2, hbase, hon(2 * q + 2), ln.hist) : pt;
