@@ -8,6 +8,8 @@ energy objective of eq. (24), mirror symmetry, amplitude scaling) or an
 independent derivative (central finite differences of the oracle's own
 forward solve).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -230,6 +232,26 @@ def test_cpml_reflection_below_minus_40db(oracle_mod):
     assert err < 1e-2, err
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """name -> value pairs of a fixture in tests/golden (text after '#' ignored)."""
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            tok = line.split("#")[0].split()
+            if tok:
+                vals[tok[0]] = float(tok[1])
+    return vals
+
+
+def test_silver_fit_is_the_papers():
+    """The silver parameters the workloads and the Fresnel pin use are the
+    fit the paper prints (Sec. 2)."""
+    assert W.SILVER_PAPER == _golden("silver_drude_fit.txt")
+
+
 def _fresnel_run(oracle_mod, dx, silver=True):
     nm = 1e-9
     ncell = lambda L: int(round(L / dx))
@@ -238,7 +260,7 @@ def _fresnel_run(oracle_mod, dx, silver=True):
     front = ncell(240 * nm)
     ny = 2 * P + 2 + 3 + front + thick + 3
     ja = P + 2
-    par = W.SILVER_PAPER if silver else W.DRUDE
+    par = _golden("silver_drude_fit.txt") if silver else W.DRUDE
     w = W.with_(W.tiny2d(), n=(4, ny, 1), dx=dx, periodic_x=True, pml_cells=P, tfsf_margin=2,
                 eps_s=1.0, eps_g=1.0, sigma_max=0.0, gamma_mult=1.0, psi_s_ratio=0.01,
                 design_lo=(0, ja + 1 + front, 0), design_n=(4, thick, 1),
