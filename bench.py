@@ -37,15 +37,15 @@ HBM_PEAK_GBS = 8000.0
 SRC_2D = ["paper_2203_01462_amd/csrc/fdtd_2d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 SRC_3D = ["paper_2203_01462_amd/csrc/fdtd_3d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "9dfbb8c0ec956cc7",
+    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "b47c0ef325601263",
                         "fwd": 77.2e6, "adj": 81.5e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step of all 64 instances = one step2d_batch_mix_kernel launch
-    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "9dfbb8c0ec956cc7",
+    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "b47c0ef325601263",
                          "fwd": 500.0e6, "adj": 521.3e6,
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = step3d_general (three launches) + step3d_plain
-    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "2420f8979a0d814c",
+    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "d8e3e17bb6885fbf",
                        "fwd": 1303.1e6, "adj": 1338.6e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
 }

@@ -234,13 +234,14 @@ fdtd_status fdtd_batch_depth(fdtd_batch *b, int32_t index, int32_t *depth_out);
 /* Release the batch and all instances.  NULL is accepted. */
 fdtd_status fdtd_batch_destroy(fdtd_batch *b);
 
-/* Message of the last failing call on `b` (or of the last failing
- * fdtd_batch_create when b is NULL). */
+/* Message of the last failing call on `b` (or, when b is NULL, of the
+ * calling thread's last failing fdtd_batch_create). */
 const char *fdtd_batch_last_error(const fdtd_batch *b);
 
-/* Message of the last failing call on `ctx` (or of the last failing
- * fdtd_create when ctx is NULL).  Owned by the library; valid until the next
- * call on the same context. */
+/* Message of the last failing call on `ctx` (or, when ctx is NULL, of the
+ * calling thread's last failing fdtd_create).  Owned by the library; valid
+ * until the next call on the same context (or the next fdtd_create on the
+ * same thread). */
 const char *fdtd_last_error(const fdtd_ctx *ctx);
 
 #ifdef __cplusplus

@@ -65,7 +65,7 @@ struct fdtd_ctx {
 
 namespace {
 
-std::string g_create_error;
+thread_local std::string g_create_error;  // per thread: creates may run on several threads
 
 Error einval(const std::string &m) { return Error{FDTD_EINVAL, m}; }
 
@@ -778,7 +778,7 @@ struct fdtd_batch {
 
 namespace {
 
-std::string g_batch_error;
+thread_local std::string g_batch_error;
 
 // Launch one time step of every instance (one launch per tile-depth group).
 template <typename T>
