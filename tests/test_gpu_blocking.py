@@ -69,3 +69,31 @@ def test_blocked_schedule_bit_identical_to_per_step(gpu, n_steps):
         print(f"[blocking] N={n_steps} K={K}: F {F:.17e} vs {F_ref:.17e}", flush=True)
         assert F == F_ref, (K, F, F_ref)
         assert np.array_equal(grad, g_ref), K
+
+
+def test_blocked_schedule_bit_identical_full_size(gpu):
+    """The 2048^2 workload's grid and physics in FP64, 6001 steps (the pulse
+    peak reaches the gap; an odd count ends on a single step): the single
+    context's blocked schedule, with its super-tile and rest lists in XCD order
+    at this size, against the one-instance per-step batch, to the last bit;
+    also with checkpoints every 1000 steps (segment re-runs beside the
+    adjoint sweep)."""
+    import fdtd_workloads as W
+    w = W.with_(W.c2(), precision=64, n_steps=6001)
+    assert super_tiles(w) > 3000
+    rho = W.seeded_rho(w, 0)
+    print("[blocking] 2048^2 fp64 x 6001: per-step batch reference", flush=True)
+    b = gpu.Batch([w], rows=2, depth=1)
+    b.set_density(0, rho)
+    F_ref = float(b.forward()[0])
+    b.adjoint()
+    g_ref = b.gradient(0)
+    b.close()
+    assert F_ref > 0 and np.abs(g_ref).max() > 0
+    for K in (0, 1000):
+        g = gpu.FDTD(w, ckpt_every=K)
+        F, grad = g.run(rho)
+        g.close()
+        print(f"[blocking] 2048^2 K={K}: F {F:.17e} vs {F_ref:.17e}", flush=True)
+        assert F == F_ref, (K, F, F_ref)
+        assert np.array_equal(grad, g_ref), K
