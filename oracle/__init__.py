@@ -93,6 +93,7 @@ def lib():
             getattr(L, pre + "_adjoint_ext").argtypes = [P, dp, dp]
             getattr(L, pre + "_step_free").argtypes = [P, C.c_int]
             getattr(L, pre + "_incident_column").argtypes = [P, C.c_int, dp]
+            getattr(L, pre + "_set_checkpoint").argtypes = [P, C.c_int]
         dpa = C.POINTER(dp)
         L.or3d_set_state.argtypes = [P, dpa, dpa, dpa]
         L.or3d_get_state.argtypes = [P, dpa, dpa, dpa]
@@ -161,7 +162,10 @@ class OracleError(RuntimeError):
 class Oracle:
     """One problem instance of the CPU oracle (2D TMz or 3D)."""
 
-    def __init__(self, w):
+    def __init__(self, w, ckpt_every=0):
+        """ckpt_every = K > 0 keeps K steps of design-edge history plus a
+        snapshot of the state every K steps; the adjoint re-runs each segment
+        (same results as the full history, bounded host memory)."""
         self.w = dict(w)
         self.dims = w["dims"]
         self.pre = "or2d" if self.dims == 2 else "or3d"
@@ -181,6 +185,8 @@ class Oracle:
         dnx, dny, dnz = w["design_n"]
         self.dshape = (dnz, dny, dnx) if self.dims == 3 else (dny, dnx)
         self.N = w["n_steps"]
+        if ckpt_every:
+            self._check(self._fn("set_checkpoint")(self.h, int(ckpt_every)))
 
     def _fn(self, name):
         return getattr(lib(), self.pre + "_" + name)

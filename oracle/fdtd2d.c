@@ -66,8 +66,16 @@ typedef struct or2d {
   double *rho;
   double *dft;   /* [K][ng][2] */
   double *gapE;  /* [N+1][ng] */
-  double *hist;  /* [N][nd]: E^{n+1} on design edges */
+  double *hist;  /* [hist_steps][nd]: E^{n+1} on design edges, slot n - hist_base */
+  int hist_steps, hist_base, hist_on, mon_on;
   double *gEps, *gSig, *gPsi;
+  /* segment checkpointing (ck > 0): a snapshot of the forward state at the
+   * start of every ck-step segment, and a second state (the r* arrays) on
+   * which the adjoint re-runs each segment to refill a ck-step history */
+  int ck, nseg;
+  size_t snap_len;
+  double *snap;
+  double *rEz, *rHx, *rHy, *rJ, *rpHx, *rpHy, *rpEx, *rpEy;
   double F;
   int state; /* 0 created, 1 density set, 2 forward done, 3 adjoint done */
   char err[256];
@@ -121,7 +129,8 @@ void or2d_destroy(or2d *o) {
   double **ptrs[] = {&o->freqs, &o->wts, &o->bxe, &o->axe, &o->kxe, &o->bxh, &o->axh, &o->kxh,
                      &o->bye, &o->aye, &o->kye, &o->byh, &o->ayh, &o->kyh, &o->Ez, &o->Hx, &o->Hy,
                      &o->J, &o->pHx, &o->pHy, &o->pEx, &o->pEy, &o->einc, &o->hinc, &o->rho,
-                     &o->dft, &o->gapE, &o->hist, &o->gEps, &o->gSig, &o->gPsi};
+                     &o->dft, &o->gapE, &o->hist, &o->gEps, &o->gSig, &o->gPsi, &o->snap,
+                     &o->rEz, &o->rHx, &o->rHy, &o->rJ, &o->rpHx, &o->rpHy, &o->rpEx, &o->rpEy};
   for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; ++k) free(*ptrs[k]);
   free(o->inx_e); free(o->inx_h); free(o->iny_e); free(o->iny_h);
   free(o);
@@ -192,11 +201,8 @@ int or2d_create(const or_cfg *cfg, or2d **out) {
   o->gEps = (double *)calloc((size_t)o->nd, sizeof(double));
   o->gSig = (double *)calloc((size_t)o->nd, sizeof(double));
   o->gPsi = (double *)calloc((size_t)o->nd, sizeof(double));
-  const double hist_bytes = 8.0 * (double)o->N * o->nd;
-  if (hist_bytes > 24e9) { or2d_destroy(o); return fail(NULL, OR_ENOMEM, "design history would exceed 24 GB"); }
-  o->hist = (double *)malloc(sizeof(double) * (size_t)o->N * o->nd);
   if (!o->freqs || !o->wts || !o->Ez || !o->Hx || !o->Hy || !o->J || !o->pHx || !o->pHy || !o->pEx ||
-      !o->pEy || !o->rho || !o->dft || !o->gapE || !o->hist || !o->gEps || !o->gSig || !o->gPsi ||
+      !o->pEy || !o->rho || !o->dft || !o->gapE || !o->gEps || !o->gSig || !o->gPsi ||
       !o->bxe || !o->kyh || !o->inx_e || !o->iny_h) {
     or2d_destroy(o);
     return fail(NULL, OR_ENOMEM, "out of memory");
@@ -323,7 +329,7 @@ static void fwd_e(or2d *o, int n, int tf, const double *qsrc, double *efull_out)
       }
     }
   /* monitors: gap time series and running DFT at time (n+1) dt; design history */
-  for (int gj = 0; gj < o->gny; ++gj)
+  for (int gj = 0; gj < (o->mon_on ? o->gny : 0); ++gj)
     for (int gi = 0; gi < o->gnx; ++gi) {
       const int g = gj * o->gnx + gi;
       const double e = o->Ez[IX(o, o->gx0 + gi, o->gy0 + gj)];
@@ -334,9 +340,9 @@ static void fwd_e(or2d *o, int n, int tf, const double *qsrc, double *efull_out)
         o->dft[((size_t)k * o->ng + g) * 2 + 1] -= dt * e * sin(ph);
       }
     }
-  for (int dj = 0; dj < o->dny; ++dj)
+  for (int dj = 0; dj < (o->hist_on ? o->dny : 0); ++dj)
     for (int di = 0; di < o->dnx; ++di)
-      o->hist[(size_t)n * o->nd + dj * o->dnx + di] = o->Ez[IX(o, o->dx0 + di, o->dy0 + dj)];
+      o->hist[(size_t)(n - o->hist_base) * o->nd + dj * o->dnx + di] = o->Ez[IX(o, o->dx0 + di, o->dy0 + dj)];
   if (efull_out) memcpy(efull_out + (size_t)n * nx * ny, o->Ez, sizeof(double) * nx * ny);
 }
 
@@ -355,11 +361,98 @@ static double objective_from_monitors(const or2d *o) {
   return F;
 }
 
+/* ------------------------------------------------------- checkpointing */
+
+/* Walk the forward state in a fixed order, copying it to (save) or from
+ * (load) buf: E_z, H_x, H_y whole, J over the design box, and each absorber
+ * memory only on the rows/columns where its grading is active (it is zero
+ * elsewhere).  Returns the number of doubles; buf = NULL only counts. */
+static size_t snap_io(or2d *o, double *buf, int save) {
+  const int nx = o->nx, ny = o->ny;
+  const size_t n2 = (size_t)nx * ny;
+  size_t k = 0;
+  double *whole[3] = {o->Ez, o->Hx, o->Hy};
+  for (int f = 0; f < 3; ++f) {
+    if (buf) { if (save) memcpy(buf + k, whole[f], n2 * sizeof(double)); else memcpy(whole[f], buf + k, n2 * sizeof(double)); }
+    k += n2;
+  }
+  if (buf && !save) memset(o->J, 0, n2 * sizeof(double));
+  for (int dj = 0; dj < o->dny; ++dj)
+    for (int di = 0; di < o->dnx; ++di, ++k) {
+      double *v = &o->J[IX(o, o->dx0 + di, o->dy0 + dj)];
+      if (buf) { if (save) buf[k] = *v; else *v = buf[k]; }
+    }
+  /* memory arrays and the flag that marks where each one is updated */
+  double *mem[4] = {o->pHx, o->pHy, o->pEx, o->pEy};
+  for (int f = 0; f < 4; ++f) {
+    if (buf && !save) memset(mem[f], 0, n2 * sizeof(double));
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int on = f == 0 ? o->iny_h[j] : f == 1 ? o->inx_h[i] : f == 2 ? o->inx_e[i] : o->iny_e[j];
+        if (!on) continue;
+        if (buf) { if (save) buf[k] = mem[f][IX(o, i, j)]; else mem[f][IX(o, i, j)] = buf[k]; }
+        ++k;
+      }
+  }
+  return k;
+}
+
+/* Exchange the working state with the re-run state. */
+static void swap_state(or2d *o) {
+  double **a[8] = {&o->Ez, &o->Hx, &o->Hy, &o->J, &o->pHx, &o->pHy, &o->pEx, &o->pEy};
+  double **b[8] = {&o->rEz, &o->rHx, &o->rHy, &o->rJ, &o->rpHx, &o->rpHy, &o->rpEx, &o->rpEy};
+  for (int k = 0; k < 8; ++k) { double *t = *a[k]; *a[k] = *b[k]; *b[k] = t; }
+}
+
+/* Store E on the design edges for every step (every = 0), or only `every`
+ * steps of it plus a snapshot of the state at the start of every segment of
+ * `every` steps; the adjoint then re-runs each segment from its snapshot
+ * before the adjoint steps that read it.  Both give identical results. */
+int or2d_set_checkpoint(or2d *o, int every) {
+  if (every < 0) return fail(o, OR_EINVAL, "negative checkpoint interval");
+  o->ck = (every > 0 && every < o->N) ? every : 0;
+  free(o->hist); o->hist = NULL; o->hist_steps = 0;
+  free(o->snap); o->snap = NULL;
+  if (o->state > 1) o->state = 1;
+  return OR_OK;
+}
+
+/* Allocate the history (and, with checkpoints, the snapshots and the
+ * re-run state) for the current checkpoint interval. */
+static int ensure_history(or2d *o) {
+  const int steps = o->ck ? o->ck : o->N;
+  o->nseg = o->ck ? (o->N + o->ck - 1) / o->ck : 1;
+  o->snap_len = o->ck ? snap_io(o, NULL, 1) : 0;
+  const double bytes = 8.0 * ((double)steps * o->nd + (double)o->nseg * o->snap_len);
+  if (bytes > 40e9) return fail(o, OR_ENOMEM, "design history and snapshots would exceed 40 GB");
+  if (!o->hist || o->hist_steps != steps) {
+    free(o->hist);
+    o->hist = (double *)malloc(sizeof(double) * (size_t)steps * (o->nd > 0 ? o->nd : 1));
+    o->hist_steps = o->hist ? steps : 0;
+    if (!o->hist) return fail(o, OR_ENOMEM, "out of memory (history)");
+  }
+  if (o->ck && !o->snap) {
+    const size_t n2 = (size_t)o->nx * o->ny;
+    o->snap = (double *)malloc(sizeof(double) * o->snap_len * o->nseg);
+    double **r[8] = {&o->rEz, &o->rHx, &o->rHy, &o->rJ, &o->rpHx, &o->rpHy, &o->rpEx, &o->rpEy};
+    for (int k = 0; k < 8; ++k) if (!*r[k]) *r[k] = (double *)calloc(n2, sizeof(double));
+    if (!o->snap || !o->rEz || !o->rHx || !o->rHy || !o->rJ || !o->rpHx || !o->rpHy || !o->rpEx || !o->rpEy)
+      return fail(o, OR_ENOMEM, "out of memory (snapshots)");
+  }
+  return OR_OK;
+}
+
 static int run_forward(or2d *o, int tf, const double *qsrc, double *efull_out) {
+  int rc = ensure_history(o);
+  if (rc) return rc;
   zero_state(o);
   memset(o->dft, 0, sizeof(double) * o->K * o->ng * 2);
   memset(o->gapE, 0, sizeof(double) * (size_t)(o->N + 1) * o->ng);
+  o->mon_on = 1;
+  o->hist_on = !o->ck;
+  o->hist_base = 0;
   for (int n = 0; n < o->N; ++n) {
+    if (o->ck && n % o->ck == 0) snap_io(o, o->snap + (size_t)(n / o->ck) * o->snap_len, 1);
     fwd_h(o, n, tf);
     fwd_e(o, n, tf, qsrc ? qsrc + (size_t)n * o->nx * o->ny : NULL, efull_out);
   }
@@ -438,7 +531,7 @@ static void adj_step(or2d *o, int m, const double *ssrc, double *estar_out) {
       if (o->inx_h[i]) nHy[q] = o->bxh[i] * nHy[q] + o->axh[i] * Hy[q];
     }
   /* (4) E*^{m-1/2}, J*^{m-1/2}; sensitivity sums */
-  const double *Em = o->hist + (size_t)(m - 1) * o->nd;
+  const double *Em = o->hist ? o->hist + (size_t)(m - 1 - o->hist_base) * o->nd : NULL;
 #pragma omp parallel for schedule(static)
   for (int j = 1; j < ny - 1; ++j)
     for (int i = i_lo; i <= i_hi; ++i) {
@@ -476,7 +569,27 @@ int or2d_adjoint(or2d *o) {
   memset(o->gEps, 0, sizeof(double) * o->nd);
   memset(o->gSig, 0, sizeof(double) * o->nd);
   memset(o->gPsi, 0, sizeof(double) * o->nd);
-  for (int m = o->N; m >= 1; --m) adj_step(o, m, NULL, NULL);
+  if (!o->ck) {
+    o->hist_base = 0;
+    for (int m = o->N; m >= 1; --m) adj_step(o, m, NULL, NULL);
+  } else {
+    /* newest segment first: re-run the forward over steps [a, b) from the
+     * snapshot on the second state (history only, monitors off), then the
+     * adjoint steps m = b .. a+1 that read it */
+    for (int s = o->nseg - 1; s >= 0; --s) {
+      const int a = s * o->ck, b = a + o->ck < o->N ? a + o->ck : o->N;
+      swap_state(o);
+      snap_io(o, o->snap + (size_t)s * o->snap_len, 0);
+      o->mon_on = 0; o->hist_on = 1; o->hist_base = a;
+      for (int n = a; n < b; ++n) {
+        fwd_h(o, n, o->tf_on);
+        fwd_e(o, n, o->tf_on, NULL, NULL);
+      }
+      o->mon_on = 1;
+      swap_state(o);
+      for (int m = b; m >= a + 1; --m) adj_step(o, m, NULL, NULL);
+    }
+  }
   o->state = 3;
   return OR_OK;
 }
@@ -549,6 +662,7 @@ int or2d_forward_ext(or2d *o, const double *q, double *efull) {
 int or2d_adjoint_ext(or2d *o, const double *s, double *estar) {
   if (o->state < 1) return fail(o, OR_ESTATE, "adjoint before set_density");
   zero_state(o);
+  o->hist_base = 0;
   for (int m = o->N; m >= 1; --m) adj_step(o, m, s + (size_t)(m - 1) * o->nx * o->ny, estar);
   return OR_OK;
 }
@@ -576,7 +690,9 @@ int or2d_get_state(const or2d *o, double *Ez, double *Hx, double *Hy, double *J)
 
 int or2d_step_free(or2d *o, int k) {
   if (o->state < 1) return fail(o, OR_ESTATE, "step before set_density");
-  /* the step-0 monitor slots are overwritten; they are not used here */
+  /* monitors and history are off: only the fields evolve */
+  o->mon_on = 0;
+  o->hist_on = 0;
   for (int s = 0; s < k; ++s) {
     fwd_h(o, 0, 0);
     fwd_e(o, 0, 0, NULL, NULL);

@@ -46,8 +46,16 @@ typedef struct or3d {
   double *rho;
   double *dft;   /* [K][ng][3][2] */
   double *gapE;  /* [N+1][ng][3] */
-  double *hist;  /* [N][3][nd] */
+  double *hist;  /* [hist_steps][3][nd]: E^{n+1} on design edges, slot n - hist_base */
+  int hist_steps, hist_base, hist_on, mon_on;
   double *gEps, *gSig, *gPsi; /* [3][nd] */
+  /* segment checkpointing (ck > 0): a snapshot of the forward state at the
+   * start of every ck-step segment, and a second state (rE, rH, rJ, rpE,
+   * rpH) on which the adjoint re-runs each segment to refill the history */
+  int ck, nseg;
+  size_t snap_len;
+  double *snap;
+  double *rE[3], *rH[3], *rJ[3], *rpE[3][3], *rpH[3][3];
   int state;
   char err[256];
 } or3d;
@@ -100,7 +108,10 @@ void or3d_destroy(or3d *o) {
     free(o->be[a]); free(o->ae[a]); free(o->ike[a]); free(o->bh[a]); free(o->ah[a]); free(o->ikh[a]);
     free(o->ine[a]); free(o->inh[a]); free(o->E[a]); free(o->H[a]); free(o->J[a]);
     for (int b = 0; b < 3; ++b) { free(o->pE[a][b]); free(o->pH[a][b]); }
+    free(o->rE[a]); free(o->rH[a]); free(o->rJ[a]);
+    for (int b = 0; b < 3; ++b) { free(o->rpE[a][b]); free(o->rpH[a][b]); }
   }
+  free(o->snap);
   free(o->einc); free(o->hinc); free(o->rho); free(o->dft); free(o->gapE); free(o->hist);
   free(o->gEps); free(o->gSig); free(o->gPsi);
   free(o);
@@ -162,16 +173,13 @@ int or3d_create(const or_cfg *cfg, or3d **out) {
     bad |= !o->be[d] || !o->ae[d] || !o->ike[d] || !o->bh[d] || !o->ah[d] || !o->ikh[d] || !o->ine[d] || !o->inh[d] ||
            !o->E[d] || !o->H[d] || !o->J[d];
   }
-  const double hist_bytes = 8.0 * 3.0 * o->N * o->nd;
-  if (hist_bytes > 24e9) { or3d_destroy(o); return fail3(NULL, OR_ENOMEM, "design history would exceed 24 GB"); }
   o->rho = calloc((size_t)o->nd, sizeof(double));
   o->dft = calloc((size_t)o->K * (o->ng ? o->ng : 1) * 3 * 2, sizeof(double));
   o->gapE = calloc((size_t)(o->N + 1) * (o->ng ? o->ng : 1) * 3, sizeof(double));
-  o->hist = malloc(sizeof(double) * 3 * (size_t)o->N * o->nd);
   o->gEps = calloc(3 * (size_t)o->nd, sizeof(double));
   o->gSig = calloc(3 * (size_t)o->nd, sizeof(double));
   o->gPsi = calloc(3 * (size_t)o->nd, sizeof(double));
-  if (bad || !o->rho || !o->dft || !o->gapE || !o->hist || !o->gEps || !o->gSig || !o->gPsi) {
+  if (bad || !o->rho || !o->dft || !o->gapE || !o->gEps || !o->gSig || !o->gPsi) {
     or3d_destroy(o);
     return fail3(NULL, OR_ENOMEM, "out of memory");
   }
@@ -333,7 +341,7 @@ static void fwd_e3(or3d *o, int n, int tf, const double *qsrc, double *efull) {
         }
   }
   for (int c = 0; c < 3; ++c) {
-    for (int gk = 0; gk < o->gn[2]; ++gk)
+    for (int gk = 0; gk < (o->mon_on ? o->gn[2] : 0); ++gk)
       for (int gj = 0; gj < o->gn[1]; ++gj)
         for (int gi = 0; gi < o->gn[0]; ++gi) {
           const int g = (gk * o->gn[1] + gj) * o->gn[0] + gi;
@@ -345,10 +353,10 @@ static void fwd_e3(or3d *o, int n, int tf, const double *qsrc, double *efull) {
             o->dft[(((size_t)kf * o->ng + g) * 3 + c) * 2 + 1] -= dt * e * sin(ph);
           }
         }
-    for (int dk = 0; dk < o->dn[2]; ++dk)
+    for (int dk = 0; dk < (o->hist_on ? o->dn[2] : 0); ++dk)
       for (int dj = 0; dj < o->dn[1]; ++dj)
         for (int di = 0; di < o->dn[0]; ++di)
-          o->hist[((size_t)n * 3 + c) * o->nd + (dk * o->dn[1] + dj) * o->dn[0] + di] =
+          o->hist[((size_t)(n - o->hist_base) * 3 + c) * o->nd + (dk * o->dn[1] + dj) * o->dn[0] + di] =
               o->E[c][IX3(o, o->d0[0] + di, o->d0[1] + dj, o->d0[2] + dk)];
     if (efull) memcpy(efull + ((size_t)n * 3 + c) * n3, o->E[c], n3 * sizeof(double));
   }
@@ -368,12 +376,121 @@ static double objective3(const or3d *o) {
   return F;
 }
 
+/* ------------------------------------------------------- checkpointing */
+
+/* Walk the forward state in a fixed order, copying it to (save) or from
+ * (load) buf: E and H whole, J over the design box, and each absorber memory
+ * only where its grading is active (it is zero elsewhere).  Returns the
+ * number of doubles; buf = NULL only counts. */
+static size_t snap_io3(or3d *o, double *buf, int save) {
+  const size_t n = (size_t)o->nx * o->ny * o->nz;
+  size_t k = 0;
+  for (int c = 0; c < 3; ++c)
+    for (int f = 0; f < 2; ++f) {
+      double *a = f ? o->H[c] : o->E[c];
+      if (buf) { if (save) memcpy(buf + k, a, n * sizeof(double)); else memcpy(a, buf + k, n * sizeof(double)); }
+      k += n;
+    }
+  for (int c = 0; c < 3; ++c) {
+    if (buf && !save) memset(o->J[c], 0, n * sizeof(double));
+    for (int dk = 0; dk < o->dn[2]; ++dk)
+      for (int dj = 0; dj < o->dn[1]; ++dj)
+        for (int di = 0; di < o->dn[0]; ++di, ++k) {
+          double *v = &o->J[c][IX3(o, o->d0[0] + di, o->d0[1] + dj, o->d0[2] + dk)];
+          if (buf) { if (save) buf[k] = *v; else *v = buf[k]; }
+        }
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int u = 0; u < 3; ++u) {
+      if (u == c) continue;
+      for (int f = 0; f < 2; ++f) {
+        double *a = f ? o->pH[c][u] : o->pE[c][u];
+        const unsigned char *flag = f ? o->inh[u] : o->ine[u];
+        if (buf && !save) memset(a, 0, n * sizeof(double));
+        for (int kk = 0; kk < o->nz; ++kk)
+          for (int j = 0; j < o->ny; ++j)
+            for (int i = 0; i < o->nx; ++i) {
+              const int idx[3] = {i, j, kk};
+              if (!flag[idx[u]]) continue;
+              const size_t q = IX3(o, i, j, kk);
+              if (buf) { if (save) buf[k] = a[q]; else a[q] = buf[k]; }
+              ++k;
+            }
+      }
+    }
+  return k;
+}
+
+/* Exchange the working state with the re-run state. */
+static void swap3(or3d *o) {
+  for (int c = 0; c < 3; ++c) {
+    double *t;
+    t = o->E[c]; o->E[c] = o->rE[c]; o->rE[c] = t;
+    t = o->H[c]; o->H[c] = o->rH[c]; o->rH[c] = t;
+    t = o->J[c]; o->J[c] = o->rJ[c]; o->rJ[c] = t;
+    for (int u = 0; u < 3; ++u) {
+      t = o->pE[c][u]; o->pE[c][u] = o->rpE[c][u]; o->rpE[c][u] = t;
+      t = o->pH[c][u]; o->pH[c][u] = o->rpH[c][u]; o->rpH[c][u] = t;
+    }
+  }
+}
+
+/* Full history (every = 0) or `every` steps of it plus segment snapshots;
+ * see or2d_set_checkpoint.  Both give identical results. */
+int or3d_set_checkpoint(or3d *o, int every) {
+  if (every < 0) return fail3(o, OR_EINVAL, "negative checkpoint interval");
+  o->ck = (every > 0 && every < o->N) ? every : 0;
+  free(o->hist); o->hist = NULL; o->hist_steps = 0;
+  free(o->snap); o->snap = NULL;
+  if (o->state > 1) o->state = 1;
+  return OR_OK;
+}
+
+static int ensure_history3(or3d *o) {
+  const int steps = o->ck ? o->ck : o->N;
+  o->nseg = o->ck ? (o->N + o->ck - 1) / o->ck : 1;
+  o->snap_len = o->ck ? snap_io3(o, NULL, 1) : 0;
+  const double bytes = 8.0 * (3.0 * steps * o->nd + (double)o->nseg * o->snap_len);
+  if (bytes > 40e9) return fail3(o, OR_ENOMEM, "design history and snapshots would exceed 40 GB");
+  if (!o->hist || o->hist_steps != steps) {
+    free(o->hist);
+    o->hist = (double *)malloc(sizeof(double) * 3 * (size_t)steps * (o->nd > 0 ? o->nd : 1));
+    o->hist_steps = o->hist ? steps : 0;
+    if (!o->hist) return fail3(o, OR_ENOMEM, "out of memory (history)");
+  }
+  if (o->ck && !o->snap) {
+    const size_t n = (size_t)o->nx * o->ny * o->nz;
+    o->snap = (double *)malloc(sizeof(double) * o->snap_len * o->nseg);
+    int bad = !o->snap;
+    for (int c = 0; c < 3; ++c) {
+      if (!o->rE[c]) o->rE[c] = calloc(n, sizeof(double));
+      if (!o->rH[c]) o->rH[c] = calloc(n, sizeof(double));
+      if (!o->rJ[c]) o->rJ[c] = calloc(n, sizeof(double));
+      bad |= !o->rE[c] || !o->rH[c] || !o->rJ[c];
+      for (int u = 0; u < 3; ++u) {
+        if (u == c) continue;
+        if (!o->rpE[c][u]) o->rpE[c][u] = calloc(n, sizeof(double));
+        if (!o->rpH[c][u]) o->rpH[c][u] = calloc(n, sizeof(double));
+        bad |= !o->rpE[c][u] || !o->rpH[c][u];
+      }
+    }
+    if (bad) return fail3(o, OR_ENOMEM, "out of memory (snapshots)");
+  }
+  return OR_OK;
+}
+
 static int run_fwd3(or3d *o, int tf, const double *q, double *efull) {
+  int rc = ensure_history3(o);
+  if (rc) return rc;
   zero3(o);
   memset(o->dft, 0, sizeof(double) * o->K * (o->ng ? o->ng : 1) * 6);
   memset(o->gapE, 0, sizeof(double) * (size_t)(o->N + 1) * (o->ng ? o->ng : 1) * 3);
   const size_t n3 = (size_t)o->nx * o->ny * o->nz;
+  o->mon_on = 1;
+  o->hist_on = !o->ck;
+  o->hist_base = 0;
   for (int n = 0; n < o->N; ++n) {
+    if (o->ck && n % o->ck == 0) snap_io3(o, o->snap + (size_t)(n / o->ck) * o->snap_len, 1);
     fwd_h3(o, n, tf);
     fwd_e3(o, n, tf, q ? q + (size_t)n * 3 * n3 : NULL, efull);
   }
@@ -472,7 +589,7 @@ static void adj_step3(or3d *o, int m, const double *ssrc, double *estar) {
     e_range(o, c, lo, hi);
     double *Ec = o->E[c], *Jc = o->J[c];
     const double *Hv = o->H[v], *Hu = o->H[u], *nv = o->pH[v][u], *nu_ = o->pH[u][v];
-    const double *Em = o->hist + ((size_t)(m - 1) * 3 + c) * o->nd;
+    const double *Em = o->hist ? o->hist + ((size_t)(m - 1 - o->hist_base) * 3 + c) * o->nd : NULL;
 #pragma omp parallel for schedule(static)
     for (int k = lo[2]; k <= hi[2]; ++k)
       for (int j = lo[1]; j <= hi[1]; ++j)
@@ -516,7 +633,26 @@ int or3d_adjoint(or3d *o) {
   memset(o->gEps, 0, sizeof(double) * 3 * o->nd);
   memset(o->gSig, 0, sizeof(double) * 3 * o->nd);
   memset(o->gPsi, 0, sizeof(double) * 3 * o->nd);
-  for (int m = o->N; m >= 1; --m) adj_step3(o, m, NULL, NULL);
+  if (!o->ck) {
+    o->hist_base = 0;
+    for (int m = o->N; m >= 1; --m) adj_step3(o, m, NULL, NULL);
+  } else {
+    /* newest segment first: re-run the forward over steps [a, b) from its
+     * snapshot on the second state (history only), then adjoint m = b..a+1 */
+    for (int s = o->nseg - 1; s >= 0; --s) {
+      const int a = s * o->ck, b = a + o->ck < o->N ? a + o->ck : o->N;
+      swap3(o);
+      snap_io3(o, o->snap + (size_t)s * o->snap_len, 0);
+      o->mon_on = 0; o->hist_on = 1; o->hist_base = a;
+      for (int n = a; n < b; ++n) {
+        fwd_h3(o, n, o->tf_on);
+        fwd_e3(o, n, o->tf_on, NULL, NULL);
+      }
+      o->mon_on = 1;
+      swap3(o);
+      for (int m = b; m >= a + 1; --m) adj_step3(o, m, NULL, NULL);
+    }
+  }
   o->state = 3;
   return OR_OK;
 }
@@ -590,6 +726,7 @@ int or3d_forward_ext(or3d *o, const double *q, double *efull) {
 int or3d_adjoint_ext(or3d *o, const double *s, double *estar) {
   if (o->state < 1) return fail3(o, OR_ESTATE, "adjoint before set_density");
   zero3(o);
+  o->hist_base = 0;
   const size_t n3 = (size_t)o->nx * o->ny * o->nz;
   for (int m = o->N; m >= 1; --m) adj_step3(o, m, s + (size_t)(m - 1) * 3 * n3, estar);
   return OR_OK;
@@ -619,6 +756,8 @@ int or3d_get_state(const or3d *o, double *const *E, double *const *H, double *co
 
 int or3d_step_free(or3d *o, int k) {
   if (o->state < 1) return fail3(o, OR_ESTATE, "step before set_density");
+  o->mon_on = 0;  /* monitors and history off: only the fields evolve */
+  o->hist_on = 0;
   for (int s = 0; s < k; ++s) {
     fwd_h3(o, 0, 0);
     fwd_e3(o, 0, 0, NULL, NULL);
