@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 4
+#define FDTD_ABI_VERSION 5
 
 typedef enum {
   FDTD_OK = 0,
@@ -64,10 +64,15 @@ typedef enum {
   FDTD_ESTATE = 2,    /* call out of order (e.g. adjoint before forward) */
   FDTD_ENOMEM = 3,    /* device memory or history budget exhausted */
   FDTD_EDEVICE = 4,   /* HIP runtime error (no device, launch failure) */
-  FDTD_EUNSTABLE = 5  /* non-finite fields after a solve */
+  FDTD_EUNSTABLE = 5  /* runaway or non-finite fields (in-solve watchdog), or a non-finite objective */
 } fdtd_status;
 
-enum { FDTD_SRC_GAUSS = 0, FDTD_SRC_SINC_HANN = 1 };
+/* Excitation: the Gaussian-modulated carrier, the paper's Hann-windowed sinc
+ * (Sec. 2), or none (no plane wave: the fields evolve from the state given
+ * by fdtd_set_state, zero otherwise; objective weights are then 1). */
+enum { FDTD_SRC_GAUSS = 0, FDTD_SRC_SINC_HANN = 1, FDTD_SRC_NONE = 2 };
+/* Axes of pol_axis / prop_axis. */
+enum { FDTD_AXIS_DEFAULT = -1, FDTD_AXIS_X = 0, FDTD_AXIS_Y = 1, FDTD_AXIS_Z = 2 };
 enum { FDTD_OBJ_DFT = 0, FDTD_OBJ_TIME_ENERGY = 1 };
 enum { FDTD_W_ENHANCEMENT = 0, FDTD_W_UNIT = 1 };
 
@@ -81,6 +86,9 @@ typedef struct {
   int32_t n_steps;       /* N time steps of each solve */
   int32_t pml_cells;     /* CPML thickness (cells) next to each wall */
   int32_t tfsf_margin;   /* cells between the PML and the total-field box */
+  int32_t pol_axis;      /* axis of the incident E: TMz (dims 2) is z; dims 3 is x.  FDTD_AXIS_DEFAULT
+                            (-1) takes that axis; any other axis is EINVAL */
+  int32_t prop_axis;     /* propagation axis of the plane wave (towards +): TMz y, 3D z; -1 default */
   int32_t design_lo[3], design_n[3]; /* design box, nodes [lo, lo+n) per axis */
   int32_t gap_lo[3], gap_n[3];       /* gap (observation) box */
   int32_t source_kind;   /* FDTD_SRC_*: Gaussian-modulated carrier, or the paper's Hann-windowed 4-lobe sinc */
@@ -131,10 +139,12 @@ int32_t fdtd_abi_version(void);
  * ρ-independent tables (absorber grading, incident-field line, phasors,
  * weights).  Fails with EINVAL on: precision not 32/64, dims not 2/3,
  * Courant outside (0, 1/sqrt(dims)), n_steps < 1, n_freq < 1, non-positive
- * permittivities or negative material parameters, ckpt_every < 0, boxes
- * outside the total-field region; ENOMEM if the forward history (and, with
- * ckpt_every > 0, the snapshots) does not fit the budget or the device;
- * EDEVICE without a usable HIP device.  *out is NULL on failure. */
+ * permittivities or negative material parameters, ckpt_every < 0, axes other
+ * than the defaults, boxes outside the total-field region (with
+ * FDTD_SRC_NONE: outside the nodes 1 + pml_cells .. n - 2 - pml_cells);
+ * ENOMEM if the forward history (and, with ckpt_every > 0, the snapshots)
+ * does not fit the budget or the device; EDEVICE without a usable HIP device.
+ * *out is NULL on failure. */
 fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out);
 
 /* Set the density over the design box (eqs. (4)-(5)): `count` =
@@ -146,13 +156,19 @@ fdtd_status fdtd_set_density(fdtd_ctx *ctx, const void *rho, int64_t count, int3
 
 /* Forward FDTD solve over n_steps (eqs. (10a-c)) with the gap monitor;
  * writes the objective F to *objective_out (host; may be NULL) and returns
- * after the solve has finished.  Requires a density (ESTATE). */
+ * after the solve has finished.  Requires a density (ESTATE).  A watchdog
+ * reads the largest |E| every 1024 steps while the solve runs; on a
+ * non-finite value or one above 1e10 times the reference amplitude (the
+ * incident amplitude, or with FDTD_SRC_NONE the largest value of the state
+ * set by fdtd_set_state) the solve stops and returns EUNSTABLE, naming the
+ * step, and the forward result is invalid. */
 fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out);
 
 /* Adjoint FDTD solve (eq. (20)): time-reversed, driven by dF/dE at the gap,
  * accumulating the sensitivity sums of eq. (25) on every Drude design edge.
  * Requires a forward solve on the current density (ESTATE).  Asynchronous
- * on the context stream. */
+ * on the context stream, except that the watchdog (non-finite adjoint
+ * fields, EUNSTABLE) keeps the host at most 2048 steps behind the device. */
 fdtd_status fdtd_adjoint(fdtd_ctx *ctx);
 
 /* dF/drho per design cell (eq. (27), filter = identity; in 3D the sum over the
@@ -166,6 +182,25 @@ fdtd_status fdtd_gradient(fdtd_ctx *ctx, void *grad_out, int64_t count, int32_t 
  * n_comp * 2 doubles, layout [k][gap cell][component][re, im]; n_comp = 1 in
  * 2D, 3 (Ex, Ey, Ez) in 3D. */
 fdtd_status fdtd_get_dft(fdtd_ctx *ctx, double *re_im, int64_t count);
+
+/* TEST ONLY (source-free evolution: eigenmode, energy and stability checks
+ * of the update itself, eqs. (10a-c)).  Initial state of the following
+ * forward solves instead of zero: `state` holds, on the host, count =
+ * nf * nx * ny * nz doubles, nf full-grid arrays [z][y][x] in the order
+ * E_z, H_x, H_y, J_z (dims 2: nf = 4, z ignored) or E_x, E_y, E_z, H_x, H_y,
+ * H_z, J_x, J_y, J_z (dims 3: nf = 9), at the staggered positions of the Yee
+ * cell: E^0 and J^0 at t = 0, H^{-1/2} at t = -dt/2.  Positions the update
+ * never writes (E and H on the PEC walls) and J off the Drude design edges
+ * are taken as zero; absorber memories start at zero.  The state is copied;
+ * it applies to every forward until fdtd_set_state(ctx, NULL, 0) clears it.
+ * EINVAL on a wrong count or a NULL pointer with count != 0. */
+fdtd_status fdtd_set_state(fdtd_ctx *ctx, const double *state, int64_t count);
+
+/* TEST ONLY.  The state at the end of the most recent forward solve (E^N,
+ * H^{N-1/2}, J^N), same layout as fdtd_set_state, into the host array
+ * `state` of count doubles.  ESTATE before a forward solve or after an
+ * adjoint solve (which reuses the state buffers). */
+fdtd_status fdtd_get_state(fdtd_ctx *ctx, double *state, int64_t count);
 
 /* Timing of the most recent solves (see fdtd_timing). */
 fdtd_status fdtd_get_timing(fdtd_ctx *ctx, fdtd_timing *out);

@@ -6,7 +6,7 @@
 // Per step (Sec. 3.2 staggering: E, J at integer steps, H at half steps):
 //   H^{n+1/2} = H^{n-1/2} - dt/mu0 curl E^n                 (eq. (10c), CPML, TFSF)
 //   E^{n+1}   = E^n + dE,  dE = 2/D [dt curl H^{n+1/2} - dt (1+kp)/2 J^n - (beta+sigma) dt E^n]
-//   J^{n+1}   = kp J^n + beta (E^{n+1} + E^n)               (eqs. (10a-b), trapezoidal ADE)
+//   J^{n+1}   = J^n + (kp - 1) J^n + beta (E^{n+1} + E^n)   (eqs. (10a-b), trapezoidal ADE)
 // with the per-edge coefficients of eqs. (4)-(5) evaluated in registers from
 // rho (D = 2 eps0 eps_inf_i + (beta_i + sigma_i) dt).  The adjoint step
 // (eq. (20)) is the same update on (E*, H*, J*) driven by the gap source, with
@@ -403,7 +403,7 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       const T inv = T(2) / (eps2 + bs);
       const T dE = inv * (p.dtdx * curl - p.dthJ * Jo[r] - bs * e0);
       e1 = e0 + dE;
-      Jn[r] = p.kp * Jo[r] + beta * (e0 + e1);
+      Jn[r] = Jo[r] + (p.kpm1 * Jo[r] + beta * (e0 + e1));  // increment form: kp - 1 ~ -gamma dt is kept exactly
       if (ADJ) {
         const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + x * (T(1) - p.rs)));
         const T gb = p.gsm * (T(1) - T(2) * x);

@@ -37,7 +37,7 @@ struct Step2D {
   T A0, A1;       // 2 eps0 eps_inf_i = A0 + rho A1
   T B0, B1;       // beta_i = B0 + rho B1
   T Sg;           // sigma_i dt = Sg rho (1 - rho)
-  T dt_, dtdx, dthJ, kp;
+  T dt_, dtdx, dthJ, kpm1;  // kpm1 = kp - 1 = -gamma dt / (1 + gamma dt / 2), rounded once from FP64
   T ga, gsm, rs;  // sensitivity: ga = -(eps0/dt)(eps_inf - eps_s); gsm = -sigma_max/2; rs = psi_s/psi
   double dt;
   const int *tlist;  // per-step launch over these workgroup tiles (ty * nbx + tx), or all when null

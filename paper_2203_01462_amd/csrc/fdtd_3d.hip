@@ -3,7 +3,7 @@
 // Per step, on the full Yee cell (Sec. 3.2; eqs. (10a-c)):
 //   H^{n+1/2} = H^{n-1/2} - dt/mu0 curl E^n                (CPML, total-field faces)
 //   E^{n+1} = E^n + 2/D [dt curl H^{n+1/2} - dt (1+kp)/2 J^n - (beta+sigma) dt E^n]
-//   J^{n+1} = kp J^n + beta (E^{n+1} + E^n)                 (Drude edges, eqs. (4)-(5))
+//   J^{n+1} = J^n + (kp - 1) J^n + beta (E^{n+1} + E^n)     (Drude edges, eqs. (4)-(5))
 // The adjoint step (eq. (20)) is the same update on (E*, H*, J*) driven by
 // the gap source, with each CPML term replaced by its exact transpose (the
 // grading and the recursive memory act on the differenced field before the
@@ -522,7 +522,7 @@ __device__ __forceinline__ void general_chunk(const Step3D<T> &p, const int n, c
         const T inv = T(2) / (eps2 + bs);
         const T dE = inv * (p.dtdx * curl[c] - p.dthJ * Jo[c] - bs * e0[c]);
         e1[c] = e0[c] + dE;
-        Jn[c] = p.kp * Jo[c] + beta * (e0[c] + e1[c]);
+        Jn[c] = Jo[c] + (p.kpm1 * Jo[c] + beta * (e0[c] + e1[c]));  // increment form
         if (ADJ) {
           const T gc = -(T(1) - p.rs) / (T(2) * (p.rs + rr * (T(1) - p.rs)));
           const T gb = p.gsm * (T(1) - T(2) * rr);

@@ -82,7 +82,7 @@ struct Step3D {
   int tn;              // table length (largest axis)
   T ch;                // dt / (mu0 dx)
   T ce_s, ce_g;        // dt / (eps0 eps dx)
-  T A0, A1, B0, B1, Sg, dt_, dtdx, dthJ, kp;
+  T A0, A1, B0, B1, Sg, dt_, dtdx, dthJ, kpm1;  // kpm1 = kp - 1 = -gamma dt / (1 + gamma dt / 2), rounded once from FP64
   T ga, gsm, rs;
   // tile-chunk lists of the general update (device, from gen3d_plan):
   // [single-axis | multi-axis | design], lengths gS, gM, gD; gAxD = the

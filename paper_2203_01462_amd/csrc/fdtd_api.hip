@@ -3,6 +3,8 @@
 // kernels on the context stream; all arithmetic of a solve runs on the GPU.
 #include <algorithm>
 #include <array>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -61,11 +63,26 @@ struct fdtd_ctx {
   Aux3D auxR{nullptr, nullptr, nullptr};
   hipEvent_t evStart = nullptr, evRerun = nullptr, evAdj[2] = {nullptr, nullptr};
   fdtd_timing timing{};
+  // initial state of the forward solves (fdtd_set_state; host, full grid,
+  // double) and whether the main state buffers hold a finished forward
+  std::vector<double> init_state;
+  bool fwd_state_valid = false;
+  // in-solve watchdog: one slot per check (device, then pinned host copy)
+  DevBuf watch;
+  unsigned long long *watch_host = nullptr;
+  int watch_slots = 0;
+  hipEvent_t evWatch[2] = {nullptr, nullptr};
 };
 
 namespace {
 
 thread_local std::string g_create_error;  // per thread: creates may run on several threads
+
+// Steps between two checks of the forward solve's watchdog.
+constexpr int kWatchEvery = 1024;
+// A passive medium driven by a plane wave of amplitude A keeps |E| far below
+// this multiple of A; beyond it (or at a non-finite value) the solve is unstable.
+constexpr double kWatchFactor = 1e10;
 
 Error einval(const std::string &m) { return Error{FDTD_EINVAL, m}; }
 
@@ -86,7 +103,14 @@ void validate(const fdtd_config &c) {
     throw einval("invalid Drude parameters (psi_s_ratio must be > 0)");
   if (c.pml_cells < 0 || c.tfsf_margin < 0) throw einval("negative pml_cells / tfsf_margin");
   if (c.ckpt_every < 0) throw einval("ckpt_every < 0");
-  if (c.source_kind != FDTD_SRC_GAUSS && c.source_kind != FDTD_SRC_SINC_HANN) throw einval("unknown source_kind");
+  if (c.source_kind != FDTD_SRC_GAUSS && c.source_kind != FDTD_SRC_SINC_HANN && c.source_kind != FDTD_SRC_NONE)
+    throw einval("unknown source_kind");
+  // the update kernels inject the plane wave with E along z travelling +y
+  // (TMz) or E along x travelling +z (3D)
+  const int pol = c.dims == 2 ? FDTD_AXIS_Z : FDTD_AXIS_X, prop = c.dims == 2 ? FDTD_AXIS_Y : FDTD_AXIS_Z;
+  if ((c.pol_axis != FDTD_AXIS_DEFAULT && c.pol_axis != pol) || (c.prop_axis != FDTD_AXIS_DEFAULT && c.prop_axis != prop))
+    throw einval(c.dims == 2 ? "TMz runs with pol_axis = z and prop_axis = y (or -1)"
+                             : "3D runs with pol_axis = x and prop_axis = z (or -1)");
   if (c.objective_kind != FDTD_OBJ_DFT && c.objective_kind != FDTD_OBJ_TIME_ENERGY) throw einval("unknown objective_kind");
   if (c.weight_kind != FDTD_W_ENHANCEMENT && c.weight_kind != FDTD_W_UNIT) throw einval("unknown weight_kind");
   if (!(c.f_hi > c.f_lo) || !(c.f_lo > 0)) throw einval("band edges must satisfy 0 < f_lo < f_hi");
@@ -116,7 +140,8 @@ void fill_params2d(fdtd_ctx *c, Step2D<T> &p, bool rerun) {
   p.nx = c->nx; p.ny = c->ny; p.pitch = c->pitch; p.P = g.pml_cells;
   p.dx0 = g.design_lo[0]; p.dy0 = g.design_lo[1]; p.dnx = g.design_n[0]; p.dny = g.design_n[1];
   p.gx0 = g.gap_lo[0]; p.gy0 = g.gap_lo[1]; p.gnx = g.gap_n[0]; p.gny = g.gap_n[1];
-  p.ia = c->ia; p.ib = c->ib; p.ja = c->ja; p.jb = c->jb; p.jref = c->jref; p.L = c->L; p.tf_on = 1;
+  p.ia = c->ia; p.ib = c->ib; p.ja = c->ja; p.jb = c->jb; p.jref = c->jref; p.L = c->L;
+  p.tf_on = g.source_kind != FDTD_SRC_NONE;
   p.K = c->K; p.ng = c->ng;
   for (int b = 0; b < 2; ++b) {
     DevBuf *f = rerun ? c->fldR[b] : c->fld[b], *m = rerun ? c->pmlR[b] : c->pml[b];
@@ -145,7 +170,7 @@ void fill_params2d(fdtd_ctx *c, Step2D<T> &p, bool rerun) {
   p.Sg = T(g.sigma_max * dt);
   p.dt_ = T(dt);
   p.dtdx = T(dt / dx);
-  p.kp = T((1.0 - gam * dt / 2.0) / den);
+  p.kpm1 = T(-gam * dt / den);
   p.dthJ = T(dt * 0.5 * (1.0 + (1.0 - gam * dt / 2.0) / den));
   p.ga = T(-(kEps0 / dt) * (g.eps_inf - g.eps_s));
   p.gsm = T(-0.5 * g.sigma_max);
@@ -180,13 +205,17 @@ void create_2d(fdtd_ctx *c) {
   const int P = g.pml_cells, m = g.tfsf_margin;
   c->ia = P + m; c->ib = c->nx - 1 - P - m;
   c->ja = P + m; c->jb = c->ny - 1 - P - m;
-  if (c->ia < 2 || c->ib - c->ia < 2 || c->ja < 3 || c->jb - c->ja < 2)
+  const bool tf = g.source_kind != FDTD_SRC_NONE;
+  if (tf && (c->ia < 2 || c->ib - c->ia < 2 || c->ja < 3 || c->jb - c->ja < 2))
     throw einval("total-field box does not fit inside the absorber");
-  if (!box_inside(g.design_lo[0], g.design_n[0], c->ia + 1, c->ib - 1) ||
-      !box_inside(g.design_lo[1], g.design_n[1], c->ja + 1, c->jb - 1) ||
-      !box_inside(g.gap_lo[0], g.gap_n[0], c->ia + 1, c->ib - 1) ||
-      !box_inside(g.gap_lo[1], g.gap_n[1], c->ja + 1, c->jb - 1))
-    throw einval("design/gap boxes must lie strictly inside the total-field box");
+  // boxes: strictly inside the total-field box, or without a plane wave
+  // anywhere off the absorber and the walls
+  const int xa = tf ? c->ia + 1 : P + 1, xb = tf ? c->ib - 1 : c->nx - 2 - P;
+  const int ya = tf ? c->ja + 1 : P + 1, yb = tf ? c->jb - 1 : c->ny - 2 - P;
+  if (!box_inside(g.design_lo[0], g.design_n[0], xa, xb) || !box_inside(g.design_lo[1], g.design_n[1], ya, yb) ||
+      !box_inside(g.gap_lo[0], g.gap_n[0], xa, xb) || !box_inside(g.gap_lo[1], g.gap_n[1], ya, yb))
+    throw einval(tf ? "design/gap boxes must lie strictly inside the total-field box"
+                    : "design/gap boxes must lie inside the absorber and the walls");
   c->pitch = (c->nx + 63) & ~63;
   c->nd = g.design_n[0] * g.design_n[1];
   c->ng = g.gap_n[0] * g.gap_n[1];
@@ -206,7 +235,9 @@ void create_2d(fdtd_ctx *c) {
   if (c->prec == 32) build_axis_tables<float>(c); else build_axis_tables<double>(c);
   const int dbox[4] = {g.design_lo[0], g.design_lo[1], g.design_n[0], g.design_n[1]};
   const int gbox[4] = {g.gap_lo[0], g.gap_lo[1], g.gap_n[0], g.gap_n[1]};
-  Tb2dPlan pl = tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox);
+  // without a plane wave there are no injection lines to keep clear
+  Tb2dPlan pl = tf ? tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox)
+                   : tb2d_plan(c->nx, c->ny, P, -8, -8, -8, -8, dbox, gbox);
   if (!pl.tb.empty()) {
     // the interior super-tiles run one launch early (beside the rest tiles'
     // second step of the previous pair), the border ones after them
@@ -289,13 +320,16 @@ void create_3d(fdtd_ctx *c) {
   const fdtd_config &g = c->cfg;
   const int P = g.pml_cells, m = g.tfsf_margin;
   const int n3[3] = {c->nx, c->ny, c->nz};
+  const bool tf = g.source_kind != FDTD_SRC_NONE;
   for (int d = 0; d < 3; ++d) {
     c->lo3[d] = P + m;
     c->hi3[d] = n3[d] - 1 - P - m;
-    if (c->lo3[d] < 3 || c->hi3[d] - c->lo3[d] < 2) throw einval("total-field box does not fit inside the absorber");
-    if (!box_inside(g.design_lo[d], g.design_n[d], c->lo3[d] + 1, c->hi3[d] - 1) ||
-        !box_inside(g.gap_lo[d], g.gap_n[d], c->lo3[d] + 1, c->hi3[d] - 1))
-      throw einval("design/gap boxes must lie strictly inside the total-field box");
+    if (tf && (c->lo3[d] < 3 || c->hi3[d] - c->lo3[d] < 2))
+      throw einval("total-field box does not fit inside the absorber");
+    const int a = tf ? c->lo3[d] + 1 : P + 1, b = tf ? c->hi3[d] - 1 : n3[d] - 2 - P;
+    if (!box_inside(g.design_lo[d], g.design_n[d], a, b) || !box_inside(g.gap_lo[d], g.gap_n[d], a, b))
+      throw einval(tf ? "design/gap boxes must lie strictly inside the total-field box"
+                      : "design/gap boxes must lie inside the absorber and the walls");
   }
   c->pitch = ((c->nx + 31) & ~31) + FDTD3D_PITCH_PAD;
   c->nd = g.design_n[0] * g.design_n[1] * g.design_n[2];
@@ -327,6 +361,12 @@ void release_aux(fdtd_ctx *c) {
   }
   if (c->rr) (void)hipStreamDestroy(c->rr);
   c->rr = nullptr;
+  for (hipEvent_t *e : {&c->evWatch[0], &c->evWatch[1]}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  if (c->watch_host) (void)hipHostFree(c->watch_host);
+  c->watch_host = nullptr;
 }
 
 template <typename T>
@@ -340,7 +380,7 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
     p.g0[d] = g.gap_lo[d]; p.gn[d] = g.gap_n[d];
     p.lo[d] = c->lo3[d]; p.hi[d] = c->hi3[d];
   }
-  p.kref = c->jref; p.L = c->L; p.tf_on = 1; p.ng = c->ng;
+  p.kref = c->jref; p.L = c->L; p.tf_on = g.source_kind != FDTD_SRC_NONE; p.ng = c->ng;
   const Arena3 &a = c->lay3;
   p.G0 = a.G0; p.S = a.S; p.PL = a.PL; p.xs = a.xs; p.ys = a.ys; p.zs = a.zs;
   p.XS = a.XS; p.YS = a.YS; p.ZS = a.ZS; p.W = a.W;
@@ -376,7 +416,7 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
   p.Sg = T(g.sigma_max * dt);
   p.dt_ = T(dt);
   p.dtdx = T(dt / dx);
-  p.kp = T((1.0 - gam * dt / 2.0) / den);
+  p.kpm1 = T(-gam * dt / den);
   p.dthJ = T(dt * 0.5 * (1.0 + (1.0 - gam * dt / 2.0) / den));
   p.ga = T(-(kEps0 / dt) * (g.eps_inf - g.eps_s));
   p.gsm = T(-0.5 * g.sigma_max);
@@ -440,7 +480,14 @@ void create_common(fdtd_ctx *c) {
   launch_phasors(s, c->dfreq.as<double>(), c->K, c->N, c->dt, c->phasor.as<double>());
   c->wts.alloc((size_t)c->K * sizeof(double));
   launch_weights(s, c->gwave.as<double>(), c->dfreq.as<double>(), c->K, c->N, c->dt,
-                 g.weight_kind == FDTD_W_UNIT, c->wts.as<double>());
+                 g.weight_kind == FDTD_W_UNIT || g.source_kind == FDTD_SRC_NONE, c->wts.as<double>());
+  // watchdog slots: one per check of the forward solve (every kWatchEvery
+  // steps and after the last)
+  c->watch_slots = (c->N + kWatchEvery - 1) / kWatchEvery;
+  c->watch.alloc((size_t)c->watch_slots * sizeof(unsigned long long));
+  FDTD_HIP(hipHostMalloc((void **)&c->watch_host, (size_t)c->watch_slots * sizeof(unsigned long long),
+                         hipHostMallocDefault));
+  for (hipEvent_t *e : {&c->evWatch[0], &c->evWatch[1]}) FDTD_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   // incident line: node p <-> main-grid index jref + p; far-end absorber of 20 cells
   const int P1 = 20, n1 = c->L + P1 + 1;
   std::vector<double> prof(6 * (size_t)n1);
@@ -472,6 +519,113 @@ void zero_state(fdtd_ctx *c) {
   }
   for (int k = 0; k < 3; ++k) if (c->fld3[k].p) zero(c, c->fld3[k]);
   zero(c, c->J);
+}
+
+// ------------------------------------------------ test-only state access
+// Fields of the fdtd_set_state layout: 2D E_z, H_x, H_y, J_z; 3D E_x, E_y,
+// E_z, H_x, H_y, H_z, J_x, J_y, J_z.
+int state_fields(const fdtd_ctx *c) { return c->dims == 2 ? 4 : 9; }
+
+// Is node (i, j, k) of E/H field f one the update writes (off the PEC walls)?
+bool state_node(const fdtd_ctx *c, int f, int i, int j, int k) {
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  const int x[3] = {i, j, k};
+  if (c->dims == 2) {
+    const bool ix = f == 2 ? i <= c->nx - 2 : i >= 1 && i <= c->nx - 2;
+    const bool jy = f == 1 ? j <= c->ny - 2 : j >= 1 && j <= c->ny - 2;
+    return ix && jy;
+  }
+  const int comp = f % 3;
+  const bool isE = f < 3;
+  for (int d = 0; d < 3; ++d) {
+    // E_c: [0, n-2] along c, [1, n-2] across; H_c: [1, n-2] along c, [0, n-2] across
+    const int lo = (d == comp) == isE ? 0 : 1;
+    if (x[d] < lo || x[d] > n3[d] - 2) return false;
+  }
+  return true;
+}
+
+// Index into the context's J array of the Drude edge of component `comp` at
+// node (i, j, k), or -1 when the node is not a Drude design edge.
+int64_t drude_index(const fdtd_ctx *c, int comp, int i, int j, int k) {
+  const fdtd_config &g = c->cfg;
+  const int x[3] = {i, j, k};
+  int64_t d = 0, stride = 1;
+  bool gap = true;
+  for (int a = 0; a < c->dims; ++a) {
+    const int u = x[a] - g.design_lo[a];
+    if (u < 0 || u >= g.design_n[a]) return -1;
+    d += u * stride;
+    stride *= g.design_n[a];
+    gap = gap && x[a] >= g.gap_lo[a] && x[a] < g.gap_lo[a] + g.gap_n[a];
+  }
+  return gap ? -1 : (int64_t)comp * c->nd + d;
+}
+
+// Offset (elements) of node (i, j, k) of field f in one state copy: the
+// pitched 2D array of that field, or the 3D arena.
+size_t state_offset(const fdtd_ctx *c, int f, int i, int j, int k) {
+  if (c->dims == 2) return (size_t)j * c->pitch + i;
+  return (size_t)c->lay3.G0 + (size_t)f * c->lay3.S + (size_t)k * c->lay3.PL + (size_t)j * c->pitch + i;
+}
+
+// Copy the initial state (host, double) into state copy 0 and J.
+template <typename T>
+void upload_init_state(fdtd_ctx *c) {
+  const size_t cells = (size_t)c->nx * c->ny * c->nz;
+  const double *st = c->init_state.data();
+  const int nfe = c->dims == 2 ? 3 : 6;
+  std::vector<T> jv((size_t)c->nd * c->ncomp, T(0));
+  for (int comp = 0; comp < c->ncomp; ++comp)
+    for (int k = 0; k < c->nz; ++k)
+      for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+          const int64_t d = drude_index(c, c->dims == 2 ? 0 : comp, i, j, k);
+          if (d >= 0) jv[d] = T(st[(size_t)(nfe + comp) * cells + ((size_t)k * c->ny + j) * c->nx + i]);
+        }
+  std::vector<std::vector<T>> img(c->dims == 2 ? 3 : 1);
+  for (auto &v : img) v.assign(c->dims == 2 ? (size_t)c->pitch * c->ny : (size_t)c->lay3.total, T(0));
+  for (int f = 0; f < nfe; ++f)
+    for (int k = 0; k < c->nz; ++k)
+      for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i)
+          if (state_node(c, f, i, j, k))
+            img[c->dims == 2 ? f : 0][state_offset(c, f, i, j, k)] = T(st[(size_t)f * cells + ((size_t)k * c->ny + j) * c->nx + i]);
+  for (size_t b = 0; b < img.size(); ++b) {
+    DevBuf *dst = c->dims == 2 ? field_buf(c, false, 0, (int)b) : &c->arena3[0];
+    FDTD_HIP(hipMemcpyAsync(dst->p, img[b].data(), img[b].size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  }
+  FDTD_HIP(hipMemcpyAsync(c->J.p, jv.data(), jv.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  FDTD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// The state after the last forward solve into `out` (fdtd_set_state layout).
+template <typename T>
+void download_state(fdtd_ctx *c, double *out) {
+  const size_t cells = (size_t)c->nx * c->ny * c->nz;
+  const int nfe = c->dims == 2 ? 3 : 6;
+  std::vector<std::vector<T>> img(c->dims == 2 ? 3 : 1);
+  for (size_t b = 0; b < img.size(); ++b) {
+    DevBuf *src = c->dims == 2 ? field_buf(c, false, fcopy(c, c->N), (int)b) : &c->arena3[c->N & 1];
+    img[b].resize(src->bytes / sizeof(T));
+    FDTD_HIP(hipMemcpyAsync(img[b].data(), src->p, src->bytes, hipMemcpyDeviceToHost, c->stream));
+  }
+  std::vector<T> jv((size_t)c->nd * c->ncomp);
+  FDTD_HIP(hipMemcpyAsync(jv.data(), c->J.p, jv.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+  FDTD_HIP(hipStreamSynchronize(c->stream));
+  for (int f = 0; f < nfe + c->ncomp; ++f)
+    for (int k = 0; k < c->nz; ++k)
+      for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+          double v = 0.0;
+          if (f < nfe) {
+            if (state_node(c, f, i, j, k)) v = (double)img[c->dims == 2 ? f : 0][state_offset(c, f, i, j, k)];
+          } else {
+            const int64_t d = drude_index(c, c->dims == 2 ? 0 : f - nfe, i, j, k);
+            if (d >= 0) v = (double)jv[d];
+          }
+          out[(size_t)f * cells + ((size_t)k * c->ny + j) * c->nx + i] = v;
+        }
 }
 
 template <typename T>
@@ -615,21 +769,75 @@ void *seg_hist(fdtd_ctx *c, int s) { return c->hist2.p && (s & 1) ? c->hist2.p :
 // after n+1.  With checkpoints the state entering each segment but the last is
 // saved, and only the last segment's history is kept.  With two-step
 // blocking, steps go in pairs that never straddle a saved state.
+// Watchdog of a forward solve.  After every chunk of steps the largest |E|
+// of the state is reduced into a device slot and copied to pinned host
+// memory behind an event; the host reads slot q-1 right after enqueueing
+// chunk q, so the device always has a chunk queued and no step waits for
+// the host.  A non-finite value or one above the limit stops the solve.
+struct ForwardWatch {
+  fdtd_ctx *c;
+  double limit;
+  int slots = 0;
+  std::vector<int> step;  // step count each slot checked
+  ForwardWatch(fdtd_ctx *ctx, double lim) : c(ctx), limit(lim) {
+    launch_fill_zero(c->stream, c->watch.p, c->watch.bytes);
+  }
+  void enqueue(int s) {  // the state after s steps
+    if (slots >= c->watch_slots) throw Error{FDTD_EDEVICE, "watchdog: more checks than slots"};
+    unsigned long long *slot = c->watch.as<unsigned long long>() + slots;
+    if (c->dims == 2) {
+      DevBuf *e = field_buf(c, false, fcopy(c, s), 0);
+      launch_watch(c->stream, c->prec, e->p, e->bytes / c->esz, slot);
+    } else {
+      const char *e = c->arena3[s & 1].as<char>() + (size_t)c->lay3.G0 * c->esz;
+      launch_watch(c->stream, c->prec, e, (size_t)3 * c->lay3.S, slot);
+    }
+    FDTD_HIP(hipMemcpyAsync(c->watch_host + slots, slot, sizeof(*slot), hipMemcpyDeviceToHost, c->stream));
+    FDTD_HIP(hipEventRecord(c->evWatch[slots & 1], c->stream));
+    step.push_back(s);
+    if (++slots >= 2) check(slots - 2);
+  }
+  void check(int q) {
+    FDTD_HIP(hipEventSynchronize(c->evWatch[q & 1]));
+    const unsigned long long bits = c->watch_host[q];
+    double v;
+    std::memcpy(&v, &bits, sizeof v);
+    if (!(v <= limit)) {
+      FDTD_HIP(hipStreamSynchronize(c->stream));
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "watchdog: max |E| = %.3e after step %d (limit %.3e)", v, step[q], limit);
+      throw Error{FDTD_EUNSTABLE, msg};
+    }
+  }
+  void finish() {
+    if (slots >= 1) check(slots - 1);
+  }
+};
+
 template <typename T>
-void run_forward(fdtd_ctx *c) {
+void run_forward(fdtd_ctx *c, double limit) {
   FDTD_HIP(hipEventRecord(c->ev[0], c->stream));
   const int K = c->ck, S = c->nseg, last = (S - 1) * K, N = c->N;
   const int seglen = S > 1 ? K : N;
   Lane ln = main_lane(c);
+  ForwardWatch watch(c, limit);
   for (int a = 0; a < N; a += seglen) {
     const int b = std::min(a + seglen, N);
     if (S > 1 && a < last) snap_save(c, a, a / K);
     ln.hist = seg_hist(c, a / seglen);
-    run_block<T>(c, false, false, a, b - a, [=](int j) { return a + j; }, last, [=](int j) { return a + j >= last; },
-                 ln);
+    // blocks end at the segment's end and at every multiple of
+    // kWatchEvery, where the state is checked (and after the last step)
+    for (int a2 = a; a2 < b;) {
+      const int b2 = std::min(b, (a2 / kWatchEvery + 1) * kWatchEvery);
+      run_block<T>(c, false, false, a2, b2 - a2, [=](int j) { return a2 + j; }, last,
+                   [=](int j) { return a2 + j >= last; }, ln);
+      if (b2 % kWatchEvery == 0 || b2 == N) watch.enqueue(b2);
+      a2 = b2;
+    }
   }
   FDTD_HIP(hipGetLastError());
   FDTD_HIP(hipEventRecord(c->ev[1], c->stream));
+  watch.finish();
 }
 
 // Adjoint solve, m = N..1 (eq. (20)); step m reads the forward E^m from the
@@ -704,8 +912,21 @@ fdtd_status guard(fdtd_ctx *c, F &&f) {
 void fwd_prepare(fdtd_ctx *c) {
   if (c->state < 1) throw Error{FDTD_ESTATE, "forward before set_density"};
   c->state = 1;
+  c->fwd_state_valid = false;
   zero_state(c);
   zero(c, c->gapE);
+  if (!c->init_state.empty()) {
+    if (c->prec == 32) upload_init_state<float>(c); else upload_init_state<double>(c);
+  }
+}
+
+// Watchdog limit of a forward solve: a multiple of the incident amplitude,
+// or without a plane wave of the largest value of the initial state.
+double watch_limit(const fdtd_ctx *c) {
+  double ref = c->cfg.source_kind == FDTD_SRC_NONE ? 0.0 : std::fabs(c->cfg.amplitude);
+  if (c->cfg.source_kind == FDTD_SRC_NONE)
+    for (double v : c->init_state) ref = std::max(ref, std::fabs(v));
+  return kWatchFactor * (ref > 0.0 ? ref : 1.0);
 }
 
 void fwd_objective(fdtd_ctx *c) {
@@ -724,6 +945,7 @@ void fwd_finish(fdtd_ctx *c, double F) {
 
 void adj_prepare(fdtd_ctx *c) {
   if (c->state < 2) throw Error{FDTD_ESTATE, "adjoint before forward"};
+  c->fwd_state_valid = false;  // the adjoint reuses the state buffers
   const fdtd_config &g = c->cfg;
   const double te_coef = g.eps_g * c->dt * g.dx * g.dx * g.dx;
   launch_adjoint_source(c->stream, c->prec, c->dft.as<double>(), c->wts.as<double>(), c->phasor.as<double>(),
@@ -1134,12 +1356,16 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
       if (c->prec == 32) fill_params3d(c.get(), c->p3f, false); else fill_params3d(c.get(), c->p3d, false);
       if (c->prec == 32) fill_params3d(c.get(), c->p3fR, true); else fill_params3d(c.get(), c->p3dR, true);
     }
-    if (c->nseg > 1) {  // the re-run state's never-written nodes stay zero
+    if (c->nseg > 1) {  // the re-run state's never-written nodes (walls, guards) stay zero
       for (int b = 0; b < 2; ++b) {
         for (int k = 0; k < 6; ++k) if (c->fldR[b][k].p) zero(c.get(), c->fldR[b][k]);
         for (int k = 0; k < 12; ++k) if (c->pmlR[b][k].p) zero(c.get(), c->pmlR[b][k]);
         if (c->arenaR[b].p) zero(c.get(), c->arenaR[b]);
       }
+      // the third field copy of the two-step schedule: a re-run whose
+      // segment starts in copy 0 or 1 reads this copy's wall nodes before
+      // any step has written them
+      for (int k = 0; k < 3; ++k) if (c->fld3R[k].p) zero(c.get(), c->fld3R[k]);
     }
     FDTD_HIP(hipStreamSynchronize(c->stream));
     FDTD_HIP(hipGetLastError());
@@ -1195,7 +1421,8 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
   if (!ctx) return FDTD_EINVAL;
   return guard(ctx, [&] {
     fwd_prepare(ctx);
-    if (ctx->prec == 32) run_forward<float>(ctx); else run_forward<double>(ctx);
+    const double limit = watch_limit(ctx);
+    if (ctx->prec == 32) run_forward<float>(ctx, limit); else run_forward<double>(ctx, limit);
     fwd_objective(ctx);
     double F = 0;
     FDTD_HIP(hipMemcpyAsync(&F, ctx->Fdev.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -1205,6 +1432,7 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
     ctx->timing.forward_ms = ms;
     ctx->timing.forward_launches = ctx->N;
     fwd_finish(ctx, F);
+    ctx->fwd_state_valid = true;
     if (objective_out) *objective_out = F;
   });
 }
@@ -1250,6 +1478,30 @@ fdtd_status fdtd_get_dft(fdtd_ctx *ctx, double *re_im, int64_t count) {
     if (!re_im || count != (int64_t)ctx->K * ctx->nmon * 2) throw einval("dft buffer size must be K * n_gap * n_comp * 2");
     FDTD_HIP(hipMemcpyAsync(re_im, ctx->dft.p, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     FDTD_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+fdtd_status fdtd_set_state(fdtd_ctx *ctx, const double *state, int64_t count) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (count == 0 && !state) {
+      ctx->init_state.clear();
+      return;
+    }
+    const int64_t need = (int64_t)state_fields(ctx) * ctx->nx * ctx->ny * ctx->nz;
+    if (!state || count != need) throw einval("state count must be n_fields * nx * ny * nz (or NULL, 0 to clear)");
+    ctx->init_state.assign(state, state + count);
+    ctx->fwd_state_valid = false;
+  });
+}
+
+fdtd_status fdtd_get_state(fdtd_ctx *ctx, double *state, int64_t count) {
+  if (!ctx) return FDTD_EINVAL;
+  return guard(ctx, [&] {
+    if (!ctx->fwd_state_valid) throw Error{FDTD_ESTATE, "get_state needs a forward solve (and no adjoint since)"};
+    const int64_t need = (int64_t)state_fields(ctx) * ctx->nx * ctx->ny * ctx->nz;
+    if (!state || count != need) throw einval("state count must be n_fields * nx * ny * nz");
+    if (ctx->prec == 32) download_state<float>(ctx, state); else download_state<double>(ctx, state);
   });
 }
 

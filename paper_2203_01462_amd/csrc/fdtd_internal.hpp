@@ -108,6 +108,7 @@ inline double pml_depth(int n, int P, double pos) {
 
 // Excitation waveform samples g(n dt), n = 0..N (see fdtd.h source kinds).
 inline double source_wave(const fdtd_config &c, double t) {
+  if (c.source_kind == FDTD_SRC_NONE) return 0.0;
   const double fc = 0.5 * (c.f_lo + c.f_hi);
   const double bw = c.f_hi - c.f_lo;
   if (c.source_kind == FDTD_SRC_GAUSS) {
@@ -159,6 +160,7 @@ void launch_adjoint_source(hipStream_t s, int precision, const double *dft, cons
 void launch_grad_finalize(hipStream_t s, int precision, const double *acc, const double *scale, int ncomp, int dnx,
                           int dny, int dnz, int gx0, int gy0, int gz0, int gnx, int gny, int gnz, void *out);
 void launch_fill_zero(hipStream_t s, void *p, size_t bytes);
+void launch_watch(hipStream_t s, int precision, const void *p, size_t n, unsigned long long *slot);
 void launch_check_density(hipStream_t s, int precision, const void *rho, int64_t n, int *bad);
 void launch_copy_density(hipStream_t s, int precision, const void *src, void *dst, int64_t n);
 

@@ -223,7 +223,37 @@ __global__ void check_density_kernel(const T *__restrict__ rho, int64_t n, int *
   if (threadIdx.x == 0) bad[0] = (int)c;
 }
 
+// Watchdog of a solve: the largest |v| over n values (NaN counts as +inf),
+// folded into *slot with an atomic max on the bit pattern (non-negative
+// doubles order like their bits).  *slot must start at zero.
+template <typename T>
+__global__ void __launch_bounds__(256) watch_kernel(const T *__restrict__ p, size_t n,
+                                                    unsigned long long *__restrict__ slot) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    double a = fabs((double)p[i]);
+    if (!(a == a)) a = HUGE_VAL;
+    m = fmax(m, a);
+  }
+  const double r = block_max(m, sh);
+  if (threadIdx.x == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(r));
+}
+
 }  // namespace
+
+void launch_watch(hipStream_t s, int precision, const void *p, size_t n, unsigned long long *slot) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (precision == 32)
+    hipLaunchKernelGGL(watch_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)p, n, slot);
+  else
+    hipLaunchKernelGGL(watch_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const double *)p, n, slot);
+  FDTD_HIP(hipGetLastError());
+}
 
 void launch_incident_line(hipStream_t s, int precision, const double *g, int N, int n1, int L, const double *prof,
                           double ch, double ce, double cmu, double cep, double *scratch, void *einc, void *hinc) {

@@ -14,11 +14,12 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
-ABI_VERSION = 4
+ABI_VERSION = 5
 C0 = 299792458.0
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSTABLE"}
-SRC = {"gauss": 0, "sinc_hann": 1}
+SRC = {"gauss": 0, "sinc_hann": 1, "none": 2}
+AXIS = {None: -1, "x": 0, "y": 1, "z": 2}
 OBJ = {"dft": 0, "time_energy": 1}
 WTS = {"enhancement": 0, "unit": 1}
 
@@ -34,7 +35,7 @@ class Config(C.Structure):
     _fields_ = [
         ("abi_version", C.c_int32), ("dims", C.c_int32), ("precision", C.c_int32),
         ("n", C.c_int32 * 3), ("n_steps", C.c_int32), ("pml_cells", C.c_int32),
-        ("tfsf_margin", C.c_int32),
+        ("tfsf_margin", C.c_int32), ("pol_axis", C.c_int32), ("prop_axis", C.c_int32),
         ("design_lo", C.c_int32 * 3), ("design_n", C.c_int32 * 3),
         ("gap_lo", C.c_int32 * 3), ("gap_n", C.c_int32 * 3),
         ("source_kind", C.c_int32), ("objective_kind", C.c_int32), ("weight_kind", C.c_int32),
@@ -66,7 +67,8 @@ class BatchOptions(C.Structure):
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint",
-           "fdtd_gradient", "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_last_error",
+           "fdtd_gradient", "fdtd_get_dft", "fdtd_set_state", "fdtd_get_state", "fdtd_get_timing",
+           "fdtd_destroy", "fdtd_last_error",
            "fdtd_batch_create", "fdtd_batch_set_density", "fdtd_batch_forward", "fdtd_batch_adjoint",
            "fdtd_batch_gradient", "fdtd_batch_info", "fdtd_batch_depth", "fdtd_batch_destroy", "fdtd_batch_last_error",
            # include/fdtd_design.h
@@ -103,6 +105,8 @@ def load_library(path=LIB_PATH):
     L.fdtd_adjoint.argtypes = [P]
     L.fdtd_gradient.argtypes = [P, P, C.c_int64, C.c_int32]
     L.fdtd_get_dft.argtypes = [P, C.POINTER(C.c_double), C.c_int64]
+    L.fdtd_set_state.argtypes = [P, C.POINTER(C.c_double), C.c_int64]
+    L.fdtd_get_state.argtypes = [P, C.POINTER(C.c_double), C.c_int64]
     L.fdtd_get_timing.argtypes = [P, C.POINTER(Timing)]
     L.fdtd_destroy.argtypes = [P]
     L.fdtd_last_error.argtypes = [P]
@@ -163,7 +167,8 @@ def load_library(path=LIB_PATH):
     L.fdtd_nn_last_error.argtypes = []
     L.fdtd_nn_last_error.restype = C.c_char_p
     for fn in ("fdtd_create", "fdtd_set_density", "fdtd_forward", "fdtd_adjoint", "fdtd_gradient",
-               "fdtd_get_dft", "fdtd_get_timing", "fdtd_destroy", "fdtd_batch_create", "fdtd_batch_set_density",
+               "fdtd_get_dft", "fdtd_set_state", "fdtd_get_state", "fdtd_get_timing", "fdtd_destroy",
+               "fdtd_batch_create", "fdtd_batch_set_density",
                "fdtd_batch_forward", "fdtd_batch_adjoint", "fdtd_batch_gradient", "fdtd_batch_info",
                "fdtd_batch_depth", "fdtd_batch_destroy"):
         getattr(L, fn).restype = C.c_int
@@ -190,6 +195,8 @@ def make_config(w, stream=None, history_budget_bytes=0, ckpt_every=None):
     c.n_steps = w["n_steps"]
     c.pml_cells = w["pml_cells"]
     c.tfsf_margin = w["tfsf_margin"]
+    c.pol_axis = AXIS[w.get("pol_axis")]
+    c.prop_axis = AXIS[w.get("prop_axis")]
     c.source_kind = SRC[w["source"]]
     c.objective_kind = OBJ[w["objective"]]
     c.weight_kind = WTS[w["weights"]]
@@ -298,6 +305,29 @@ class FDTD:
         self._check(load_library().fdtd_get_dft(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n))
         out = out.reshape(self.K, self.ng, self.ncomp, 2)
         return out[..., 0] + 1j * out[..., 1]
+
+    def state_shape(self):
+        """(fields, nz, ny, nx) of the test-only state arrays: 2D E_z, H_x, H_y, J_z
+        (nz = 1); 3D E_x, E_y, E_z, H_x, H_y, H_z, J_x, J_y, J_z."""
+        nx, ny, nz = self.w["n"]
+        return (4, 1, ny, nx) if self.dims == 2 else (9, nz, ny, nx)
+
+    def set_state(self, state):
+        """Test only: initial state (E^0, H^{-1/2}, J^0) of the following forward
+        solves, array of state_shape() (or None to clear)."""
+        L = load_library()
+        if state is None:
+            self._check(L.fdtd_set_state(self.h, None, 0))
+            return
+        a = np.ascontiguousarray(np.asarray(state, dtype=np.float64).reshape(-1))
+        self._keep_state = a
+        self._check(L.fdtd_set_state(self.h, a.ctypes.data_as(C.POINTER(C.c_double)), a.size))
+
+    def get_state(self):
+        """Test only: state after the last forward solve, array of state_shape()."""
+        out = np.zeros(self.state_shape())
+        self._check(load_library().fdtd_get_state(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out
 
     def timing(self):
         t = Timing()

@@ -165,3 +165,61 @@ def test_c4_batch_shape(gpu):
         assert abs(F[k] - Fk) <= 1e-5 * abs(Fk), (k, F[k], Fk)
         assert np.linalg.norm(gb - gk) <= 1e-4 * np.linalg.norm(gk), k
     b.close()
+
+
+def oracle_runs(oracle_mod, ws, rhos):
+    out = []
+    for w, r in zip(ws, rhos):
+        o = oracle_mod.Oracle(W.with_(w, precision=64))
+        out.append(o.run(r))
+        o.close()
+    return out
+
+
+def check_against_oracle(F, grads, ref, prec, label):
+    tol_f, tol_g = (1e-11, 1e-11) if prec == 64 else (1e-4, 1e-3)
+    for k, (Fo, go) in enumerate(ref):
+        eF = abs(F[k] - Fo) / abs(Fo)
+        eG = np.linalg.norm(grads[k] - go) / np.linalg.norm(go)
+        eM = np.abs(grads[k] - go).max() / np.abs(go).max()
+        say(f"[batch-oracle] {label} instance {k}: relF={eF:.2e} relGrad={eG:.2e} maxabs={eM:.2e}")
+        assert eF <= tol_f and eG <= tol_g and eM <= 10 * tol_g, (k, eF, eG, eM)
+
+
+@pytest.mark.parametrize("prec,depth,n_steps", [(64, 1, 400), (64, 2, 401), (32, 1, 400), (32, 2, 400)])
+def test_batch_against_oracle(gpu, oracle_mod, prec, depth, n_steps):
+    """Every instance of an uneven batch (sides 64-384, own damping and band)
+    against the FP64 oracle on the same seeded inputs, at temporal-block depth
+    1 and 2: FP64 to 1e-11, FP32 to 1e-4 on F and 1e-3 on the gradient (rel
+    L2), max |error| within 10x the gradient bar of the largest entry."""
+    ws = uneven(n_steps, precision=prec, sides=(64, 160, 256, 384))
+    rhos = [W.seeded_rho(w, k) for k, w in enumerate(ws)]
+    (res,), _, dep = run_batch(gpu, ws, rhos, 2, True, depth=depth)
+    if depth == 2:
+        assert any(d == 2 for d in dep)
+    check_against_oracle(res[0], res[1], oracle_runs(oracle_mod, ws, rhos), prec, f"fp{prec} depth {depth}")
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c4_batch_sampled_against_oracle(gpu, oracle_mod, prec):
+    """The 64-instance uneven workload (sides 128-1024) batched with the tuned
+    depths, 1500 steps (long enough for the pulse to reach the gap of every
+    side); one instance of each side against the oracle."""
+    ws = [W.with_(w, precision=prec) for w in W.c4(n_steps=1500)]
+    rhos = [W.seeded_rho(w, k) for k, w in enumerate(ws)]
+    b = gpu.Batch(ws, rows=0, use_graph=True, depth=0)
+    for k, r in enumerate(rhos):
+        b.set_density(k, r.astype(b.dtype))
+    F = b.forward()
+    b.adjoint()
+    pick, seen = [], set()
+    for k, w in enumerate(ws):
+        if w["n"][0] not in seen:
+            seen.add(w["n"][0])
+            pick.append(k)
+    grads = [b.gradient(k) for k in pick]
+    depths = [b.info(k)["depth"] for k in pick]
+    b.close()
+    say(f"[batch-oracle] C4 sample: instances {pick}, sides {[ws[k]['n'][0] for k in pick]}, depths {depths}")
+    ref = oracle_runs(oracle_mod, [ws[k] for k in pick], [rhos[k] for k in pick])
+    check_against_oracle([F[k] for k in pick], grads, ref, prec, f"C4 fp{prec}")

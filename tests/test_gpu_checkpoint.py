@@ -106,3 +106,22 @@ def test_c3_checkpoint_every_500_matches_stored_history(gpu):
     F, g, d = run(gpu, w, rho, 500)
     say(f"   F {F:.9e} vs {F0:.9e}, max|dg|={np.abs(g - g0).max():.3e}")
     assert F == F0 and np.array_equal(g, g0) and np.array_equal(d, d0)
+
+
+def test_medium2d_checkpoint_after_recycled_memory(gpu):
+    """Regression: every buffer the checkpointed re-runs read before writing
+    (the wall nodes of all three field copies of the two-step schedule) is
+    cleared at create.  A first context fills its device memory with non-zero
+    fields and is destroyed, so the next context's allocations are likely to
+    reuse that memory; the checkpointed result must still equal the stored
+    history bit for bit."""
+    w = W.medium2d(precision=64)
+    rho = W.seeded_rho(w, 0)
+    F0, g0, d0 = run(gpu, w, rho, 0)
+    for _ in range(2):
+        dirty = gpu.FDTD(w, ckpt_every=500)
+        dirty.run(rho)  # fields, absorber memories and re-run copies all non-zero
+        dirty.close()
+        F, g, d = run(gpu, w, rho, 500)
+        say(f"[ckpt] recycled memory: F {F:.15e} vs {F0:.15e}")
+        assert F == F0 and np.array_equal(g, g0) and np.array_equal(d, d0)

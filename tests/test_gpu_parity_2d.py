@@ -120,12 +120,13 @@ def test_c2_full_directional_derivative(gpu):
     assert abs((Fp - Fm) - pred) <= 1e-3 * abs(Fp - Fm)
 
 
+@pytest.mark.xfail(reason="FP32 storage limit at this gap depth (see test_gpu_fullsize.C2_FP32_LIMIT)",
+                   strict=False)
 def test_c2_full_fp32_against_fp64(gpu):
     """The FP32 build at the full 2048^2 x 20000-step size against the FP64
-    build.  With the seeded grey density the gap field (F ~ 3e-11) is orders of
-    magnitude below the fields around it, and FP32 rounding there shows in the
-    objective at ~3e-4 and in the gradient at ~2.5% relative L2 (FP32 parity on
-    the 512^2 grids is ~1e-6 / ~2e-4).  Bars: 2e-3 and 5e-2."""
+    build, at the spec bars 1e-4 (F) and 1e-3 (gradient).  Measured:
+    1.5e-4 and 2.5e-2 -- the gap field is below FP32's resolution of the
+    background field; FP32 parity on the 512^2 grids is ~1e-6 / ~2e-4."""
     w = W.c2()
     rho = W.seeded_rho(w, 0)
     say("[parity] C2 full 2048^2 x 20000: fp32 vs fp64")
@@ -138,7 +139,7 @@ def test_c2_full_fp32_against_fp64(gpu):
     eF = abs(F32 - F64) / F64
     eG = rel_l2(g32, g64)
     say(f"   F32={F32:.9e} F64={F64:.9e} relF={eF:.2e} relGrad={eG:.2e}")
-    assert eF <= 2e-3 and eG <= 5e-2
+    assert eF <= 1e-4 and eG <= 1e-3
 
 def test_call_order_and_validation(gpu):
     w = W.tiny2d()
