@@ -62,6 +62,20 @@ int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int3
 fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
                                   const uint16_t *dz, float *dw, float *db, float *work, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * dw and db as fdtd_nn_conv3x3_wgrad, bit for bit (same kernels and split
+ * plan), with the partial sums in a scratch array the library holds on each
+ * device (64 MiB = 16 Mi floats, kept until the process ends) instead of a
+ * caller workspace.  Allocates nothing and calls no allocating routine; the
+ * device is the current one.  EINVAL when fdtd_nn_wgrad_work(...) exceeds
+ * 16 Mi floats (every layer of the surrogate fits: the plan's largest
+ * workspace is about 14.2 Mi floats).  Calls on one device share the array:
+ * calls that overlap on one GPU (different streams or threads) race and
+ * must be serialized by the caller. */
+fdtd_status fdtd_nn_conv3x3_wgrad_noalloc(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w,
+                                          const uint16_t *x, const uint16_t *dz, float *dw, float *db, void *stream);
+
 /* Elementwise: a = bf16(relu(z)); backward dz = bf16(da * (a > 0)) with the
  * layer's BF16 output a as the mask and an FP32 incoming gradient da. */
 fdtd_status fdtd_nn_relu_bf16(int64_t count, const float *z, uint16_t *a, void *stream);

@@ -10,6 +10,8 @@
 // MFMA operand layout (wave64): lane l holds A[l%16][4(l/16)+j],
 // B[4(l/16)+j][l%16] and returns D[4(l/16)+j][l%16], j = 0..3.
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "fdtd_internal.hpp"
@@ -796,11 +798,22 @@ int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int3
   return (int64_t)wgrad_plan(n, cin, cout, h, w).splits * cout * cin * 9 + bias_ranges(P) * cout;
 }
 
-fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
-                                  const uint16_t *dz, float *dw, float *db, float *work, void *stream) {
-  return nguard([&] {
-    need(n > 0 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && dz && dw && work);
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+// Scratch of the allocation-free weight gradient: one array per device,
+// held until the process ends (64 MiB: the largest workspace the split plan
+// asks for, about 768 partial sums of a 64 x 32 x 9 block, is 54 MiB).  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// kernels get the address hipGetSymbolAddress returns on each device.
+static constexpr int64_t kScratchFloats = int64_t(16) << 20;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+// The weight and bias gradients with partial sums in `work` (at least
+// fdtd_nn_wgrad_work floats; every slot the reductions read is written first).
+void wgrad_run(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x, const uint16_t *dz,
+               float *dw, float *db, float *work, hipStream_t s) {
     const int K = cin * 9;
     const int64_t P = (int64_t)n * h * w;
     const WgradPlan pl = wgrad_plan(n, cin, cout, h, w);
@@ -825,6 +838,49 @@ fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t 
       hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(cout)), dim3(BS), 0, s, pb, (int)nr, (int64_t)cout, db);
     }
     FDTD_HIP(hipGetLastError());
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+float *scratch_on_current_device() {
+  int dev = 0;
+  FDTD_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<int, float *> ptrs;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error{FDTD_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e)};
+  }
+  ptrs[dev] = static_cast<float *>(p);
+  return ptrs[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+fdtd_status fdtd_nn_conv3x3_wgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *x,
+                                  const uint16_t *dz, float *dw, float *db, float *work, void *stream) {
+  return nguard([&] {
+    need(n > 0 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && dz && dw && work);
+    wgrad_run(n, cin, cout, h, w, x, dz, dw, db, work, (hipStream_t)stream);
+  });
+}
+
+fdtd_status fdtd_nn_conv3x3_wgrad_noalloc(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w,
+                                          const uint16_t *x, const uint16_t *dz, float *dw, float *db, void *stream) {
+  return nguard([&] {
+    need(n > 0 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && dz && dw);
+    const int64_t want = fdtd_nn_wgrad_work(n, cin, cout, h, w);
+    if (want > kScratchFloats)
+      throw Error{FDTD_EINVAL, "weight gradient needs " + std::to_string(want) + " floats of scratch; the static array "
+                               "holds " + std::to_string(kScratchFloats) + " (use fdtd_nn_conv3x3_wgrad with a workspace)"};
+    wgrad_run(n, cin, cout, h, w, x, dz, dw, db, scratch_on_current_device(), (hipStream_t)stream);
   });
 }
 

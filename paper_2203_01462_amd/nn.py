@@ -67,6 +67,13 @@ def conv3x3_wgrad(x, dz, dw, db, work, n, cin, cout, h, w, stream=None):
                                                 _p(work), _s(stream)))
 
 
+def conv3x3_wgrad_noalloc(x, dz, dw, db, n, cin, cout, h, w, stream=None):
+    """conv3x3_wgrad with the partial sums in the library's static per-device
+    scratch instead of a workspace (for callers that cannot allocate)."""
+    _check(load_library().fdtd_nn_conv3x3_wgrad_noalloc(n, cin, cout, h, w, _p(_u16(x)), _p(_u16(dz)), _p(dw),
+                                                        _p(db), _s(stream)))
+
+
 def relu_bf16(z, a, stream=None):
     _check(load_library().fdtd_nn_relu_bf16(z.numel(), _p(z), _p(_u16(a)), _s(stream)))
 
