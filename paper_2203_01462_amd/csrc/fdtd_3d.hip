@@ -655,12 +655,46 @@ __host__ __device__ inline void plain_grid(const int pb[6], int &nbx, int &nby, 
   nbz = (nbz + 7) / 8 * 8;
 }
 
+// Does node (i, j, k) belong to a two-step super-chunk?
+template <typename T>
+__device__ __forceinline__ bool in_super(const Step3D<T> &p, int i, int j, int k) {
+  const int u = i - p.so[0], v = j - p.so[1], w = k - p.so[2];
+  if (u < 0 || v < 0 || w < 0) return false;
+  const int cx = u / SCX, cy = v / SCY, cz = w / SCZ;
+  if (cx >= p.sn[0] || cy >= p.sn[1] || cz >= p.sn[2]) return false;
+  return p.sflag[(cz * p.sn[1] + cy) * p.sn[0] + cx] != 0;
+}
+
+// Does the box [x0, x1) x [y0, y1) x [z0, z1) lie inside two-step
+// super-chunks only?  (At most two chunks per axis for boxes no larger
+// than a chunk.)
+template <typename T>
+__device__ __forceinline__ bool all_super(const Step3D<T> &p, int x0, int x1, int y0, int y1, int z0, int z1) {
+  const int lo[3] = {x0, y0, z0}, hi[3] = {x1, y1, z1}, sc[3] = {SCX, SCY, SCZ};
+  int c0[3], c1[3];
+  for (int a = 0; a < 3; ++a) {
+    if (lo[a] < p.so[a] || hi[a] > p.so[a] + p.sn[a] * sc[a]) return false;
+    c0[a] = (lo[a] - p.so[a]) / sc[a];
+    c1[a] = (hi[a] - 1 - p.so[a]) / sc[a];
+  }
+  for (int cz = c0[2]; cz <= c1[2]; ++cz)
+    for (int cy = c0[1]; cy <= c1[1]; ++cy)
+      for (int cx = c0[0]; cx <= c1[0]; ++cx)
+        if (!p.sflag[(cz * p.sn[1] + cy) * p.sn[0] + cx]) return false;
+  return true;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
   const int nx = p.n[0], ny = p.n[1];
   int nbx, nby, nbz, bx, by, bz;
   plain_grid(p.pb, nbx, nby, nbz);
   block_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
+  if (p.skip_super) {
+    // a tile held wholly by super-chunks has nothing to do (uniform exit)
+    const int x0 = p.pb[0] + bx * PTX, y0 = p.pb[1] + by * PTY, z0 = p.pb[2] + bz * PKC;
+    if (all_super(p, x0, min(x0 + PTX, nx), y0, min(y0 + PTY, ny), z0, min(z0 + PKC, p.pb[2] + p.pb[5]))) return;
+  }
   const int i = p.pb[0] + bx * PTX + (threadIdx.x % PTX), j = p.pb[1] + by * PTY + (threadIdx.x / PTX);
   if (i >= nx || j >= ny) return;  // no barriers in this kernel
   const Tile tl = tile_xy(p, i - i % TX, j - j % TY);
@@ -683,7 +717,10 @@ __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
   T hxp = T(0), hyp = T(0), exc = T(0), exl = T(0), eyc = T(0), eys = T(0);
   bool have = false;
   for (int k = kb; k < ke; ++k) {
-    if (!plane_plain(p, tl, k)) {
+    // general planes belong to the general launches, super-chunk nodes to the
+    // two-step pass; a plane that follows a super node recomputes its new H
+    // (plane_plain holds there) from the read copy
+    if (!plane_plain(p, tl, k) || (p.skip_super && in_super(p, i, j, k))) {
       have = false;
       continue;
     }
@@ -730,6 +767,187 @@ __global__ void __launch_bounds__(PNT) step3d_plain(const Step3D<T> p) {
     exl = exl1;
     eyc = eyc1;
     eys = eys1;
+  }
+}
+
+// ---------------------------------------------------------------- two-step
+// Two time steps of the plain background per pass over a super-chunk
+// (60 x 16 x 8 nodes): the update of step3d_plain applied twice, to the last
+// bit.  A wavefront covers 64 consecutive columns c = a - 2 + lane (outputs
+// for lanes 2..61; neighbours along x come from the adjacent lane by DPP wave
+// shifts) and four output rows, holding the two rows below and above them in
+// registers; it marches through planes kb-2 .. ke, carrying E^n, H^{n+1/2},
+// E^{n+1} and the x, y components of H^{n+3/2} of the planes below, with the
+// next plane's loads issued one iteration ahead.  Validity shrinks by one
+// column per half step (H^{n+1/2}: lanes 0..62, E^{n+1}: 1..62, H^{n+3/2}:
+// 1..61, E^{n+2}: 2..61), by one row per half step in y and one plane in z.
+// Border nodes (faces flagged by the planner) also store E^{n+1}, H^{n+1/2}
+// into the intermediate copy, which the per-step launches of the second step
+// read.  No LDS and no barriers.
+constexpr int SR = 4, SW = SCY / SR;  // rows per wavefront, wavefronts per workgroup
+
+// v of lane l-1 (wave_shr:1) and of lane l+1 (wave_shl:1); the lane without
+// a source gets 0, which only feeds values outside the valid lanes.
+__device__ __forceinline__ float lane_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+__global__ void __launch_bounds__(64 * SW) step3d_super(const Step3D<float> p, const float *__restrict__ rd,
+                                                        float *__restrict__ mid, float *__restrict__ out,
+                                                        const int *__restrict__ list) {
+  const int code = ((cptr<int>)list)[blockIdx.x];
+  if (code < 0) return;
+  const int faces = code & 63, cidx = code >> 6;
+  const int cx = cidx % p.sn[0], cy = (cidx / p.sn[0]) % p.sn[1], cz = cidx / (p.sn[0] * p.sn[1]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int a = p.so[0] + cx * SCX, c = a - 2 + lane;
+  const int b = p.so[1] + cy * SCY, y0 = b + wv * SR;
+  const int kb = p.so[2] + cz * SCZ, ke = kb + SCZ;
+  const uint32_t pitch = p.pitch, PL = p.PL, S = p.S;
+  const float *__restrict__ Ex = rd + p.G0;
+  const float *__restrict__ Ey = Ex + S;
+  const float *__restrict__ Ez = Ex + 2 * (size_t)S;
+  const float *__restrict__ Hx = Ex + 3 * (size_t)S;
+  const float *__restrict__ Hy = Ex + 4 * (size_t)S;
+  const float *__restrict__ Hz = Ex + 5 * (size_t)S;
+  float *__restrict__ O = out + p.G0;
+  float *__restrict__ M = mid + p.G0;
+  const float ch = p.ch, ce = p.ce_s;
+  auto at = [&](int t, int k) { return (uint32_t)k * PL + (uint32_t)(y0 - 2 + t) * pitch + (uint32_t)c; };
+  const bool own = lane >= 2 && lane < 2 + SCX;
+  const bool bxf = (lane == 2 && (faces & 1)) || (lane == 1 + SCX && (faces & 2));
+  constexpr int NE = SR + 4, NH = SR + 3;
+  // E^n(m) rows 0..NE-1; H^{n+1/2}(m-1) rows 0..NH-1; E^{n+1}(m-1) rows 1..NH-1; H^{n+3/2}(m-2) x, y rows 2..SR+1
+  float ex0[NE], ey0[NE], ez0[NE], h1x[NH], h1y[NH], h1z[NH], e1x[NH], e1y[NH], e1z[NH], h2x[SR + 2], h2y[SR + 2];
+  float exn[NE], eyn[NE], ezn[NE], hxo[NH], hyo[NH], hzo[NH];
+#pragma unroll
+  for (int t = 0; t < NH; ++t) h1x[t] = h1y[t] = h1z[t] = e1x[t] = e1y[t] = e1z[t] = 0.f;
+#pragma unroll
+  for (int t = 0; t < SR + 2; ++t) h2x[t] = h2y[t] = 0.f;
+  int m = kb - 2;
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const uint32_t q = at(t, m);
+    ex0[t] = Ex[q]; ey0[t] = Ey[q]; ez0[t] = Ez[q];
+  }
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const uint32_t q = at(t, m + 1);
+    exn[t] = Ex[q]; eyn[t] = Ey[q]; ezn[t] = Ez[q];
+  }
+#pragma unroll
+  for (int t = 0; t < NH; ++t) {
+    const uint32_t q = at(t, m);
+    hxo[t] = Hx[q]; hyo[t] = Hy[q]; hzo[t] = Hz[q];
+  }
+  for (; m <= ke; ++m) {
+    // next plane's E^n(m+2) and H^{n-1/2}(m+1), one iteration ahead
+    float pxn[NE], pyn[NE], pzn[NE], pxo[NH], pyo[NH], pzo[NH];
+    if (m < ke) {
+#pragma unroll
+      for (int t = 0; t < NE; ++t) {
+        const uint32_t q = at(t, m + 2);
+        pxn[t] = Ex[q]; pyn[t] = Ey[q]; pzn[t] = Ez[q];
+      }
+#pragma unroll
+      for (int t = 0; t < NH; ++t) {
+        const uint32_t q = at(t, m + 1);
+        pxo[t] = Hx[q]; pyo[t] = Hy[q]; pzo[t] = Hz[q];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NE; ++t) pxn[t] = pyn[t] = pzn[t] = 0.f;
+#pragma unroll
+      for (int t = 0; t < NH; ++t) pxo[t] = pyo[t] = pzo[t] = 0.f;
+    }
+    // H^{n+1/2}(m): Hx: d_y Ez - d_z Ey; Hy: d_z Ex - d_x Ez; Hz: d_x Ey - d_y Ex
+    float hx[NH], hy[NH], hz[NH];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const float ezR = lane_right(ez0[t]), eyR = lane_right(ey0[t]);
+      hx[t] = hxo[t] - ch * ((ez0[t + 1] - ez0[t]) - (eyn[t] - ey0[t]));
+      hy[t] = hyo[t] - ch * ((exn[t] - ex0[t]) - (ezR - ez0[t]));
+      hz[t] = hzo[t] - ch * ((eyR - ey0[t]) - (ex0[t + 1] - ex0[t]));
+    }
+    // E^{n+1}(m): Ex: d_y Hz - d_z Hy; Ey: d_z Hx - d_x Hz; Ez: d_x Hy - d_y Hx
+    float ex[NH], ey[NH], ez[NH];
+#pragma unroll
+    for (int t = 1; t < NH; ++t) {
+      const float hzL = lane_left(hz[t]), hyL = lane_left(hy[t]);
+      ex[t] = ex0[t] + ce * ((hz[t] - hz[t - 1]) - (hy[t] - h1y[t]));
+      ey[t] = ey0[t] + ce * ((hx[t] - h1x[t]) - (hz[t] - hzL));
+      ez[t] = ez0[t] + ce * ((hy[t] - hyL) - (hx[t] - hx[t - 1]));
+    }
+    if (m >= kb && m < ke) {
+      // border nodes: the state after the first step, for the per-step launches
+#pragma unroll
+      for (int t = 2; t < SR + 2; ++t) {
+        const int j = y0 - 2 + t;
+        const bool border = bxf || (j == b && (faces & 4)) || (j == b + SCY - 1 && (faces & 8)) ||
+                            (m == kb && (faces & 16)) || (m == ke - 1 && (faces & 32));
+        if (own && border) {
+          const uint32_t q = at(t, m);
+          M[q] = ex[t];
+          M[q + S] = ey[t];
+          M[q + 2 * S] = ez[t];
+          M[q + 3 * S] = hx[t];
+          M[q + 4 * S] = hy[t];
+          M[q + 5 * S] = hz[t];
+        }
+      }
+    }
+    if (m >= kb) {
+      // H^{n+3/2}(m-1) from E^{n+1}(m-1) (carried) and E^{n+1}(m)
+      float gx[SR + 2], gy[SR + 2], gz[SR + 2];
+#pragma unroll
+      for (int t = 1; t < SR + 2; ++t) {
+        const float ezR = lane_right(e1z[t]), eyR = lane_right(e1y[t]);
+        gx[t] = h1x[t] - ch * ((e1z[t + 1] - e1z[t]) - (ey[t] - e1y[t]));
+        gy[t] = h1y[t] - ch * ((ex[t] - e1x[t]) - (ezR - e1z[t]));
+        gz[t] = h1z[t] - ch * ((eyR - e1y[t]) - (e1x[t + 1] - e1x[t]));
+      }
+      if (m >= kb + 1) {
+        // E^{n+2}(m-1); store it and H^{n+3/2}(m-1)
+#pragma unroll
+        for (int t = 2; t < SR + 2; ++t) {
+          const float gzL = lane_left(gz[t]), gyL = lane_left(gy[t]);
+          const float fx = e1x[t] + ce * ((gz[t] - gz[t - 1]) - (gy[t] - h2y[t]));
+          const float fy = e1y[t] + ce * ((gx[t] - h2x[t]) - (gz[t] - gzL));
+          const float fz = e1z[t] + ce * ((gy[t] - gyL) - (gx[t] - gx[t - 1]));
+          if (own) {
+            const uint32_t q = at(t, m - 1);
+            __builtin_nontemporal_store(fx, &O[q]);
+            __builtin_nontemporal_store(fy, &O[q + S]);
+            __builtin_nontemporal_store(fz, &O[q + 2 * S]);
+            __builtin_nontemporal_store(gx[t], &O[q + 3 * S]);
+            __builtin_nontemporal_store(gy[t], &O[q + 4 * S]);
+            __builtin_nontemporal_store(gz[t], &O[q + 5 * S]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 2; t < SR + 2; ++t) {
+        h2x[t] = gx[t];
+        h2y[t] = gy[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      ex0[t] = exn[t]; ey0[t] = eyn[t]; ez0[t] = ezn[t];
+      exn[t] = pxn[t]; eyn[t] = pyn[t]; ezn[t] = pzn[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      h1x[t] = hx[t]; h1y[t] = hy[t]; h1z[t] = hz[t];
+      hxo[t] = pxo[t]; hyo[t] = pyo[t]; hzo[t] = pzo[t];
+    }
+#pragma unroll
+    for (int t = 1; t < NH; ++t) {
+      e1x[t] = ex[t]; e1y[t] = ey[t]; e1z[t] = ez[t];
+    }
   }
 }
 
@@ -826,6 +1044,133 @@ std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &
   return out;
 }
 
+template <typename T>
+std::vector<int> plan3d_super(const Step3D<T> &p, int so[3], int sn[3], std::vector<unsigned char> &flags) {
+  const int n3[3] = {p.n[0], p.n[1], p.n[2]}, nx = n3[0], ny = n3[1], nz = n3[2], P = p.P;
+  const size_t tot = (size_t)nx * ny * nz;
+  auto id = [&](int i, int j, int k) { return ((size_t)k * ny + j) * nx + i; };
+  // nodes of plain tile-planes (general tiling)
+  std::vector<unsigned char> ok(tot, 0);
+  for (int j0 = 0; j0 < ny; j0 += TY)
+    for (int i0 = 0; i0 < nx; i0 += TX) {
+      const Tile tl = tile_xy(p, i0, j0);
+      if (!tl.xy_plain) continue;
+      for (int k = 0; k < nz; ++k)
+        if (plane_plain(p, tl, k))
+          for (int j = j0; j < std::min(j0 + TY, ny); ++j)
+            for (int i = i0; i < std::min(i0 + TX, nx); ++i) ok[id(i, j, k)] = 1;
+    }
+  // plain background: off the walls and absorber (E and H), injection lines
+  // and faces, design and gap; then every node within three of it too
+  std::vector<unsigned char> ph(tot, 0);
+  std::vector<char> axok[3];
+  for (int a = 0; a < 3; ++a) {
+    axok[a].assign(n3[a], 0);
+    for (int i = 1; i <= n3[a] - 2; ++i) {
+      bool g = !pml_e(i, n3[a], P) && !pml_h(i, n3[a], P);
+      if (p.tf_on) g = g && i != p.lo[a] - 1 && i != p.lo[a] && i != p.hi[a] && i != p.hi[a] + 1;
+      axok[a][i] = g;
+    }
+  }
+  auto inbox = [](const int *lo, const int *n, int i, int j, int k) {
+    return i >= lo[0] && i < lo[0] + n[0] && j >= lo[1] && j < lo[1] + n[1] && k >= lo[2] && k < lo[2] + n[2];
+  };
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        ph[id(i, j, k)] = axok[0][i] && axok[1][j] && axok[2][k] && !inbox(p.d0, p.dn, i, j, k) &&
+                          !inbox(p.g0, p.gn, i, j, k);
+  // erosion by 3 along each axis in turn (a box of side 7): a node stays when
+  // the 7 nodes of its line centred on it are all plain
+  std::vector<unsigned char> tmp(tot);
+  const size_t st[3] = {1, (size_t)nx, (size_t)nx * ny};
+  for (int a = 0; a < 3; ++a) {
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    for (int u = 0; u < n3[b1]; ++u)
+      for (int v = 0; v < n3[b2]; ++v) {
+        const size_t base = (size_t)u * st[b1] + (size_t)v * st[b2];
+        int run = 0;  // plain nodes in a row ending at x + 3
+        for (int x = -3; x < n3[a]; ++x) {
+          const int y = x + 3;
+          run = (y < n3[a] && ph[base + (size_t)y * st[a]]) ? run + 1 : 0;
+          if (x >= 0) tmp[base + (size_t)x * st[a]] = x >= 3 && x + 3 < n3[a] && run >= 7;
+        }
+      }
+    ph.swap(tmp);
+  }
+  // prefix sums of ineligible nodes, for O(1) chunk tests
+  std::vector<int> pre((size_t)(nx + 1) * (ny + 1) * (nz + 1), 0);
+  auto P3 = [&](int i, int j, int k) -> int & { return pre[((size_t)k * (ny + 1) + j) * (nx + 1) + i]; };
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int bad = !(ok[id(i, j, k)] && ph[id(i, j, k)]);
+        P3(i + 1, j + 1, k + 1) = bad + P3(i, j + 1, k + 1) + P3(i + 1, j, k + 1) + P3(i + 1, j + 1, k) -
+                                  P3(i, j, k + 1) - P3(i, j + 1, k) - P3(i + 1, j, k) + P3(i, j, k);
+      }
+  auto clean = [&](int x, int y, int z) {  // chunk with origin (x, y, z) has no ineligible node
+    const int X = x + SCX, Y = y + SCY, Z = z + SCZ;
+    if (x < 0 || y < 0 || z < 0 || X > nx || Y > ny || Z > nz) return false;
+    return P3(X, Y, Z) - P3(x, Y, Z) - P3(X, y, Z) - P3(X, Y, z) + P3(x, y, Z) + P3(x, Y, z) + P3(X, y, z) -
+               P3(x, y, z) == 0;
+  };
+  // origin of the chunk grid: a few offsets from the plain box, the one
+  // covering the most nodes
+  int best = -1;
+  for (int dz = 0; dz < SCZ; dz += 2)
+    for (int dy = 0; dy < SCY; dy += 2)
+      for (int dx = 0; dx < 12; dx += 2) {
+        const int o[3] = {p.pb[0] + dx, p.pb[1] + dy, p.pb[2] + dz};
+        int cnt = 0;
+        for (int z = o[2]; z + SCZ <= nz; z += SCZ)
+          for (int y = o[1]; y + SCY <= ny; y += SCY)
+            for (int x = o[0]; x + SCX <= nx; x += SCX) cnt += clean(x, y, z);
+        if (cnt > best) {
+          best = cnt;
+          for (int a = 0; a < 3; ++a) so[a] = o[a];
+        }
+      }
+  const int sc[3] = {SCX, SCY, SCZ};
+  for (int a = 0; a < 3; ++a) sn[a] = best > 0 ? std::max(0, (n3[a] - so[a]) / sc[a]) : 0;
+  flags.assign((size_t)std::max(1, sn[0] * sn[1] * sn[2]), 0);
+  if (best <= 0) return {};
+  for (int cz = 0; cz < sn[2]; ++cz)
+    for (int cy = 0; cy < sn[1]; ++cy)
+      for (int cx = 0; cx < sn[0]; ++cx)
+        flags[((size_t)cz * sn[1] + cy) * sn[0] + cx] =
+            clean(so[0] + cx * SCX, so[1] + cy * SCY, so[2] + cz * SCZ);
+  auto sup = [&](int cx, int cy, int cz) {
+    return cx >= 0 && cy >= 0 && cz >= 0 && cx < sn[0] && cy < sn[1] && cz < sn[2] &&
+           flags[((size_t)cz * sn[1] + cy) * sn[0] + cx];
+  };
+  std::vector<int> codes, group, work;
+  for (int cz = 0; cz < sn[2]; ++cz)
+    for (int cy = 0; cy < sn[1]; ++cy)
+      for (int cx = 0; cx < sn[0]; ++cx) {
+        if (!sup(cx, cy, cz)) continue;
+        // face f (axis f/2, side f%2) is a border when any of the nine chunks
+        // across it (edges and corners included) is not a super-chunk
+        int faces = 0;
+        for (int f = 0; f < 6; ++f) {
+          const int ax = f / 2, sd = f % 2 ? 1 : -1;
+          bool border = false;
+          for (int u = -1; u <= 1; ++u)
+            for (int v = -1; v <= 1; ++v) {
+              int d[3];
+              d[ax] = sd;
+              d[(ax + 1) % 3] = u;
+              d[(ax + 2) % 3] = v;
+              border = border || !sup(cx + d[0], cy + d[1], cz + d[2]);
+            }
+          if (border) faces |= 1 << f;
+        }
+        codes.push_back((((cz * sn[1] + cy) * sn[0] + cx) << 6) | faces);
+        group.push_back(cz * ((sn[1] + 1) / 2) + cy / 2);
+        work.push_back(1);
+      }
+  return xcd_order(codes, group, work);
+}
+
 #ifndef FDTD3D_AUX
 #define FDTD3D_AUX 1
 #endif
@@ -858,10 +1203,10 @@ static void launch_general(const Step3D<T> &q, int n, hipStream_t s, const Aux3D
 }
 
 template <typename T>
-void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s, const Aux3D &aux) {
+void launch_step3d(const Step3D<T> &p, T *rd, T *wr, int n, bool adjoint, hipStream_t s, const Aux3D &aux) {
   Step3D<T> q = p;  // copy 0 is read, copy 1 written
-  q.A[0] = p.A[par];
-  q.A[1] = p.A[par ^ 1];
+  q.A[0] = rd;
+  q.A[1] = wr;
   // the general tile-chunks (three launches by what they need), then the
   // plain ones, which read back the new H of a general plane below them
   if (adjoint) launch_general<T, true>(q, n, s, aux);
@@ -900,7 +1245,15 @@ template std::vector<int> gen3d_plan<float>(const Step3D<float> &, int &, int &,
 template std::vector<int> gen3d_plan<double>(const Step3D<double> &, int &, int &, int &, int &);
 template void plain3d_box<float>(const Step3D<float> &, int *);
 template void plain3d_box<double>(const Step3D<double> &, int *);
-template void launch_step3d<float>(const Step3D<float> &, int, int, bool, hipStream_t, const Aux3D &);
-template void launch_step3d<double>(const Step3D<double> &, int, int, bool, hipStream_t, const Aux3D &);
+template void launch_step3d<float>(const Step3D<float> &, float *, float *, int, bool, hipStream_t, const Aux3D &);
+template void launch_step3d<double>(const Step3D<double> &, double *, double *, int, bool, hipStream_t, const Aux3D &);
+template std::vector<int> plan3d_super<float>(const Step3D<float> &, int *, int *, std::vector<unsigned char> &);
+template std::vector<int> plan3d_super<double>(const Step3D<double> &, int *, int *, std::vector<unsigned char> &);
+
+void launch_step3d_super(const Step3D<float> &p, const float *rd, float *mid, float *out, const int *list, int count,
+                         hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(step3d_super, dim3(count), dim3(64 * SW), 0, s, p, rd, mid, out, list);
+}
 
 }  // namespace fdtd

@@ -90,7 +90,30 @@ struct Step3D {
   const int *glist;
   int gS, gM, gD, gAxD;
   int pb[6];  // bounding box of the plain tile-planes: origin x, y, z, extent x, y, z (from plain3d_box)
+  // Two-step blocking of the plain background (see plan3d_super): the grid of
+  // super-chunks (origin so, chunk counts sn), one flag byte per chunk
+  // (non-zero: the chunk advances two steps per pass), and whether a
+  // per-step launch leaves the super-chunks' nodes to the two-step pass.
+  const unsigned char *sflag;
+  int so[3], sn[3];
+  int skip_super;
+  T *Amid;  // two-step pass: the copy that receives the intermediate state of the chunks' border nodes
 };
+
+// Two-step super-chunks: 60 x 16 x 8 nodes (a wavefront spans 64 columns, two
+// of halo on each side; four wavefronts of four rows each).
+constexpr int SCX = 60, SCY = 16, SCZ = 8;
+
+// The chunks of plain background that advance two time steps per pass: every
+// node of the chunk lies in a plain tile-plane of the general tiling and all
+// nodes within three of it (in each axis) are plain background (no absorber,
+// wall, injection line or face, design or gap).  Fills the grid (origin so,
+// counts sn, flags per chunk) and returns the launch list: per chunk
+// (index << 6) | border faces (bit f set: face f = x-, x+, y-, y+, z-, z+
+// touches a node outside the super-chunks, whose neighbours read the chunk's
+// intermediate state there), ordered for the 8 XCDs and padded with -1.
+template <typename T>
+std::vector<int> plan3d_super(const Step3D<T> &p, int so[3], int sn[3], std::vector<unsigned char> &flags);
 
 // Tile-chunks of the general update, sorted by what they need: one or no
 // absorber axis (code 4c + axis, axis 3 = none), several axes, the design or
@@ -115,7 +138,15 @@ struct Aux3D {
   hipEvent_t fork, join;
 };
 
+// One time step: copy rd read, copy wr written (general launches, then the
+// plain launch, which skips the super-chunks when p.skip_super is set).
 template <typename T>
-void launch_step3d(const Step3D<T> &p, int n, int par, bool adjoint, hipStream_t s, const Aux3D &aux);
+void launch_step3d(const Step3D<T> &p, T *rd, T *wr, int n, bool adjoint, hipStream_t s, const Aux3D &aux);
+
+// The two-step pass over `count` listed super-chunks: reads copy rd (state
+// after s steps), writes the state after s + 2 into out and the border nodes'
+// state after s + 1 into mid.  FP32 only.
+void launch_step3d_super(const Step3D<float> &p, const float *rd, float *mid, float *out, const int *list, int count,
+                         hipStream_t s);
 
 }  // namespace fdtd

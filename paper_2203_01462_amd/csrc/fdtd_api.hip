@@ -4,10 +4,12 @@
 #include <algorithm>
 #include <array>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "fdtd_2d.hpp"
@@ -33,16 +35,23 @@ struct fdtd_ctx {
   // device memory: 2D fields (Ez, Hx, Hy) and absorber memories (4), two
   // copies each; 3D: one arena per copy (fields and absorber slabs) and the
   // packed CPML tables
-  DevBuf fld[2][6], pml[2][12], arena3[2], tab3, J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
+  DevBuf fld[2][6], pml[2][12], arena3[3], tab3, J, rho, hist, grad, dft, gapE, phasor, wts, dfreq, asrc, einc, hinc;
   DevBuf axis[18], gwave, lineprof, linescr, scal, bad, Fdev, gtmp;
   // checkpointed adjoint: a second state (both copies and J) for re-running
   // forward segments, and the snapshots [nseg-1][state copy + J]
-  DevBuf fldR[2][6], pmlR[2][12], arenaR[2], JR, snap;
+  DevBuf fldR[2][6], pmlR[2][12], arenaR[3], JR, snap;
   // 2D two-step blocking of the plain background: a third copy of the fields
   // (main and re-run state), the super-tiles and the per-step tiles
   DevBuf fld3[3], fld3R[3], tbTiles, tbRest;
   DevBuf glist3;  // 3D: tile-chunk lists of the general update
   int gS = 0, gM = 0, gD = 0, gAxD = 0;  // lengths of the three lists in glist3
+  // 3D two-step blocking of the plain background (FP32): the super-chunk
+  // launch list and flag grid; with super-chunks the state rotates over
+  // three arenas (the state after s steps lives in arena s mod 3)
+  DevBuf sup_list, sup_flags;
+  Aux3D sup{nullptr, nullptr, nullptr}, supR{nullptr, nullptr, nullptr};  // the pass's stream (main, re-run lane)
+  int nSup = 0, so3[3] = {0, 0, 0}, sn3[3] = {0, 0, 0};
+  bool sup_planned = false;
   int nTb = 0, nRest = 0, nEarly = 0;  // tbTiles = [interior super-tiles (run early) | border ones]
   int ck = 0, nseg = 1;  // segment length (steps) and count; nseg = 1: full history
   size_t snap_bytes = 0;
@@ -200,6 +209,18 @@ void deal_to_xcds(std::vector<int> &v, int lo, int hi, G group) {
   }
 }
 
+// Two-step blocking of the plain background, read when a context is
+// created: FDTD_TEMPORAL_BLOCKING=0 turns it off, =1 on; unset, 2D contexts
+// use it (super-tiles) and 3D contexts do not (super-chunks: bit-identical
+// but slower on the 256^3 workload, whose plain background is half the grid
+// and a third of the step time).  Both schedules give the same results.
+bool blocking_enabled(int dims) {
+  const char *v = std::getenv("FDTD_TEMPORAL_BLOCKING");
+  if (v && v[0] == '0') return false;
+  if (v && v[0] == '1') return true;
+  return dims == 2;
+}
+
 void create_2d(fdtd_ctx *c) {
   const fdtd_config &g = c->cfg;
   const int P = g.pml_cells, m = g.tfsf_margin;
@@ -238,7 +259,7 @@ void create_2d(fdtd_ctx *c) {
   // without a plane wave there are no injection lines to keep clear
   Tb2dPlan pl = tf ? tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox)
                    : tb2d_plan(c->nx, c->ny, P, -8, -8, -8, -8, dbox, gbox);
-  if (!pl.tb.empty()) {
+  if (!pl.tb.empty() && blocking_enabled(2)) {
     // the interior super-tiles run one launch early (beside the rest tiles'
     // second step of the previous pair), the border ones after them
     std::vector<int> order;
@@ -277,6 +298,12 @@ void create_2d(fdtd_ctx *c) {
 // copy s+2, as two single steps would), else two.  Absorber memories always
 // alternate between two copies.
 int fcopy(const fdtd_ctx *c, int s) { return c->nTb > 0 ? s % 3 : s & 1; }
+
+// 3D arena holding the state after `s` steps: three rotate with two-step
+// blocking, else two.
+int acopy(const fdtd_ctx *c, int s) { return c->nSup > 0 ? s % 3 : s & 1; }
+DevBuf &arena(fdtd_ctx *c, bool rerun, int s) { return rerun ? c->arenaR[acopy(c, s)] : c->arena3[acopy(c, s)]; }
+
 
 DevBuf *field_buf(fdtd_ctx *c, bool rerun, int copy, int k) {
   if (copy == 2) return rerun ? &c->fld3R[k] : &c->fld3[k];
@@ -354,6 +381,8 @@ void create_3d(fdtd_ctx *c) {
 void release_aux(fdtd_ctx *c) {
   release_one(c->aux);
   release_one(c->auxR);
+  release_one(c->sup);
+  release_one(c->supR);
   if (c->rr) (void)hipStreamSynchronize(c->rr);
   for (hipEvent_t *e : {&c->evStart, &c->evRerun, &c->evAdj[0], &c->evAdj[1]}) {
     if (*e) (void)hipEventDestroy(*e);
@@ -402,6 +431,30 @@ void fill_params3d(fdtd_ctx *c, Step3D<T> &p, bool rerun) {
   p.glist = c->glist3.as<int>();
   p.gS = c->gS; p.gM = c->gM; p.gD = c->gD; p.gAxD = c->gAxD;
   plain3d_box(p, p.pb);
+  if (!c->sup_planned) {
+    c->sup_planned = true;
+    if (c->prec == 32 && blocking_enabled(3)) {
+      std::vector<unsigned char> flags;
+      const std::vector<int> list = plan3d_super(p, c->so3, c->sn3, flags);
+      c->nSup = (int)list.size();
+      if (c->nSup > 0) {
+        upload(c->stream, c->sup_list, list);
+        upload(c->stream, c->sup_flags, flags);
+        FDTD_HIP(hipStreamSynchronize(c->stream));
+        c->arena3[2].alloc((size_t)c->lay3.total * c->esz);
+        if (c->nseg > 1) c->arenaR[2].alloc((size_t)c->lay3.total * c->esz);
+        create_one(c->sup);
+        if (c->nseg > 1) create_one(c->supR);
+      }
+    }
+  }
+  p.sflag = c->nSup > 0 ? c->sup_flags.as<unsigned char>() : nullptr;
+  for (int a = 0; a < 3; ++a) {
+    p.so[a] = c->so3[a];
+    p.sn[a] = c->nSup > 0 ? c->sn3[a] : 0;
+  }
+  p.skip_super = 0;
+  p.Amid = nullptr;
   const double dt = c->dt, dx = g.dx;
   const double psi = g.omega_p * g.omega_p, psi_s = g.psi_s_ratio * psi;
   const double gam = g.gamma_mult * g.gamma_p;
@@ -515,8 +568,9 @@ void zero_state(fdtd_ctx *c) {
   for (int b = 0; b < 2; ++b) {
     for (int k = 0; k < 6; ++k) if (c->fld[b][k].p) zero(c, c->fld[b][k]);
     for (int k = 0; k < 12; ++k) if (c->pml[b][k].p) zero(c, c->pml[b][k]);
-    if (c->arena3[b].p) zero(c, c->arena3[b]);
   }
+  for (int b = 0; b < 3; ++b)
+    if (c->arena3[b].p) zero(c, c->arena3[b]);
   for (int k = 0; k < 3; ++k) if (c->fld3[k].p) zero(c, c->fld3[k]);
   zero(c, c->J);
 }
@@ -606,7 +660,7 @@ void download_state(fdtd_ctx *c, double *out) {
   const int nfe = c->dims == 2 ? 3 : 6;
   std::vector<std::vector<T>> img(c->dims == 2 ? 3 : 1);
   for (size_t b = 0; b < img.size(); ++b) {
-    DevBuf *src = c->dims == 2 ? field_buf(c, false, fcopy(c, c->N), (int)b) : &c->arena3[c->N & 1];
+    DevBuf *src = c->dims == 2 ? field_buf(c, false, fcopy(c, c->N), (int)b) : &arena(c, false, c->N);
     img[b].resize(src->bytes / sizeof(T));
     FDTD_HIP(hipMemcpyAsync(img[b].data(), src->p, src->bytes, hipMemcpyDeviceToHost, c->stream));
   }
@@ -641,14 +695,15 @@ Step3D<float> &params3d<float>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3fR
 template <>
 Step3D<double> &params3d<double>(fdtd_ctx *c, bool rerun) { return rerun ? c->p3dR : c->p3d; }
 
-// Where a block of steps runs: its stream, the 3D side stream, and the
-// history buffer the design edges write (forward) or read (adjoint).
+// Where a block of steps runs: its stream, the 3D side streams (general
+// launches; two-step pass), and the history buffer the design edges write
+// (forward) or read (adjoint).
 struct Lane {
   hipStream_t s;
-  const Aux3D *aux;
+  const Aux3D *aux, *sup;
   void *hist;
 };
-Lane main_lane(fdtd_ctx *c) { return Lane{c->stream, &c->aux, c->hist.p}; }
+Lane main_lane(fdtd_ctx *c) { return Lane{c->stream, &c->aux, &c->sup, c->hist.p}; }
 
 // 2D parameters of the step that follows `s` steps of a solve: copy 0 read,
 // copy 1 written, parities resolved.
@@ -684,7 +739,7 @@ void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_b
     p.hist = static_cast<T *>(ln.hist);
     p.hist_base = hist_base;
     p.hist_on = hist_on;
-    launch_step3d<T>(p, n, s & 1, adjoint, ln.s, *ln.aux);
+    launch_step3d<T>(p, arena(c, rerun, s).as<T>(), arena(c, rerun, s + 1).as<T>(), n, adjoint, ln.s, *ln.aux);
   }
 }
 
@@ -698,9 +753,42 @@ void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_b
 // pair is already written, and write their output into the copy that the
 // rest tiles read in that launch only outside the super-tiles.  An odd last
 // step is a full-grid single step.
+//
+// In 3D with super-chunks (FP32) a pair is the two-step pass over the
+// super-chunks (state after s0+2q read, after s0+2q+2 written, border nodes
+// also after s0+2q+1) on the lane's pass stream, beside the first per-step
+// update of the other nodes, and the second per-step update after both.
+// The three arenas make the pass's reads and writes disjoint from those of
+// the first per-step update.
 template <typename T, typename NOF, typename HON>
 void run_block(fdtd_ctx *c, bool rerun, bool adjoint, int s0, int count, NOF nof, int hbase, HON hon,
                const Lane &ln) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->dims == 3 && c->nSup > 0) {
+      const int P = count / 2;
+      for (int q = 0; q < P; ++q) {
+        const int s = s0 + 2 * q;
+        Step3D<float> p = params3d<float>(c, rerun);
+        p.hist = static_cast<float *>(ln.hist);
+        p.hist_base = hbase;
+        const Aux3D &sp = *ln.sup;
+        FDTD_HIP(hipEventRecord(sp.fork, ln.s));
+        FDTD_HIP(hipStreamWaitEvent(sp.stream, sp.fork, 0));
+        launch_step3d_super(p, arena(c, rerun, s).as<float>(), arena(c, rerun, s + 1).as<float>(),
+                            arena(c, rerun, s + 2).as<float>(), c->sup_list.as<int>(), c->nSup, sp.stream);
+        FDTD_HIP(hipEventRecord(sp.join, sp.stream));
+        p.skip_super = 1;
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1) FDTD_HIP(hipStreamWaitEvent(ln.s, sp.join, 0));
+          p.hist_on = hon(2 * q + h);
+          launch_step3d<float>(p, arena(c, rerun, s + h).as<float>(), arena(c, rerun, s + h + 1).as<float>(),
+                               nof(2 * q + h), adjoint, ln.s, *ln.aux);
+        }
+      }
+      if (count & 1) launch_step<T>(c, rerun, nof(count - 1), s0 + count - 1, adjoint, hbase, hon(count - 1), ln);
+      return;
+    }
+  }
   if (c->dims != 2 || c->nTb == 0) {
     for (int j = 0; j < count; ++j) launch_step<T>(c, rerun, nof(j), s0 + j, adjoint, hbase, hon(j), ln);
     return;
@@ -738,7 +826,7 @@ std::vector<DevBuf *> state_bufs(fdtd_ctx *c, int st, bool rerun) {
     for (int k = 0; k < 3; ++k) v.push_back(field_buf(c, rerun, fcopy(c, st), k));
     for (int k = 0; k < 4; ++k) v.push_back(rerun ? &c->pmlR[st & 1][k] : &c->pml[st & 1][k]);
   } else {
-    v.push_back(rerun ? &c->arenaR[st & 1] : &c->arena3[st & 1]);
+    v.push_back(&arena(c, rerun, st));
   }
   v.push_back(rerun ? &c->JR : &c->J);
   return v;
@@ -789,7 +877,7 @@ struct ForwardWatch {
       DevBuf *e = field_buf(c, false, fcopy(c, s), 0);
       launch_watch(c->stream, c->prec, e->p, e->bytes / c->esz, slot);
     } else {
-      const char *e = c->arena3[s & 1].as<char>() + (size_t)c->lay3.G0 * c->esz;
+      const char *e = arena(c, false, s).as<char>() + (size_t)c->lay3.G0 * c->esz;
       launch_watch(c->stream, c->prec, e, (size_t)3 * c->lay3.S, slot);
     }
     FDTD_HIP(hipMemcpyAsync(c->watch_host + slots, slot, sizeof(*slot), hipMemcpyDeviceToHost, c->stream));
@@ -865,7 +953,7 @@ void run_adjoint(fdtd_ctx *c) {
     run_block<T>(c, false, true, N - b, b - a, [=](int j) { return b - j; }, a, [](int) { return false; }, main);
   };
   if (S > 1 && c->hist2.p) {
-    Lane rl{c->rr, &c->auxR, nullptr};
+    Lane rl{c->rr, &c->auxR, &c->supR, nullptr};
     FDTD_HIP(hipEventRecord(c->evStart, c->stream));
     FDTD_HIP(hipStreamWaitEvent(c->rr, c->evStart, 0));
     for (int s = S - 1; s >= 0; --s) {
@@ -1360,8 +1448,9 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
       for (int b = 0; b < 2; ++b) {
         for (int k = 0; k < 6; ++k) if (c->fldR[b][k].p) zero(c.get(), c->fldR[b][k]);
         for (int k = 0; k < 12; ++k) if (c->pmlR[b][k].p) zero(c.get(), c->pmlR[b][k]);
-        if (c->arenaR[b].p) zero(c.get(), c->arenaR[b]);
       }
+      for (int b = 0; b < 3; ++b)
+        if (c->arenaR[b].p) zero(c.get(), c->arenaR[b]);
       // the third field copy of the two-step schedule: a re-run whose
       // segment starts in copy 0 or 1 reads this copy's wall nodes before
       // any step has written them

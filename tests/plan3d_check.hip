@@ -4,8 +4,10 @@
 // tile-chunk holding a general plane appears in exactly one list, that no
 // other chunk does, that single-axis codes name the one absorber axis the
 // chunk's planes need, that the design list holds exactly the chunks that
-// meet the design or gap box, and that the plain launch's box holds every
-// plain tile-plane.  Prints one summary line; exit status 0 when all hold.
+// meet the design or gap box, that the plain launch's box holds every
+// plain tile-plane, and that the two-step super-chunks keep to plain
+// background and store every node the per-step launches read from them.
+// Prints one summary line; exit status 0 when all hold.
 #include "../paper_2203_01462_amd/csrc/fdtd_3d.hip"
 
 #include <cstdio>
@@ -99,7 +101,86 @@ int main(int argc, char **argv) {
     if (part[c] == 1 && (ax == 0 || ax == 1 || ax == 2 || ax == 4)) ++bad;
     if (part[c] == 2 && (ax & ~axD)) ++bad;
   }
-  std::printf("chunks %d general %d lists %d %d %d axD %d plain-box %d %d %d %d %d %d plain-planes %d bad %d\n", tot,
-              general, nS, nM, nD, axD, pb[0], pb[1], pb[2], pb[3], pb[4], pb[5], plain_planes, bad);
+  // two-step super-chunks: each flagged chunk once in the launch list; every
+  // chunk node in a plain tile-plane and every node within three of the
+  // chunk plain background (inside the walls, off the absorber, injection
+  // planes, design and gap); every super-chunk node that a node outside the
+  // super-chunks reads in a per-step update (its 26 neighbours) stored by the
+  // pass's border rule
+  for (int a = 0; a < 6; ++a) p.pb[a] = pb[a];
+  int so[3], sn[3];
+  std::vector<unsigned char> flags;
+  const std::vector<int> SL = plan3d_super(p, so, sn, flags);
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2], P = p.P;
+  int nsup = 0, sbad = 0;
+  std::vector<int> faces_of(flags.size(), -1);
+  if (SL.size() % 8) ++sbad;
+  for (int code : SL) {
+    if (code < 0) continue;
+    const int ci = code >> 6;
+    if (ci >= (int)flags.size() || !flags[ci] || faces_of[ci] >= 0) {
+      ++sbad;
+      continue;
+    }
+    faces_of[ci] = code & 63;
+    ++nsup;
+  }
+  auto plain_node = [&](int i, int j, int k) {
+    const int c3[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+      const int v = c3[a], n = p.n[a];
+      if (v < 1 || v > n - 2 || pml_e(v, n, P) || pml_h(v, n, P)) return false;
+      if (v == p.lo[a] - 1 || v == p.lo[a] || v == p.hi[a] || v == p.hi[a] + 1) return false;
+    }
+    auto in = [&](const int *o, const int *n) {
+      return i >= o[0] && i < o[0] + n[0] && j >= o[1] && j < o[1] + n[1] && k >= o[2] && k < o[2] + n[2];
+    };
+    return !in(p.d0, p.dn) && !in(p.g0, p.gn);
+  };
+  std::vector<int> owner((size_t)nx * ny * nz, -1);  // super-chunk of each node
+  for (int ci = 0; ci < (int)flags.size(); ++ci) {
+    if (!flags[ci]) continue;
+    if (faces_of[ci] < 0) ++sbad;  // flagged but not launched
+    const int cx = ci % sn[0], cy = (ci / sn[0]) % sn[1], cz = ci / (sn[0] * sn[1]);
+    const int a = so[0] + cx * SCX, b = so[1] + cy * SCY, kb = so[2] + cz * SCZ;
+    for (int k = kb - 3; k < kb + SCZ + 3; ++k)
+      for (int j = b - 3; j < b + SCY + 3; ++j)
+        for (int i = a - 3; i < a + SCX + 3; ++i) {
+          if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz || !plain_node(i, j, k)) {
+            ++sbad;
+            continue;
+          }
+          const bool mine = i >= a && i < a + SCX && j >= b && j < b + SCY && k >= kb && k < kb + SCZ;
+          if (!mine) continue;
+          const Tile tl = tile_xy(p, i - i % TX, j - j % TY);
+          if (!plane_plain(p, tl, k)) ++sbad;
+          owner[((size_t)k * ny + j) * nx + i] = ci;
+        }
+  }
+  long long super_nodes = 0;
+  for (int k = 1; k < nz - 1; ++k)
+    for (int j = 1; j < ny - 1; ++j)
+      for (int i = 1; i < nx - 1; ++i) {
+        const int ci = owner[((size_t)k * ny + j) * nx + i];
+        if (ci < 0) continue;
+        ++super_nodes;
+        const int f = faces_of[ci];
+        if (f < 0) continue;
+        const int cx = ci % sn[0], cy = (ci / sn[0]) % sn[1], cz = ci / (sn[0] * sn[1]);
+        const int a = so[0] + cx * SCX, b = so[1] + cy * SCY, kb = so[2] + cz * SCZ;
+        const bool stored = (i == a && (f & 1)) || (i == a + SCX - 1 && (f & 2)) || (j == b && (f & 4)) ||
+                            (j == b + SCY - 1 && (f & 8)) || (k == kb && (f & 16)) || (k == kb + SCZ - 1 && (f & 32));
+        bool read_outside = false;
+        for (int dk = -1; dk <= 1; ++dk)
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di)
+              read_outside = read_outside || owner[((size_t)(k + dk) * ny + j + dj) * nx + i + di] < 0;
+        if (read_outside && !stored) ++sbad;
+      }
+  bad += sbad;
+  std::printf("chunks %d general %d lists %d %d %d axD %d plain-box %d %d %d %d %d %d plain-planes %d "
+              "super %d super-nodes %lld super-bad %d bad %d\n",
+              tot, general, nS, nM, nD, axD, pb[0], pb[1], pb[2], pb[3], pb[4], pb[5], plain_planes, nsup, super_nodes,
+              sbad, bad);
   return bad ? 1 : 0;
 }

@@ -97,3 +97,50 @@ def test_blocked_schedule_bit_identical_full_size(gpu):
         print(f"[blocking] 2048^2 K={K}: F {F:.17e} vs {F_ref:.17e}", flush=True)
         assert F == F_ref, (K, F, F_ref)
         assert np.array_equal(grad, g_ref), K
+
+
+def solve_3d(gpu, w, rho, K, blocking):
+    """Forward (objective, gap DFT, final state) and adjoint (gradient) of one
+    3D context created with the two-step pass on or off."""
+    import os
+    old = os.environ.get("FDTD_TEMPORAL_BLOCKING")
+    os.environ["FDTD_TEMPORAL_BLOCKING"] = "1" if blocking else "0"
+    try:
+        g = gpu.FDTD(w, ckpt_every=K)
+    finally:
+        if old is None:
+            del os.environ["FDTD_TEMPORAL_BLOCKING"]
+        else:
+            os.environ["FDTD_TEMPORAL_BLOCKING"] = old
+    g.set_density(rho.astype(g.dtype))
+    F = g.forward()
+    d = g.dft()
+    st = g.get_state()
+    g.adjoint()
+    grad = g.gradient()
+    g.close()
+    return F, d, st, grad
+
+
+@pytest.mark.parametrize("n_steps,K", [(1201, 0), (1200, 0), (1201, 300), (1200, 7)])
+def test_3d_two_step_bit_identical_to_per_step(gpu, n_steps, K):
+    """The 256^3 workload's grid in FP32 with the 3D two-step pass switched
+    on (765 super-chunks of 60 x 16 x 8 nodes, 35% of the nodes, advance two
+    steps per pass, on a stream of their own beside the first per-step
+    update): objective, gap DFT, the whole final state and the gradient equal
+    those of the per-step schedule (the 3D default) to the last bit -- odd
+    and even step counts, with and without checkpoint segments (segment
+    edges at odd steps, re-runs on the second state)."""
+    import fdtd_workloads as W
+    w = W.with_(W.c3(), n_steps=n_steps)
+    rho = W.seeded_rho(w, 1)
+    print(f"[blocking3d] 256^3 fp32 N={n_steps} K={K}: per-step reference", flush=True)
+    F0, d0, s0, g0 = solve_3d(gpu, w, rho, K, False)
+    print(f"[blocking3d] 256^3 fp32 N={n_steps} K={K}: two-step", flush=True)
+    F1, d1, s1, g1 = solve_3d(gpu, w, rho, K, True)
+    print(f"   F {F1:.9e} vs {F0:.9e}; max|state| {np.abs(s0).max():.3e}", flush=True)
+    assert F0 > 0 and np.abs(g0).max() > 0 and np.abs(s0).max() > 0
+    assert F1 == F0
+    assert np.array_equal(d1, d0)
+    assert np.array_equal(s1, s0)
+    assert np.array_equal(g1, g0)

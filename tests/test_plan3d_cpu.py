@@ -1,8 +1,10 @@
 """The 3D work lists (host code of the HIP library, built here for the CPU
 host): every tile-chunk with a general plane is in exactly one of the three
 general launches, with the absorber axes and design code it needs, and the
-plain launch's box covers every plain tile-plane.  The C3 geometry, a small
-one, one without absorber and one with ragged tiles and chunks."""
+plain launch's box covers every plain tile-plane; the two-step super-chunks
+keep to plain background with three nodes to spare and store every node the
+per-step launches read from them.  The 256^3 geometry, a small one, one
+without absorber and one with ragged tiles and chunks."""
 import os
 import shutil
 import subprocess
@@ -46,3 +48,7 @@ def test_plan3d_lists(exe, case):
     assert general > 0
     if case in AXD:
         assert int(fields[fields.index("axD") + 1]) == AXD[case]
+    assert int(fields[fields.index("super-bad") + 1]) == 0
+    if case == "c3":
+        # about a third of the 256^3 grid advances two steps per pass
+        assert int(fields[fields.index("super-nodes") + 1]) > 0.3 * 256 ** 3
