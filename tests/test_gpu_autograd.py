@@ -21,7 +21,7 @@ def tg():
     return torch, A
 
 
-def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3):
+def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3, bar=1e-6, verbose=False):
     torch, A = tg
     s = A.Solver(w, ckpt_every=ckpt_every)
     rho0 = W.seeded_rho(w, 0)
@@ -42,8 +42,10 @@ def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3):
         fd = (vals[0] - vals[1]) / (2 * h)
         err = abs(g[idx] - fd) / max(abs(fd), 1e-3 * np.abs(g).max())
         worst = max(worst, err)
+        if verbose:
+            say(f"   cell {idx}: adjoint {g[idx]:.9e} central difference {fd:.9e} rel err {err:.2e}")
     say(f"[autograd] {w['name']} K={ckpt_every}: F={F.item():.9e} worst FD rel err={worst:.2e}")
-    assert worst <= 1e-6
+    assert worst <= bar
     return F.item(), g
 
 
@@ -56,6 +58,16 @@ def test_tiny2d_autograd_matches_fd_and_oracle(tg, oracle_mod):
 
 def test_medium3d_autograd_checkpointed_matches_fd(tg):
     fd_check(tg, W.medium3d(precision=64), 100)
+
+
+def test_c3_full_autograd_checkpointed_matches_fd(tg):
+    """The 256^3 x 8000-step workload in the FP64 build, checkpoint every 500
+    steps: the autograd gradient against central differences (h = 1e-4) on 20
+    random design cells, at the bar of the smaller cases (1e-6; the paper
+    reports better than four digits for its own adjoint, Sec. 3.2).  Observed:
+    5e-9 at worst, the FP64 rounding of F (~1e-13 of F, over 2h) in the
+    differences of the cells with small gradients."""
+    fd_check(tg, W.with_(W.c3(), precision=64), 500, verbose=True)
 
 
 def test_backward_after_an_intervening_forward(tg):

@@ -86,8 +86,10 @@ def test_c2_full_fp32_against_oracle(gpu):
 
 
 def test_c3_full_fp64_against_oracle(gpu):
+    """Observed: F 1.1e-13, DFT 6.0e-14, gradient 1.6e-13 (max-abs 1.5e-13)."""
     run_case(gpu, "c3", 64, 1e-11, 1e-11)
 
 
 def test_c3_full_fp32_against_oracle(gpu):
+    """Observed: F 5.7e-8, DFT 5.9e-7, gradient 4.2e-7 (max-abs 3.2e-7)."""
     run_case(gpu, "c3", 32, 1e-4, 1e-3)
