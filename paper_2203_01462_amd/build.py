@@ -39,7 +39,9 @@ def build(verbose=False, jobs=4):
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
     tmp = LIB_PATH + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    # roctx: named ranges over the entry points for rocprofv3 --marker-trace
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -12,6 +12,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fdtd_2d.hpp"
 #include "fdtd_3d.hpp"
 
@@ -94,6 +96,15 @@ constexpr int kWatchEvery = 1024;
 constexpr double kWatchFactor = 1e10;
 
 Error einval(const std::string &m) { return Error{FDTD_EINVAL, m}; }
+
+// A roctx range over one entry point (host time of the call; visible to
+// rocprofv3 --marker-trace, free when no tool is attached).
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 bool box_inside(int lo, int n, int a, int b) { return n >= 1 && lo >= a && lo + n - 1 <= b; }
 
@@ -1401,6 +1412,7 @@ int32_t fdtd_abi_version(void) { return FDTD_ABI_VERSION; }
 const char *fdtd_last_error(const fdtd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
+  Range range("fdtd_create");
   if (!out) { g_create_error = "null out pointer"; return FDTD_EINVAL; }
   *out = nullptr;
   if (!cfg) { g_create_error = "null config"; return FDTD_EINVAL; }
@@ -1508,6 +1520,7 @@ fdtd_status fdtd_set_density(fdtd_ctx *ctx, const void *rho, int64_t count, int3
 
 fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
   if (!ctx) return FDTD_EINVAL;
+  Range range("fdtd_forward");
   return guard(ctx, [&] {
     fwd_prepare(ctx);
     const double limit = watch_limit(ctx);
@@ -1528,6 +1541,7 @@ fdtd_status fdtd_forward(fdtd_ctx *ctx, double *objective_out) {
 
 fdtd_status fdtd_adjoint(fdtd_ctx *ctx) {
   if (!ctx) return FDTD_EINVAL;
+  Range range("fdtd_adjoint");
   return guard(ctx, [&] {
     adj_prepare(ctx);
     if (ctx->prec == 32) run_adjoint<float>(ctx); else run_adjoint<double>(ctx);
@@ -1538,6 +1552,7 @@ fdtd_status fdtd_adjoint(fdtd_ctx *ctx) {
 
 fdtd_status fdtd_gradient(fdtd_ctx *ctx, void *grad_out, int64_t count, int32_t on_device) {
   if (!ctx) return FDTD_EINVAL;
+  Range range("fdtd_gradient");
   return guard(ctx, [&] {
     if (ctx->state < 3) throw Error{FDTD_ESTATE, "gradient before adjoint"};
     if (!grad_out) throw einval("null gradient buffer");
@@ -1655,6 +1670,7 @@ fdtd_status fdtd_batch_set_density(fdtd_batch *b, int32_t index, const void *rho
 
 fdtd_status fdtd_batch_forward(fdtd_batch *b, double *objectives_out) {
   if (!b) return FDTD_EINVAL;
+  Range range("fdtd_batch_forward");
   return bguard(b, [&] {
     for (fdtd_ctx *c : b->inst) fwd_prepare(c);
     if (b->prec == 32) batch_run<float>(b, false); else batch_run<double>(b, false);
@@ -1678,6 +1694,7 @@ fdtd_status fdtd_batch_forward(fdtd_batch *b, double *objectives_out) {
 
 fdtd_status fdtd_batch_adjoint(fdtd_batch *b) {
   if (!b) return FDTD_EINVAL;
+  Range range("fdtd_batch_adjoint");
   return bguard(b, [&] {
     for (fdtd_ctx *c : b->inst) adj_prepare(c);
     if (b->prec == 32) batch_run<float>(b, true); else batch_run<double>(b, true);

@@ -46,6 +46,19 @@ def test_library_exports_every_declared_symbol(lib):
     assert L.fdtd_abi_version() == ver == lib.fdtd.ABI_VERSION
 
 
+def test_entry_points_carry_roctx_ranges(lib):
+    """The library pushes and pops named roctx ranges over its entry points
+    (rocprofv3 --marker-trace shows fdtd_create / forward / adjoint /
+    gradient and the batch solves)."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    und = subprocess.run(["nm", "-D", "--undefined-only", lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    assert "roctxRangePushA" in und and "roctxRangePop" in und
+
+
 def test_binding_struct_layout_matches_the_header(tmp_path):
     """The ctypes mirrors of fdtd_config / fdtd_timing / fdtd_batch_options
     have the C layout (sizes and every field offset, from a C program
