@@ -115,10 +115,44 @@ def stats(x, g=None, xmin=0.0, xmax=1.0):
     return out[0], out[1]
 
 
+def gap_guard_mask(w, axis=None):
+    """Design-box mask (True = held at metal) of the two boxes of the gap's
+    size next to the gap on either side along `axis` (index into (x, y, z);
+    default: the polarization axis in 3D (x), x in 2D), clipped to the design
+    box (Sec. 4.1, 4.3: the regions on either side of the gap, of its size,
+    held at the metal)."""
+    d0, dn, g0, gn = w["design_lo"], w["design_n"], w["gap_lo"], w["gap_n"]
+    dims = w["dims"]
+    axis = 0 if axis is None else axis
+    shape = (dn[2], dn[1], dn[0]) if dims == 3 else (dn[1], dn[0])
+    m = np.zeros(shape, dtype=bool)
+    for side in (-1, 1):
+        lo = [g0[a] - d0[a] for a in range(3)]
+        lo[axis] += side * gn[axis]
+        hi = [lo[a] + gn[a] for a in range(3)]
+        lo = [max(lo[a], 0) for a in range(3)]
+        hi = [min(hi[a], dn[a]) for a in range(3)]
+        if any(hi[a] <= lo[a] for a in range(dims)):
+            continue
+        if dims == 3:
+            m[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+        else:
+            m[lo[1]:hi[1], lo[0]:hi[0]] = True
+    return m
+
+
 def optimize(w, rho0=0.5, max_iter=600, zeta_min=0.005, alphas=(64.0, 1.0, 0.3, 0.1, 0.05),
              gamma_levels=(16.0, 4.0, 1.0), sigma_levels=None, radius=2.5, level_min_iters=12, kkt_drop=0.7,
-             max_inner=40, ckpt_every=0, threshold=0.5, callback=None):
+             max_inner=40, ckpt_every=0, threshold=0.5, callback=None, fixed=None, tie_axis=None):
     """Maximize the objective of workload `w` over the design density.
+
+    `fixed`: boolean mask of the design box (array order) whose cells are
+    held at metal (the filtered density is 1 there and their sensitivities
+    are dropped; see gap_guard_mask).  `tie_axis`: an axis of the design
+    array (3D: 0 = z) along which the design is uniform (a planar structure,
+    Sec. 4.3): the variables live on the other axes, the filter acts there,
+    the density is the extrusion of the filtered variables, and the gradient
+    of a filtered variable is the sum of its cells' gradients.
 
     Level i uses filter nonlinearity alphas[min(i, .)] and damping
     gamma_levels[min(i, .)] (collision-rate multiplier) and, if given,
@@ -136,13 +170,13 @@ def optimize(w, rho0=0.5, max_iter=600, zeta_min=0.005, alphas=(64.0, 1.0, 0.3, 
     work.wait_stream(caller)
     with torch.cuda.stream(work):
         res = _optimize(w, rho0, max_iter, zeta_min, alphas, gamma_levels, sigma_levels, radius, level_min_iters,
-                        kkt_drop, max_inner, ckpt_every, threshold, callback, dev)
+                        kkt_drop, max_inner, ckpt_every, threshold, callback, dev, fixed, tie_axis)
     caller.wait_stream(work)
     return res
 
 
 def _optimize(w, rho0, max_iter, zeta_min, alphas, gamma_levels, sigma_levels, radius, level_min_iters, kkt_drop,
-              max_inner, ckpt_every, threshold, callback, dev):
+              max_inner, ckpt_every, threshold, callback, dev, fixed=None, tie_axis=None):
     dtype = torch.float32 if w["precision"] == 32 else torch.float64
     nlev = max(len(alphas), len(gamma_levels), len(sigma_levels or [0]))
 
@@ -166,28 +200,61 @@ def _optimize(w, rho0, max_iter, zeta_min, alphas, gamma_levels, sigma_levels, r
 
     dnx, dny, dnz = w["design_n"]
     shape = (dnz, dny, dnx) if w["dims"] == 3 else (dny, dnx)
-    x = torch.full(shape, float(rho0), dtype=dtype, device=dev) if np.isscalar(rho0) else \
-        torch.as_tensor(rho0, dtype=dtype, device=dev).reshape(shape).contiguous()
-    filt = Filter(shape, radius, dtype)
+    if tie_axis is not None and not 0 <= tie_axis < len(shape):
+        raise ValueError(f"tie_axis {tie_axis} outside the design array's {len(shape)} axes")
+    vshape = shape if tie_axis is None else tuple(n for a, n in enumerate(shape) if a != tie_axis)
+    if np.isscalar(rho0):
+        x = torch.full(vshape, float(rho0), dtype=dtype, device=dev)
+    else:
+        x = torch.as_tensor(rho0, dtype=dtype, device=dev)
+        x = (x.reshape(shape).mean(dim=tie_axis) if tie_axis is not None else x.reshape(shape)).contiguous()
+    fmask = None
+    if fixed is not None:
+        fmask = torch.as_tensor(np.asarray(fixed, dtype=bool), device=dev).reshape(shape)
+    filt = Filter(vshape, radius, dtype)
     mma = MMA(x.numel(), dtype)
-    rt = torch.empty_like(x)
-    gt = torch.empty_like(x)
+    rt = torch.empty(shape, dtype=dtype, device=dev)   # the density over the design box
+    gt = torch.empty_like(rt)
+    rv = torch.empty_like(x)                          # filtered variables and their gradient (tied)
+    gv = torch.empty_like(x)
     df0 = torch.empty_like(x)
     xnew = torch.empty_like(x)
+
+    def extrude(v, out):
+        out.copy_(v.unsqueeze(tie_axis).expand(shape))
+        return out
     history = []
     level, it_level, kkt_ref = 0, 0, None
     F_ref = None
     alpha, g_mult, s_max = level_params(0)
     sol = solver(g_mult, s_max)
 
+    def density(xv, a):
+        if tie_axis is None:
+            filt.apply(xv, a, out=rt)
+        else:
+            extrude(filt.apply(xv, a, out=rv), rt)
+        if fmask is not None:
+            rt.masked_fill_(fmask, 1.0)
+        return rt
+
+    def sensitivity():
+        """dF/d(variables) from dF/drho_f in gt (eq. (27); fixed cells drop out)."""
+        if fmask is not None:
+            gt.masked_fill_(fmask, 0.0)
+        if tie_axis is None:
+            filt.transpose(gt, out=df0)
+        else:
+            torch.sum(gt, dim=tie_axis, out=gv)
+            filt.transpose(gv, out=df0)
+
     def evaluate(xv, grad):
-        filt.apply(xv, alpha, out=rt)
-        sol.set_density(rt)
+        sol.set_density(density(xv, alpha))
         F = sol.forward()
         if grad:
             sol.adjoint()
             sol.gradient(out=gt)
-            filt.transpose(gt, out=df0)
+            sensitivity()
         return F
 
     F = evaluate(x, True)
@@ -244,10 +311,10 @@ def _optimize(w, rho0, max_iter, zeta_min, alphas, gamma_levels, sigma_levels, r
         # the forward at x is in the solver: adjoint and gradient only
         sol.adjoint()
         sol.gradient(out=gt)
-        filt.transpose(gt, out=df0)
+        sensitivity()
         F = Fn
         it += 1
-    rho_f = filt.apply(x, alpha)
+    rho_f = density(x, alpha).clone()
     rho_b = (rho_f >= threshold).to(dtype)
     final = solver(1.0, 0.0)
     final.set_density(rho_b)
@@ -256,5 +323,6 @@ def _optimize(w, rho0, max_iter, zeta_min, alphas, gamma_levels, sigma_levels, r
         s.close()
     filt.close()
     mma.close()
-    return dict(x=x, rho_filtered=rho_f, rho_binary=rho_b, F_final=F_final, iterations=it, zeta=zeta,
+    xs = x if tie_axis is None else extrude(x, torch.empty_like(rt))
+    return dict(x=xs, variables=x, rho_filtered=rho_f, rho_binary=rho_b, F_final=F_final, iterations=it, zeta=zeta,
                 history=history)

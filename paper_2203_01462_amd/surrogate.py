@@ -17,9 +17,11 @@ network layers; this module moves tensors and holds the control flow):
    is accepted; otherwise one exact GCMMA step is taken from the checked
    design.  Every checked design is added to the training set and the network
    is tuned on it for a few steps.
-4. ``plain``: the design loop alone (design.optimize at the same filter
-   nonlinearity and physics) as the reference; ``compare`` reports the
-   wall-clock time both take to reach within 1% of the plain run's best F.
+4. ``plain``: the design loop alone (design.optimize with damping
+   continuation and the grayness stop) as the reference; ``compare`` reports
+   the wall-clock time both take to reach within 1% of the plain optimizer's
+   converged objective, and the offline cost (data and training) with the
+   number of designs over which it pays back.
 """
 from __future__ import annotations
 
@@ -239,24 +241,33 @@ class _ExactBatch:
         self.filt.close()
 
 
-def plain(w, alpha=1.0, radius=2.5, max_iter=60, max_inner=40):
-    """The design loop alone at one level; returns [(t, F)] per outer iteration."""
+def plain(w, alpha=1.0, radius=2.5, max_iter=600, max_inner=40, gamma_levels=None, zeta_min=0.005):
+    """The design loop alone: damping continuation over `gamma_levels`
+    (collision-rate multipliers, the last one the workload's own; None: the
+    workload's only) at filter nonlinearity `alpha`, stopped at grayness
+    zeta < zeta_min or max_iter iterations.  Returns [(t, F, level)] per outer
+    iteration (F at that level's damping) and design.optimize's result."""
     trace = []
+    levels = tuple(gamma_levels) if gamma_levels else (w["gamma_mult"],)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
 
     def cb(h):
-        trace.append((time.perf_counter() - t0, h["F"]))
+        trace.append((time.perf_counter() - t0, h["F"], h["level"]))
 
-    res = design.optimize(w, alphas=(alpha,), gamma_levels=(w["gamma_mult"],), max_iter=max_iter, zeta_min=0.0,
+    res = design.optimize(w, alphas=(alpha,), gamma_levels=levels, max_iter=max_iter, zeta_min=zeta_min,
                           radius=radius, max_inner=max_inner, callback=cb)
+    torch.cuda.synchronize()
+    res["seconds"] = time.perf_counter() - t0
+    res["levels"] = levels
     return trace, res
 
 
 def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tune_steps=2, tune_batch=8,
-           tune_lr=2e-4, max_inner=40, log=None):
+           tune_lr=2e-4, max_inner=40, target=None, log=None):
     """Surrogate-guided loop; returns [(t, F of the current design)] per FDTD
-    check and counters.
+    check and counters.  Stops after `checks` checks, or once F reaches
+    `target`.
 
     A proposal: `inner` MMA steps (move limit `move`) on the surrogate, whose
     log F and log-derivative are shifted by the exact-minus-predicted
@@ -326,7 +337,7 @@ def guided(w, net, data, alpha=1.0, radius=2.5, checks=30, inner=4, move=0.2, tu
         ms.close()
         return out, kbest
 
-    while stats["checks"] < checks:
+    while stats["checks"] < checks and not (target is not None and F >= target):
         ta = time.perf_counter()
         lf0, S0 = predict(x)
         dlf = math.log(F) - lf0          # value shift
@@ -431,16 +442,26 @@ def _from_first(trace):
     """Times relative to the first point (the evaluation of the start design),
     so that context set-up is not counted for either loop."""
     t0 = trace[0][0]
-    return [(t - t0, F) for t, F in trace]
+    return [(r[0] - t0,) + tuple(r[1:]) for r in trace]
 
 
-def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60, checks=30, inner=4, seed=0,
-            n_steps=5000, w=None, settings=((0.2, 2),), log=print):
-    """Plain loop vs surrogate-guided loop from the same start design; one
-    guided run per (move limit, tuning steps[, inner steps]) in `settings`."""
+def compare(samples=20000, train_steps=8000, batch=32, alpha=1.0, checks=200, inner=10, seed=1, n_steps=5000,
+            w=None, settings=((0.2, 2),), gamma_levels=(16.0, 4.0, 1.0), zeta_min=0.005, plain_max_iter=600,
+            log=print):
+    """Plain optimizer vs surrogate-guided loop from the same start design.
+
+    Offline: `samples` triples from seeded random designs (batched solves),
+    `train_steps` Adam steps.  Reference: the plain optimizer with damping
+    continuation over `gamma_levels` and the grayness stop (zeta < zeta_min
+    or `plain_max_iter` iterations); its converged objective F* is its final
+    design's F at the workload's physics, and the target is 0.99 F*.  The
+    plain time to target is the first iterate of its last level at or above
+    the target.  One guided run per (move limit, tuning steps[, inner steps])
+    in `settings`, each stopped at the target or after `checks` checks."""
     w = W.c5(n_steps) if w is None else w
     out = dict(workload=w["name"], samples=samples, train_steps=train_steps, batch=batch, alpha=alpha,
-               inner=inner, n_steps=n_steps)
+               inner=inner, n_steps=n_steps, seed=seed, gamma_levels=list(gamma_levels), zeta_min=zeta_min,
+               plain_max_iter=plain_max_iter)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         t = time.perf_counter()
@@ -453,17 +474,28 @@ def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60,
         val = torch.arange(samples - nval, samples, device="cuda")
         net = UNet(W.design_shape(w)[0], batch, seed=seed, stream=None)
         t = time.perf_counter()
-        out["train_hist"] = train(net, data, train_steps, val=val, log=log)
+        out["train_hist"] = train(net, data, train_steps, val=val, log=log, seed=seed)
         out["train_s"] = time.perf_counter() - t
+        out["offline_s"] = out["generate_s"] + out["train_s"]
         out["val"] = evaluate_net(net, data, val)
         log(f"validation: {out['val']}")
-        ptrace, pres = plain(w, alpha=alpha, max_iter=plain_iters)
+        ptrace, pres = plain(w, alpha=alpha, max_iter=plain_max_iter, gamma_levels=gamma_levels,
+                             zeta_min=zeta_min)
         ptrace = _from_first(ptrace)
-        Fbest = max(F for _, F in ptrace)
-        target = 0.99 * Fbest
-        log(f"plain: best F {Fbest:.6g} after {len(ptrace) - 1} iterations, {ptrace[-1][0]:.2f} s")
-        out.update(plain_trace=ptrace, plain_best=Fbest, target=target, plain_time_to_target=time_to(ptrace, target),
-                   plain_iters_to_target=next(i for i, (_, F) in enumerate(ptrace) if F >= target))
+        ex = _Exact(w, alpha, 2.5)
+        Fconv = ex(pres["x"], grad=False)
+        ex.close()
+        target = 0.99 * Fconv
+        last = len(pres["levels"]) - 1
+        hit = [t for t, F, lv in ptrace if lv == last and F >= target]
+        out.update(plain_trace=ptrace, plain_converged_F=Fconv, target=target, plain_iterations=pres["iterations"],
+                   plain_zeta=pres["zeta"], plain_seconds=ptrace[-1][0],
+                   plain_reached_last_level=any(lv == last for _, _, lv in ptrace),
+                   plain_time_to_target=hit[0] if hit else ptrace[-1][0],
+                   plain_iters_to_target=next((i for i, (_, F, lv) in enumerate(ptrace) if lv == last and F >= target),
+                                              len(ptrace) - 1))
+        log(f"plain: converged F {Fconv:.6g} after {pres['iterations']} iterations, zeta {pres['zeta']:.4f}, "
+            f"{out['plain_seconds']:.2f} s; time to 99%: {out['plain_time_to_target']:.2f} s")
         # every setting starts from the same trained network and dataset
         saved = (net.p.clone(), net.m.clone(), net.v.clone(), net.t, data.n)
         runs = []
@@ -476,14 +508,18 @@ def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60,
             net.t, data.n = saved[3], saved[4]
             net.load(net.p)
             gtrace, gstats = guided(w, net, data, alpha=alpha, checks=checks, inner=inn, move=mv, tune_steps=tune,
-                                    log=log)
+                                    target=target, log=log)
             gtrace = _from_first(gtrace)
-            hit = [i for i, (_, F) in enumerate(gtrace) if F >= target]
-            runs.append(dict(move=mv, tune_steps=tune, inner=inn, trace=gtrace, stats=gstats,
-                             time_to_target=time_to(gtrace, target), checks_to_target=hit[0] if hit else None,
-                             best=max(F for _, F in gtrace)))
-            log(f"guided move {mv} tune {tune} inner {inn}: time to target {runs[-1]['time_to_target']}, "
-                f"plain {out['plain_time_to_target']}")
+            tt = time_to(gtrace, target)
+            hitg = [i for i, (_, F) in enumerate(gtrace) if F >= target]
+            saved_s = out["plain_time_to_target"] - tt if tt is not None else None
+            runs.append(dict(move=mv, tune_steps=tune, inner=inn, trace=gtrace, stats=gstats, time_to_target=tt,
+                             checks_to_target=hitg[0] if hitg else None, best=max(F for _, F in gtrace),
+                             speedup=out["plain_time_to_target"] / tt if tt else None,
+                             designs_to_amortize=math.ceil(out["offline_s"] / saved_s) if saved_s and saved_s > 0
+                             else None))
+            log(f"guided move {mv} tune {tune} inner {inn}: time to target {tt}, "
+                f"plain {out['plain_time_to_target']:.2f} s, best F {runs[-1]['best']:.6g}")
     torch.cuda.synchronize()
     out["guided"] = runs
     return out
@@ -491,16 +527,19 @@ def compare(samples=4096, train_steps=3000, batch=32, alpha=1.0, plain_iters=60,
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--samples", type=int, default=20000)
+    ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--alpha", type=float, default=1.0)
-    ap.add_argument("--plain-iters", type=int, default=60)
-    ap.add_argument("--checks", type=int, default=30)
-    ap.add_argument("--inner", type=int, default=4)
+    ap.add_argument("--checks", type=int, default=200)
+    ap.add_argument("--inner", type=int, default=10)
     ap.add_argument("--n-steps", type=int, default=5000)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--settings", default="0.2:2:4",
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--gamma-levels", default="16,4,1",
+                    help="damping continuation of the plain optimizer (collision-rate multipliers)")
+    ap.add_argument("--zeta-min", type=float, default=0.005)
+    ap.add_argument("--plain-max-iter", type=int, default=600)
+    ap.add_argument("--settings", default="0.2:2",
                     help="comma-separated move:tune_steps[:inner] settings; move may be m1/m2/... (one proposal "
                          "per move limit, checked together in one batched solve)")
     ap.add_argument("--out", default=None)
@@ -510,8 +549,9 @@ def main(argv=None):
         f = item.split(":")
         mv = tuple(float(m) for m in f[0].split("/"))
         settings.append((mv if len(mv) > 1 else mv[0], int(f[1])) + ((int(f[2]),) if len(f) > 2 else ()))
-    res = compare(a.samples, a.train_steps, a.batch, a.alpha, a.plain_iters, a.checks, a.inner, a.seed, a.n_steps,
-                  settings=settings, log=lambda m: print(m, flush=True))
+    res = compare(a.samples, a.train_steps, a.batch, a.alpha, a.checks, a.inner, a.seed, a.n_steps,
+                  settings=settings, gamma_levels=tuple(float(g) for g in a.gamma_levels.split(",")),
+                  zeta_min=a.zeta_min, plain_max_iter=a.plain_max_iter, log=lambda m: print(m, flush=True))
     summary = {k: v for k, v in res.items() if not k.endswith("_trace") and k not in ("train_hist", "guided")}
     summary["guided"] = [{k: v for k, v in r.items() if k != "trace"} for r in res["guided"]]
     print(json.dumps(summary), flush=True)

@@ -146,3 +146,28 @@ def test_optimize_small_antenna(D):
     rb = res["rho_binary"].cpu().numpy()
     assert set(np.unique(rb)) <= {0.0, 1.0}
     assert np.isfinite(res["F_final"]) and res["F_final"] > 0
+
+
+def test_optimize_fixed_gap_metal_and_planar_tie(D):
+    """The paper's 3D setting (Sec. 4.3): the metal boxes next to the gap
+    held fixed and the design uniform along the slab's thin axis (z here):
+    every iterate's density is 1 on the fixed cells and constant along z,
+    the variables live on the (y, x) plane, and F rises."""
+    torch, design = D
+    w = W.tiny3d()
+    fixed = design.gap_guard_mask(w)
+    assert fixed.sum() == 2 * 2 * 2 * 2
+    seen = []
+    res = design.optimize(w, max_iter=8, zeta_min=0.0, alphas=(4.0,), gamma_levels=(4.0,), max_inner=20,
+                          fixed=fixed, tie_axis=0, callback=seen.append)
+    h = res["history"]
+    say(f"[design] fixed + tied: F {h[0]['F']:.4e} -> {h[-1]['F']:.4e} over {len(h)} records")
+    assert res["variables"].shape == (w["design_n"][1], w["design_n"][0])
+    rf = res["rho_filtered"].cpu().numpy()
+    assert np.all(rf[fixed] == 1.0)
+    # off the fixed cells every column (y, x) holds one value along z
+    free = np.where(fixed, np.nan, rf)
+    assert np.nanmax(free, axis=0).tolist() == np.nanmin(free, axis=0).tolist()
+    x = res["x"].cpu().numpy()
+    assert np.array_equal(x, np.broadcast_to(x[:1], x.shape))
+    assert h[-1]["F"] > h[0]["F"]
