@@ -241,7 +241,8 @@ class _ExactBatch:
         self.filt.close()
 
 
-def plain(w, alpha=1.0, radius=2.5, max_iter=600, max_inner=40, gamma_levels=None, zeta_min=0.005):
+def plain(w, alpha=1.0, radius=2.5, max_iter=600, max_inner=40, gamma_levels=None, zeta_min=0.005, log=None,
+          log_every=10):
     """The design loop alone: damping continuation over `gamma_levels`
     (collision-rate multipliers, the last one the workload's own; None: the
     workload's only) at filter nonlinearity `alpha`, stopped at grayness
@@ -254,6 +255,9 @@ def plain(w, alpha=1.0, radius=2.5, max_iter=600, max_inner=40, gamma_levels=Non
 
     def cb(h):
         trace.append((time.perf_counter() - t0, h["F"], h["level"]))
+        if log and (h["iter"] % log_every == 0 or len(trace) == 1):
+            log(f"plain: iteration {h['iter']} level {h['level']} F {h['F']:.6g} zeta {h['zeta']:.4f} "
+                f"inner {h.get('inner', 0)} t {trace[-1][0]:.2f} s")
 
     res = design.optimize(w, alphas=(alpha,), gamma_levels=levels, max_iter=max_iter, zeta_min=zeta_min,
                           radius=radius, max_inner=max_inner, callback=cb)
@@ -480,7 +484,7 @@ def compare(samples=20000, train_steps=8000, batch=32, alpha=1.0, checks=200, in
         out["val"] = evaluate_net(net, data, val)
         log(f"validation: {out['val']}")
         ptrace, pres = plain(w, alpha=alpha, max_iter=plain_max_iter, gamma_levels=gamma_levels,
-                             zeta_min=zeta_min)
+                             zeta_min=zeta_min, log=log)
         ptrace = _from_first(ptrace)
         ex = _Exact(w, alpha, 2.5)
         Fconv = ex(pres["x"], grad=False)
