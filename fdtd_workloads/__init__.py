@@ -136,6 +136,46 @@ def tiny3d(**over):
     return w
 
 
+def tiny_te(**over):
+    """Small 2D TEz case (E in the plane, along x; H along z; plane wave along
+    +y), the paper's plasmonic 2D polarization, with every feature: CPML,
+    plane wave, Drude design edges, gap."""
+    w = tiny2d(name="te2d_tiny", pol_axis="x")
+    w.update(over)
+    return w
+
+
+def medium_te(**over):
+    """384x384 TEz FP32 case with the 2048^2 workload's physics (dx = 2 nm,
+    16-cell CPML, K = 16) and a 96x96 design box around a 6x6 gap, run long
+    enough for the pulse to reach the gap; sized for the oracle."""
+    w = dict(_COMMON)
+    w.update(name="te2d_384_fp32", dims=2, precision=32, n=(384, 384, 1), dx=2e-9,
+             n_steps=2400, pml_cells=16, tfsf_margin=6, t0_over_tau=3.0,
+             design_lo=(144, 144, 0), design_n=(96, 96, 1),
+             gap_lo=(189, 189, 0), gap_n=(6, 6, 1),
+             lambda_lo=500e-9, lambda_hi=1000e-9, n_freq=16, pol_axis="x")
+    w.update(over)
+    return w
+
+
+def te_edges(design_n, gap_n=(0, 0)):
+    """Edge counts of the TEz design layout: a box of nx x ny cells holds
+    nx (ny + 1) E_x edges and (nx + 1) ny E_y edges, both boundary lines
+    included; returns (E_x edges, all edges, edges that are not in a gap box
+    of gap_n cells lying inside it)."""
+    nx, ny = design_n[0], design_n[1]
+    gx, gy = gap_n[0], gap_n[1]
+    ndx = nx * (ny + 1)
+    nd = ndx + (nx + 1) * ny
+    ng = gx * (gy + 1) + (gx + 1) * gy if gx > 0 and gy > 0 else 0
+    return ndx, nd, nd - ng
+
+
+def is_te(w):
+    return w["dims"] == 2 and w.get("pol_axis") == "x"
+
+
 def instance2d(side, gamma_mult, lambda_lo, lambda_hi, n_steps, precision=32, n_freq=8, name=None):
     """One square 2D TMz instance with the 2048^2 workload's physics (dx = 2 nm,
     eps_s = 2.25, Drude metal), scaled to its side: 16-cell CPML, a centred
@@ -219,8 +259,11 @@ def with_(w, **over):
 
 
 def design_shape(w):
-    """Array shape of the density over the design box: [z][y][x] in 3D, [y][x] in 2D."""
+    """Array shape of the density over the design box: [z][y][x] in 3D, [y][x] in 2D
+    TMz; in 2D TEz one value per design edge (E_x edges, then E_y edges)."""
     nx, ny, nz = w["design_n"]
+    if is_te(w):
+        return (te_edges(w["design_n"])[1],)
     return (nz, ny, nx) if w["dims"] == 3 else (ny, nx)
 
 
@@ -249,6 +292,15 @@ def seeded_rho(w, seed, kind="smooth"):
           "zero"/"one" constant fields.
     """
     shape = design_shape(w)
+    if is_te(w) and kind in ("smooth", "binary"):
+        # the E_x block ([ny+1][nx]) and the E_y block ([ny][nx+1]), each drawn
+        # and smoothed as a 2D field
+        nx, ny, _ = w["design_n"]
+        rng = np.random.default_rng(seed)
+        bx = np.clip(box_smooth(rng.random((ny + 1, nx))), 0.0, 1.0)
+        by = np.clip(box_smooth(rng.random((ny, nx + 1))), 0.0, 1.0)
+        r = np.concatenate([bx.ravel(), by.ravel()])
+        return (r >= 0.5).astype(np.float64) if kind == "binary" else r
     if kind == "half":
         return np.full(shape, 0.5)
     if kind == "zero":

@@ -5,8 +5,8 @@ of the benchmark are the only callers.  The product path (the HIP library and
 its binding) never imports this package, and this package imports nothing
 from the product path.
 
-The C sources (``fdtd2d.c``, ``fdtd3d.c``) state which passage of the paper
-each step follows.  ``build()`` compiles them into ``liboracle_fdtd.so`` with
+The C sources (``fdtd2d.c``: 2D TMz; ``fdtd2d_te.c``: 2D TEz, E in the
+plane; ``fdtd3d.c``) state which passage of the paper each step follows.  ``build()`` compiles them into ``liboracle_fdtd.so`` with
 gcc, ``-O2 -ffp-contract=off``, OpenMP over the outer spatial loop.
 """
 from __future__ import annotations
@@ -19,7 +19,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle_fdtd.so")
-SOURCES = ["fdtd2d.c", "fdtd3d.c"]
+SOURCES = ["fdtd2d.c", "fdtd2d_te.c", "fdtd3d.c"]
 
 C0 = 299792458.0
 
@@ -73,7 +73,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)
-        for pre in ("or2d", "or3d"):
+        for pre in ("or2d", "orte", "or3d"):
             if not hasattr(L, pre + "_create"):
                 continue
             getattr(L, pre + "_create").argtypes = [C.POINTER(_Cfg), C.POINTER(P)]
@@ -92,13 +92,18 @@ def lib():
             getattr(L, pre + "_forward_ext").argtypes = [P, dp, dp]
             getattr(L, pre + "_adjoint_ext").argtypes = [P, dp, dp]
             getattr(L, pre + "_step_free").argtypes = [P, C.c_int]
-            getattr(L, pre + "_incident_column").argtypes = [P, C.c_int, dp]
-            getattr(L, pre + "_set_checkpoint").argtypes = [P, C.c_int]
+            if pre != "orte":
+                getattr(L, pre + "_incident_column").argtypes = [P, C.c_int, dp]
+                getattr(L, pre + "_set_checkpoint").argtypes = [P, C.c_int]
         dpa = C.POINTER(dp)
         L.or3d_set_state.argtypes = [P, dpa, dpa, dpa]
         L.or3d_get_state.argtypes = [P, dpa, dpa, dpa]
         L.or2d_set_state.argtypes = [P, dp, dp, dp, dp]
         L.or2d_get_state.argtypes = [P, dp, dp, dp, dp]
+        L.orte_set_state.argtypes = [P, dp, dp, dp, dp, dp]
+        L.orte_get_state.argtypes = [P, dp, dp, dp, dp, dp]
+        L.orte_sizes.argtypes = [P, C.POINTER(C.c_int32)]
+        L.orte_sizes.restype = None
         L.or2d_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -159,16 +164,22 @@ class OracleError(RuntimeError):
         self.name = ERRORS.get(code, str(code))
 
 
+def is_te(w):
+    """2D with E in the plane (E along x): the TEz oracle."""
+    return w["dims"] == 2 and w.get("pol_axis") == "x"
+
+
 class Oracle:
-    """One problem instance of the CPU oracle (2D TMz or 3D)."""
+    """One problem instance of the CPU oracle (2D TMz, 2D TEz or 3D)."""
 
     def __init__(self, w, ckpt_every=0):
         """ckpt_every = K > 0 keeps K steps of design-edge history plus a
         snapshot of the state every K steps; the adjoint re-runs each segment
-        (same results as the full history, bounded host memory)."""
+        (same results as the full history, bounded host memory; TMz and 3D)."""
         self.w = dict(w)
         self.dims = w["dims"]
-        self.pre = "or2d" if self.dims == 2 else "or3d"
+        self.te = is_te(w)
+        self.pre = "orte" if self.te else "or2d" if self.dims == 2 else "or3d"
         L = lib()
         cfg, keep = make_cfg(w)
         h = C.c_void_p()
@@ -185,7 +196,15 @@ class Oracle:
         dnx, dny, dnz = w["design_n"]
         self.dshape = (dnz, dny, dnx) if self.dims == 3 else (dny, dnx)
         self.N = w["n_steps"]
-        if ckpt_every:
+        if self.te:
+            # per-edge layout: the design box's E_x edges, then its E_y edges
+            sz = (C.c_int32 * 4)()
+            L.orte_sizes(self.h, sz)
+            self.nd, self.ndx, self.ng, self.ngx = tuple(sz)
+            self.dshape = (self.nd,)
+            if ckpt_every:
+                raise OracleError(1, "checkpointing is not built for the TEz oracle")
+        elif ckpt_every:
             self._check(self._fn("set_checkpoint")(self.h, int(ckpt_every)))
 
     def _fn(self, name):
@@ -275,7 +294,12 @@ class Oracle:
         return out
 
     def set_state(self, *fields):
-        """2D: (Ez, Hx, Hy, J).  3D: (E[3], H[3], J[3]) lists of arrays."""
+        """2D TMz: (Ez, Hx, Hy, J).  2D TEz: (Ex, Ey, Hz, Jx, Jy).  3D: (E[3],
+        H[3], J[3]) lists of arrays."""
+        if self.te:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in fields]
+            self._check(lib().orte_set_state(self.h, *[_dp(a) for a in arrs]))
+            return
         if self.dims == 2:
             arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in fields]
             self._check(lib().or2d_set_state(self.h, *[_dp(a) for a in arrs]))
@@ -289,6 +313,10 @@ class Oracle:
         self._check(lib().or3d_set_state(self.h, *ptrs))
 
     def get_state(self):
+        if self.te:
+            arrs = [np.zeros(self.shape) for _ in range(5)]
+            self._check(lib().orte_get_state(self.h, *[_dp(a) for a in arrs]))
+            return arrs
         if self.dims == 2:
             arrs = [np.zeros(self.shape) for _ in range(4)]
             self._check(lib().or2d_get_state(self.h, *[_dp(a) for a in arrs]))
