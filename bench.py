@@ -94,7 +94,7 @@ def algorithmic_bytes(w, adjoint):
         cells = nx * ny
         fields = 3
         pml_cells = 2 * (2 * P) * (nx + ny)  # psi_E and psi_H per strip direction
-        design = dnx * dny
+        design = W.te_edges(w["design_n"])[1] if W.is_te(w) else dnx * dny  # TEz: one value per edge
         ncomp = 1
     else:
         cells = nx * ny * nz
@@ -287,8 +287,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "unet"],
-                    help="c4: 64 uneven 2D instances batched; unet: training steps of the surrogate network "
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "te", "unet"],
+                    help="c4: 64 uneven 2D instances batched; te: 2D TEz (E in the plane) at 2048^2; "
+                         "unet: training steps of the surrogate network "
                          "(BF16 matrix cores) instead of FDTD")
     ap.add_argument("--n-steps", type=int, default=0, help="override the time steps of a solve (testing only)")
     ap.add_argument("--cpu-steps", type=int, default=0,
@@ -378,7 +379,8 @@ def main():
                 # counter-measured HBM bytes per step over the same event time
                 "measured_gbs": round(traffic / step_s / 1e9, 1) if traffic else None,
                 "measured_frac": round(traffic / step_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
-                "kernel": ("step2d_mix_kernel (two launches per two time steps)" if base["dims"] == 2
+                "kernel": ("step_te_fwd / step_te_adj (one launch per time step)" if W.is_te(base)
+                           else "step2d_mix_kernel (two launches per two time steps)" if base["dims"] == 2
                            else "step3d_general x3 + step3d_plain (one time step)"),
                 "bytes_per_step_fwd": bf, "bytes_per_step_adj": ba,
                 "avg_step_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
@@ -400,7 +402,7 @@ def main():
     for c in ctxs:
         c.close()
     if not args.no_cpu:
-        cs = args.cpu_steps or (200 if base["dims"] == 3 else 2000)
+        cs = args.cpu_steps or (200 if base["dims"] == 3 else 1000 if W.is_te(base) else 2000)
         out["cpu_baseline"] = cpu_baseline(base, min(cs, base["n_steps"]))
     print(json.dumps(out), flush=True)
 

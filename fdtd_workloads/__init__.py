@@ -247,8 +247,17 @@ def random_designs(count, shape, seed):
     return out
 
 
+def te2048():
+    """2D TEz FP32 2048x2048 with the 2048^2 TMz workload's physics and boxes
+    (512x512-cell design box: 525,312 design edges; 5x5-cell gap: 60 gap
+    edges), 20000 steps: the in-plane polarization at the benchmark size."""
+    w = c2()
+    w.update(name="te2d_2048_fp32", pol_axis="x")
+    return w
+
+
 PRESETS = {"c1": c1, "c2": c2, "c3": c3, "medium2d": medium2d, "medium3d": medium3d, "tiny2d": tiny2d,
-           "tiny3d": tiny3d, "c5": c5}
+           "tiny3d": tiny3d, "c5": c5, "te": te2048, "tiny_te": tiny_te, "medium_te": medium_te}
 
 
 def with_(w, **over):

@@ -80,16 +80,23 @@ typedef struct fdtd_ctx fdtd_ctx; /* opaque */
 
 typedef struct {
   int32_t abi_version;   /* must be FDTD_ABI_VERSION */
-  int32_t dims;          /* 2 (TMz) or 3 */
+  int32_t dims;          /* 2 (TMz, or TEz with pol_axis = x) or 3 */
   int32_t precision;     /* 32 or 64: field arithmetic and storage; DFT and sensitivity sums are always FP64 */
   int32_t n[3];          /* nodes along x, y, z (n[2] ignored in 2D) */
   int32_t n_steps;       /* N time steps of each solve */
   int32_t pml_cells;     /* CPML thickness (cells) next to each wall */
   int32_t tfsf_margin;   /* cells between the PML and the total-field box */
-  int32_t pol_axis;      /* axis of the incident E: TMz (dims 2) is z; dims 3 is x.  FDTD_AXIS_DEFAULT
-                            (-1) takes that axis; any other axis is EINVAL */
-  int32_t prop_axis;     /* propagation axis of the plane wave (towards +): TMz y, 3D z; -1 default */
-  int32_t design_lo[3], design_n[3]; /* design box, nodes [lo, lo+n) per axis */
+  int32_t pol_axis;      /* axis of the incident E.  dims 2: z selects TMz (E_z, H_x, H_y), x selects
+                            TEz (E_x, E_y, H_z: E in the plane, the paper's plasmonic 2D case,
+                            Sec. 4.1); dims 3: x.  FDTD_AXIS_DEFAULT (-1) takes z in 2D, x in 3D;
+                            any other axis is EINVAL */
+  int32_t prop_axis;     /* propagation axis of the plane wave (towards +): 2D y, 3D z; -1 default */
+  int32_t design_lo[3], design_n[3]; /* design box, nodes [lo, lo+n) per axis.  TEz: a box of
+                            design_n cells whose edges include both boundary lines; the density
+                            holds one value per edge, its E_x edges [ny+1][nx] followed by its
+                            E_y edges [ny][nx+1] (Sec. 3.2: one design variable per Yee edge);
+                            the gap box's edges are plain eps_g, zero gradient, and are the
+                            monitors (E_x edges, then E_y edges); no checkpointing, no batches */
   int32_t gap_lo[3], gap_n[3];       /* gap (observation) box */
   int32_t source_kind;   /* FDTD_SRC_*: Gaussian-modulated carrier, or the paper's Hann-windowed 4-lobe sinc */
   int32_t objective_kind;/* FDTD_OBJ_* */
@@ -140,8 +147,9 @@ int32_t fdtd_abi_version(void);
  * weights).  Fails with EINVAL on: precision not 32/64, dims not 2/3,
  * Courant outside (0, 1/sqrt(dims)), n_steps < 1, n_freq < 1, non-positive
  * permittivities or negative material parameters, ckpt_every < 0, axes other
- * than the defaults, boxes outside the total-field region (with
- * FDTD_SRC_NONE: outside the nodes 1 + pml_cells .. n - 2 - pml_cells);
+ * than the supported ones, ckpt_every > 0 on a TEz context, boxes outside
+ * the total-field region (with FDTD_SRC_NONE: outside the nodes 1 +
+ * pml_cells .. n - 2 - pml_cells; TEz: pml_cells .. n - 1 - pml_cells);
  * ENOMEM if the forward history (and, with ckpt_every > 0, the snapshots)
  * does not fit the budget or the device; EDEVICE without a usable HIP device.
  * *out is NULL on failure. */
@@ -187,8 +195,9 @@ fdtd_status fdtd_get_dft(fdtd_ctx *ctx, double *re_im, int64_t count);
  * of the update itself, eqs. (10a-c)).  Initial state of the following
  * forward solves instead of zero: `state` holds, on the host, count =
  * nf * nx * ny * nz doubles, nf full-grid arrays [z][y][x] in the order
- * E_z, H_x, H_y, J_z (dims 2: nf = 4, z ignored) or E_x, E_y, E_z, H_x, H_y,
- * H_z, J_x, J_y, J_z (dims 3: nf = 9), at the staggered positions of the Yee
+ * E_z, H_x, H_y, J_z (TMz: nf = 4, z ignored), E_x, E_y, H_z, J_x, J_y (TEz:
+ * nf = 5) or E_x, E_y, E_z, H_x, H_y, H_z, J_x, J_y, J_z (dims 3: nf = 9),
+ * at the staggered positions of the Yee
  * cell: E^0 and J^0 at t = 0, H^{-1/2} at t = -dt/2.  Positions the update
  * never writes (E and H on the PEC walls) and J off the Drude design edges
  * are taken as zero; absorber memories start at zero.  The state is copied;

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libfdtd_hip.so")
-SOURCES = ["fdtd_api.hip", "fdtd_setup.hip", "fdtd_2d.hip", "fdtd_3d.hip", "fdtd_design.hip", "fdtd_nn.hip"]
+SOURCES = ["fdtd_api.hip", "fdtd_setup.hip", "fdtd_2d.hip", "fdtd_te.hip", "fdtd_3d.hip", "fdtd_design.hip",
+           "fdtd_nn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -47,6 +47,13 @@ struct Step2D {
 template <typename T>
 void launch_step2d(const Step2D<T> &p, int n, int par, bool adjoint, hipStream_t s, int rows = 0);
 
+// One time step of the 2D TEz solve (E_x, E_y, H_z; fdtd_te.hip) on the
+// same parameter block: ez = E_x, hx = E_y, hy = H_z (copy 0 read, copy 1
+// written), pex / pey = H_z's x / y difference memories, phx = E_x's, phy =
+// E_y's; rho, J, history and sensitivity sums per design edge, ng = gap edges.
+template <typename T>
+void launch_step_te(const Step2D<T> &p, int n, bool adjoint, hipStream_t s);
+
 // Workgroups of one instance's step launch (rows <= 0: the default depth).
 int step2d_blocks(int nx, int ny, int rows);
 

@@ -33,6 +33,7 @@ struct fdtd_ctx {
   int N = 0, K = 0, nd = 0, ng = 0, ncomp = 1, nmon = 0;
   double dt = 0;
   int ia = 0, ib = 0, ja = 0, jb = 0, jref = 0, L = 0;
+  bool te = false;  // 2D TEz (E in the plane along x): fdtd_te.hip, per-edge design variables
   int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
   // device memory: 2D fields (Ez, Hx, Hy) and absorber memories (4), two
   // copies each; 3D: one arena per copy (fields and absorber slabs) and the
@@ -126,11 +127,15 @@ void validate(const fdtd_config &c) {
   if (c.source_kind != FDTD_SRC_GAUSS && c.source_kind != FDTD_SRC_SINC_HANN && c.source_kind != FDTD_SRC_NONE)
     throw einval("unknown source_kind");
   // the update kernels inject the plane wave with E along z travelling +y
-  // (TMz) or E along x travelling +z (3D)
-  const int pol = c.dims == 2 ? FDTD_AXIS_Z : FDTD_AXIS_X, prop = c.dims == 2 ? FDTD_AXIS_Y : FDTD_AXIS_Z;
+  // (TMz), E along x travelling +y (TEz, pol_axis = x in 2D) or E along x
+  // travelling +z (3D)
+  const bool te2 = c.dims == 2 && c.pol_axis == FDTD_AXIS_X;
+  const int pol = c.dims == 2 ? (te2 ? FDTD_AXIS_X : FDTD_AXIS_Z) : FDTD_AXIS_X;
+  const int prop = c.dims == 2 ? FDTD_AXIS_Y : FDTD_AXIS_Z;
   if ((c.pol_axis != FDTD_AXIS_DEFAULT && c.pol_axis != pol) || (c.prop_axis != FDTD_AXIS_DEFAULT && c.prop_axis != prop))
-    throw einval(c.dims == 2 ? "TMz runs with pol_axis = z and prop_axis = y (or -1)"
+    throw einval(c.dims == 2 ? "2D runs with pol_axis = z (TMz) or x (TEz) and prop_axis = y (or -1)"
                              : "3D runs with pol_axis = x and prop_axis = z (or -1)");
+  if (te2 && c.ckpt_every > 0) throw einval("checkpointing is not built for TEz contexts");
   if (c.objective_kind != FDTD_OBJ_DFT && c.objective_kind != FDTD_OBJ_TIME_ENERGY) throw einval("unknown objective_kind");
   if (c.weight_kind != FDTD_W_ENHANCEMENT && c.weight_kind != FDTD_W_UNIT) throw einval("unknown weight_kind");
   if (!(c.f_hi > c.f_lo) || !(c.f_lo > 0)) throw einval("band edges must satisfy 0 < f_lo < f_hi");
@@ -242,15 +247,35 @@ void create_2d(fdtd_ctx *c) {
     throw einval("total-field box does not fit inside the absorber");
   // boxes: strictly inside the total-field box, or without a plane wave
   // anywhere off the absorber and the walls
-  const int xa = tf ? c->ia + 1 : P + 1, xb = tf ? c->ib - 1 : c->nx - 2 - P;
-  const int ya = tf ? c->ja + 1 : P + 1, yb = tf ? c->jb - 1 : c->ny - 2 - P;
-  if (!box_inside(g.design_lo[0], g.design_n[0], xa, xb) || !box_inside(g.design_lo[1], g.design_n[1], ya, yb) ||
-      !box_inside(g.gap_lo[0], g.gap_n[0], xa, xb) || !box_inside(g.gap_lo[1], g.gap_n[1], ya, yb))
-    throw einval(tf ? "design/gap boxes must lie strictly inside the total-field box"
-                    : "design/gap boxes must lie inside the absorber and the walls");
+  if (c->te) {
+    // TEz boxes are cells whose edges include both boundary lines: node
+    // ranges [lo, lo + n] strictly inside the total-field box, or without a
+    // plane wave off the absorber (PEC walls allowed)
+    const int xa = tf ? c->ia + 1 : P, xb = tf ? c->ib - 1 : c->nx - 1 - P;
+    const int ya = tf ? c->ja + 1 : P, yb = tf ? c->jb - 1 : c->ny - 1 - P;
+    const bool gap = g.gap_n[0] > 0 && g.gap_n[1] > 0;
+    if (!box_inside(g.design_lo[0], g.design_n[0] + 1, xa, xb) || !box_inside(g.design_lo[1], g.design_n[1] + 1, ya, yb) ||
+        (gap && (!box_inside(g.gap_lo[0], g.gap_n[0] + 1, xa, xb) || !box_inside(g.gap_lo[1], g.gap_n[1] + 1, ya, yb))))
+      throw einval(tf ? "design/gap boxes must lie strictly inside the total-field box"
+                      : "design/gap boxes must lie off the absorber");
+  } else {
+    const int xa = tf ? c->ia + 1 : P + 1, xb = tf ? c->ib - 1 : c->nx - 2 - P;
+    const int ya = tf ? c->ja + 1 : P + 1, yb = tf ? c->jb - 1 : c->ny - 2 - P;
+    if (!box_inside(g.design_lo[0], g.design_n[0], xa, xb) || !box_inside(g.design_lo[1], g.design_n[1], ya, yb) ||
+        !box_inside(g.gap_lo[0], g.gap_n[0], xa, xb) || !box_inside(g.gap_lo[1], g.gap_n[1], ya, yb))
+      throw einval(tf ? "design/gap boxes must lie strictly inside the total-field box"
+                      : "design/gap boxes must lie inside the absorber and the walls");
+  }
   c->pitch = (c->nx + 63) & ~63;
-  c->nd = g.design_n[0] * g.design_n[1];
-  c->ng = g.gap_n[0] * g.gap_n[1];
+  if (c->te) {
+    // per-edge layout: E_x edges [dny+1][dnx], then E_y edges [dny][dnx+1]
+    const int dnx = g.design_n[0], dny = g.design_n[1], gnx = g.gap_n[0], gny = g.gap_n[1];
+    c->nd = dnx * (dny + 1) + (dnx + 1) * dny;
+    c->ng = gnx > 0 && gny > 0 ? gnx * (gny + 1) + (gnx + 1) * gny : 0;
+  } else {
+    c->nd = g.design_n[0] * g.design_n[1];
+    c->ng = g.gap_n[0] * g.gap_n[1];
+  }
   c->ncomp = 1;
   c->nmon = c->ng;
   c->jref = c->ja - 2;
@@ -270,7 +295,7 @@ void create_2d(fdtd_ctx *c) {
   // without a plane wave there are no injection lines to keep clear
   Tb2dPlan pl = tf ? tb2d_plan(c->nx, c->ny, P, c->ia, c->ib, c->ja, c->jb, dbox, gbox)
                    : tb2d_plan(c->nx, c->ny, P, -8, -8, -8, -8, dbox, gbox);
-  if (!pl.tb.empty() && blocking_enabled(2)) {
+  if (!pl.tb.empty() && blocking_enabled(2) && !c->te) {
     // the interior super-tiles run one launch early (beside the rest tiles'
     // second step of the previous pair), the border ones after them
     std::vector<int> order;
@@ -587,14 +612,23 @@ void zero_state(fdtd_ctx *c) {
 }
 
 // ------------------------------------------------ test-only state access
-// Fields of the fdtd_set_state layout: 2D E_z, H_x, H_y, J_z; 3D E_x, E_y,
-// E_z, H_x, H_y, H_z, J_x, J_y, J_z.
-int state_fields(const fdtd_ctx *c) { return c->dims == 2 ? 4 : 9; }
+// Fields of the fdtd_set_state layout: 2D TMz E_z, H_x, H_y, J_z; 2D TEz E_x,
+// E_y, H_z, J_x, J_y; 3D E_x, E_y, E_z, H_x, H_y, H_z, J_x, J_y, J_z.
+int state_fields(const fdtd_ctx *c) { return c->te ? 5 : c->dims == 2 ? 4 : 9; }
+
+// E and H fields of the layout (the rest are currents).
+int state_efields(const fdtd_ctx *c) { return c->dims == 2 ? 3 : 6; }
 
 // Is node (i, j, k) of E/H field f one the update writes (off the PEC walls)?
 bool state_node(const fdtd_ctx *c, int f, int i, int j, int k) {
   const int n3[3] = {c->nx, c->ny, c->nz};
   const int x[3] = {i, j, k};
+  if (c->te) {
+    // E_x: [0, nx-2] x [1, ny-2]; E_y: [1, nx-2] x [0, ny-2]; H_z: [0, nx-2] x [0, ny-2]
+    const bool ix = f == 1 ? i >= 1 && i <= c->nx - 2 : i <= c->nx - 2;
+    const bool jy = f == 0 ? j >= 1 && j <= c->ny - 2 : j <= c->ny - 2;
+    return ix && jy;
+  }
   if (c->dims == 2) {
     const bool ix = f == 2 ? i <= c->nx - 2 : i >= 1 && i <= c->nx - 2;
     const bool jy = f == 1 ? j <= c->ny - 2 : j >= 1 && j <= c->ny - 2;
@@ -614,6 +648,20 @@ bool state_node(const fdtd_ctx *c, int f, int i, int j, int k) {
 // node (i, j, k), or -1 when the node is not a Drude design edge.
 int64_t drude_index(const fdtd_ctx *c, int comp, int i, int j, int k) {
   const fdtd_config &g = c->cfg;
+  if (c->te) {
+    // the edge's density index (E_x block, then E_y block), off the gap's edges
+    const int u = i - g.design_lo[0], v = j - g.design_lo[1], dnx = g.design_n[0], dny = g.design_n[1];
+    const int gu = i - g.gap_lo[0], gv = j - g.gap_lo[1], gnx = g.gap_n[0], gny = g.gap_n[1];
+    const bool gp = gnx > 0 && gny > 0;
+    if (comp == 0) {
+      if (u < 0 || u >= dnx || v < 0 || v > dny) return -1;
+      if (gp && gu >= 0 && gu < gnx && gv >= 0 && gv <= gny) return -1;
+      return (int64_t)v * dnx + u;
+    }
+    if (u < 0 || u > dnx || v < 0 || v >= dny) return -1;
+    if (gp && gu >= 0 && gu <= gnx && gv >= 0 && gv < gny) return -1;
+    return (int64_t)dnx * (dny + 1) + (int64_t)v * (dnx + 1) + u;
+  }
   const int x[3] = {i, j, k};
   int64_t d = 0, stride = 1;
   bool gap = true;
@@ -639,13 +687,13 @@ template <typename T>
 void upload_init_state(fdtd_ctx *c) {
   const size_t cells = (size_t)c->nx * c->ny * c->nz;
   const double *st = c->init_state.data();
-  const int nfe = c->dims == 2 ? 3 : 6;
+  const int nfe = state_efields(c);
   std::vector<T> jv((size_t)c->nd * c->ncomp, T(0));
-  for (int comp = 0; comp < c->ncomp; ++comp)
+  for (int comp = 0; comp < state_fields(c) - nfe; ++comp)
     for (int k = 0; k < c->nz; ++k)
       for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) {
-          const int64_t d = drude_index(c, c->dims == 2 ? 0 : comp, i, j, k);
+          const int64_t d = drude_index(c, c->dims == 2 && !c->te ? 0 : comp, i, j, k);
           if (d >= 0) jv[d] = T(st[(size_t)(nfe + comp) * cells + ((size_t)k * c->ny + j) * c->nx + i]);
         }
   std::vector<std::vector<T>> img(c->dims == 2 ? 3 : 1);
@@ -668,7 +716,7 @@ void upload_init_state(fdtd_ctx *c) {
 template <typename T>
 void download_state(fdtd_ctx *c, double *out) {
   const size_t cells = (size_t)c->nx * c->ny * c->nz;
-  const int nfe = c->dims == 2 ? 3 : 6;
+  const int nfe = state_efields(c);
   std::vector<std::vector<T>> img(c->dims == 2 ? 3 : 1);
   for (size_t b = 0; b < img.size(); ++b) {
     DevBuf *src = c->dims == 2 ? field_buf(c, false, fcopy(c, c->N), (int)b) : &arena(c, false, c->N);
@@ -678,7 +726,7 @@ void download_state(fdtd_ctx *c, double *out) {
   std::vector<T> jv((size_t)c->nd * c->ncomp);
   FDTD_HIP(hipMemcpyAsync(jv.data(), c->J.p, jv.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
   FDTD_HIP(hipStreamSynchronize(c->stream));
-  for (int f = 0; f < nfe + c->ncomp; ++f)
+  for (int f = 0; f < state_fields(c); ++f)
     for (int k = 0; k < c->nz; ++k)
       for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) {
@@ -686,7 +734,7 @@ void download_state(fdtd_ctx *c, double *out) {
           if (f < nfe) {
             if (state_node(c, f, i, j, k)) v = (double)img[c->dims == 2 ? f : 0][state_offset(c, f, i, j, k)];
           } else {
-            const int64_t d = drude_index(c, c->dims == 2 ? 0 : f - nfe, i, j, k);
+            const int64_t d = drude_index(c, c->dims == 2 && !c->te ? 0 : f - nfe, i, j, k);
             if (d >= 0) v = (double)jv[d];
           }
           out[(size_t)f * cells + ((size_t)k * c->ny + j) * c->nx + i] = v;
@@ -741,7 +789,9 @@ Step2D<T> params2d_at(fdtd_ctx *c, bool rerun, int s, int hist_base, bool hist_o
 // (rerun = false) or the re-run state.
 template <typename T>
 void launch_step(fdtd_ctx *c, bool rerun, int n, int s, bool adjoint, int hist_base, bool hist_on, const Lane &ln) {
-  if (c->dims == 2) {
+  if (c->te) {
+    launch_step_te<T>(params2d_at<T>(c, rerun, s, hist_base, hist_on, ln.hist), n, adjoint, ln.s);
+  } else if (c->dims == 2) {
     // a single step updates every tile (the super-tiles take the background
     // update of the per-step kernel)
     launch_step2d<T>(params2d_at<T>(c, rerun, s, hist_base, hist_on, ln.hist), n, 0, adjoint, ln.s);
@@ -885,8 +935,11 @@ struct ForwardWatch {
     if (slots >= c->watch_slots) throw Error{FDTD_EDEVICE, "watchdog: more checks than slots"};
     unsigned long long *slot = c->watch.as<unsigned long long>() + slots;
     if (c->dims == 2) {
-      DevBuf *e = field_buf(c, false, fcopy(c, s), 0);
-      launch_watch(c->stream, c->prec, e->p, e->bytes / c->esz, slot);
+      // TMz: E_z; TEz: E_x and E_y (the two checks share the slot's maximum)
+      for (int k = 0; k < (c->te ? 2 : 1); ++k) {
+        DevBuf *e = field_buf(c, false, fcopy(c, s), k);
+        launch_watch(c->stream, c->prec, e->p, e->bytes / c->esz, slot);
+      }
     } else {
       const char *e = arena(c, false, s).as<char>() + (size_t)c->lay3.G0 * c->esz;
       launch_watch(c->stream, c->prec, e, (size_t)3 * c->lay3.S, slot);
@@ -1427,6 +1480,7 @@ fdtd_status fdtd_create(const fdtd_config *cfg, fdtd_ctx **out) {
     FDTD_HIP(hipGetDevice(&c->device));
     c->cfg = *cfg;
     c->dims = cfg->dims;
+    c->te = cfg->dims == 2 && cfg->pol_axis == FDTD_AXIS_X;
     c->prec = cfg->precision;
     c->esz = c->prec == 32 ? 4 : 8;
     c->nx = cfg->n[0]; c->ny = cfg->n[1]; c->nz = cfg->dims == 3 ? cfg->n[2] : 1;
@@ -1559,11 +1613,15 @@ fdtd_status fdtd_gradient(fdtd_ctx *ctx, void *grad_out, int64_t count, int32_t 
     if (count != (int64_t)ctx->nd) throw einval("gradient count must equal the number of design cells");
     const fdtd_config &g = ctx->cfg;
     void *dst = on_device ? grad_out : ctx->gtmp.p;
-    launch_grad_finalize(ctx->stream, ctx->prec, ctx->grad.as<double>(), ctx->scal.as<double>(), ctx->ncomp,
-                         g.design_n[0], g.design_n[1], ctx->dims == 3 ? g.design_n[2] : 1,
-                         g.gap_lo[0] - g.design_lo[0], g.gap_lo[1] - g.design_lo[1],
-                         ctx->dims == 3 ? g.gap_lo[2] - g.design_lo[2] : 0, g.gap_n[0], g.gap_n[1],
-                         ctx->dims == 3 ? g.gap_n[2] : 1, dst);
+    if (ctx->te)  // one sum per design edge; the gap's edges never accumulate
+      launch_grad_finalize(ctx->stream, ctx->prec, ctx->grad.as<double>(), ctx->scal.as<double>(), 1, ctx->nd, 1, 1,
+                           0, 0, 0, 0, 0, 0, dst);
+    else
+      launch_grad_finalize(ctx->stream, ctx->prec, ctx->grad.as<double>(), ctx->scal.as<double>(), ctx->ncomp,
+                           g.design_n[0], g.design_n[1], ctx->dims == 3 ? g.design_n[2] : 1,
+                           g.gap_lo[0] - g.design_lo[0], g.gap_lo[1] - g.design_lo[1],
+                           ctx->dims == 3 ? g.gap_lo[2] - g.design_lo[2] : 0, g.gap_n[0], g.gap_n[1],
+                           ctx->dims == 3 ? g.gap_n[2] : 1, dst);
     if (!on_device) {
       FDTD_HIP(hipMemcpyAsync(grad_out, ctx->gtmp.p, (size_t)count * ctx->esz, hipMemcpyDeviceToHost, ctx->stream));
       FDTD_HIP(hipStreamSynchronize(ctx->stream));
@@ -1630,7 +1688,8 @@ fdtd_status fdtd_batch_create(const fdtd_config *cfgs, int32_t count, const fdtd
     if (b->opt.depth == 2 && b->opt.rows != 0 && b->opt.rows != 2)
       throw einval("two-step blocking runs two rows per thread (rows 0 or 2)");
     for (int k = 0; k < count; ++k) {
-      if (cfgs[k].dims != 2) throw einval("batch instance " + std::to_string(k) + ": batches hold 2D instances");
+      if (cfgs[k].dims != 2 || cfgs[k].pol_axis == FDTD_AXIS_X)
+        throw einval("batch instance " + std::to_string(k) + ": batches hold 2D TMz instances");
       if (cfgs[k].precision != cfgs[0].precision) throw einval("batch instances must share the precision");
       if (cfgs[k].n_steps != cfgs[0].n_steps) throw einval("batch instances must share n_steps");
       if (cfgs[k].ckpt_every != 0) throw einval("batch instances keep the full history (ckpt_every = 0)");

@@ -245,10 +245,18 @@ class FDTD:
         self.h = h
         self.K = cfg.n_freq
         dnx, dny, dnz = w["design_n"]
-        self.dshape = (dnz, dny, dnx) if self.dims == 3 else (dny, dnx)
-        self.nd = int(np.prod(self.dshape))
         gx, gy, gz = w["gap_n"]
-        self.ng = gx * gy * (gz if self.dims == 3 else 1)
+        # 2D TEz (E along x): one density per design edge, the box's E_x edges
+        # ([dny+1][dnx]) then its E_y edges ([dny][dnx+1]); the gap's edges
+        # are its monitors
+        self.te = self.dims == 2 and w.get("pol_axis") == "x"
+        if self.te:
+            self.dshape = (dnx * (dny + 1) + (dnx + 1) * dny,)
+            self.ng = gx * (gy + 1) + (gx + 1) * gy if gx > 0 and gy > 0 else 0
+        else:
+            self.dshape = (dnz, dny, dnx) if self.dims == 3 else (dny, dnx)
+            self.ng = gx * gy * (gz if self.dims == 3 else 1)
+        self.nd = int(np.prod(self.dshape))
         self.ncomp = 3 if self.dims == 3 else 1
 
     def _check(self, rc):
@@ -309,10 +317,13 @@ class FDTD:
         return out[..., 0] + 1j * out[..., 1]
 
     def state_shape(self):
-        """(fields, nz, ny, nx) of the test-only state arrays: 2D E_z, H_x, H_y, J_z
-        (nz = 1); 3D E_x, E_y, E_z, H_x, H_y, H_z, J_x, J_y, J_z."""
+        """(fields, nz, ny, nx) of the test-only state arrays: 2D TMz E_z, H_x,
+        H_y, J_z; 2D TEz E_x, E_y, H_z, J_x, J_y (nz = 1); 3D E_x, E_y, E_z,
+        H_x, H_y, H_z, J_x, J_y, J_z."""
         nx, ny, nz = self.w["n"]
-        return (4, 1, ny, nx) if self.dims == 2 else (9, nz, ny, nx)
+        if self.dims == 2:
+            return (5 if self.te else 4, 1, ny, nx)
+        return (9, nz, ny, nx)
 
     def set_state(self, state):
         """Test only: initial state (E^0, H^{-1/2}, J^0) of the following forward

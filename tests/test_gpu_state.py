@@ -313,8 +313,8 @@ def test_state_hooks_call_order_and_validation(gpu):
         gpu.FDTD(W.tiny2d(design_lo=(7, 7, 0)))
     assert e.value.name == "EINVAL"
     gpu.FDTD(W.tiny2d(design_lo=(7, 7, 0), source="none")).close()
-    with pytest.raises(gpu.FDTDError) as e:
-        gpu.FDTD(W.tiny2d(pol_axis="x"))
+    with pytest.raises(gpu.FDTDError) as e:  # 2D: E along z (TMz) or x (TEz)
+        gpu.FDTD(W.tiny2d(pol_axis="y"))
     assert e.value.name == "EINVAL"
     gpu.FDTD(W.tiny2d(pol_axis="z", prop_axis="y")).close()
     with pytest.raises(gpu.FDTDError) as e:
