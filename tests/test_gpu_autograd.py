@@ -21,16 +21,26 @@ def tg():
     return torch, A
 
 
-def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3, bar=1e-6, verbose=False):
+def autograd_gradient(tg, w, ckpt_every):
+    """(solver, rho0, F, dF/drho from the autograd backward)."""
     torch, A = tg
     s = A.Solver(w, ckpt_every=ckpt_every)
     rho0 = W.seeded_rho(w, 0)
     rho = torch.tensor(rho0, dtype=torch.float64, device="cuda", requires_grad=True)
     F = A.objective(rho, s)
     F.backward()
-    g = rho.grad.detach().cpu().numpy()
+    return s, rho0, F.item(), rho.grad.detach().cpu().numpy()
+
+
+def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3, bar=1e-6, verbose=False, pre=None, part=None):
+    """Central differences on `cells` random design cells (of which the
+    slice `part` when given; `pre` = a precomputed autograd_gradient)."""
+    torch, A = tg
+    s, rho0, F, g = pre if pre is not None else autograd_gradient(tg, w, ckpt_every)
     rng = np.random.default_rng(seed)
     flat = rng.choice(rho0.size, size=cells, replace=False)
+    if part is not None:
+        flat = flat[part]
     worst = 0.0
     for f in flat:
         idx = np.unravel_index(f, rho0.shape)
@@ -44,9 +54,9 @@ def fd_check(tg, w, ckpt_every, cells=20, h=1e-4, seed=3, bar=1e-6, verbose=Fals
         worst = max(worst, err)
         if verbose:
             say(f"   cell {idx}: adjoint {g[idx]:.9e} central difference {fd:.9e} rel err {err:.2e}")
-    say(f"[autograd] {w['name']} K={ckpt_every}: F={F.item():.9e} worst FD rel err={worst:.2e}")
+    say(f"[autograd] {w['name']} K={ckpt_every}: F={F:.9e} worst FD rel err={worst:.2e}")
     assert worst <= bar
-    return F.item(), g
+    return F, g
 
 
 def test_tiny2d_autograd_matches_fd_and_oracle(tg, oracle_mod):
@@ -60,14 +70,24 @@ def test_medium3d_autograd_checkpointed_matches_fd(tg):
     fd_check(tg, W.medium3d(precision=64), 100)
 
 
-def test_c3_full_autograd_checkpointed_matches_fd(tg):
+@pytest.fixture(scope="module")
+def c3_autograd(tg):
+    w = W.with_(W.c3(), precision=64)
+    say("[autograd] 256^3 fp64 K=500: forward + backward")
+    return w, autograd_gradient(tg, w, 500)
+
+
+@pytest.mark.parametrize("part", [slice(0, 5), slice(5, 10), slice(10, 15), slice(15, 20)])
+def test_c3_full_autograd_checkpointed_matches_fd(tg, c3_autograd, part):
     """The 256^3 x 8000-step workload in the FP64 build, checkpoint every 500
     steps: the autograd gradient against central differences (h = 1e-4) on 20
-    random design cells, at the bar of the smaller cases (1e-6; the paper
-    reports better than four digits for its own adjoint, Sec. 3.2).  Observed:
-    5e-9 at worst, the FP64 rounding of F (~1e-13 of F, over 2h) in the
-    differences of the cells with small gradients."""
-    fd_check(tg, W.with_(W.c3(), precision=64), 500, verbose=True)
+    random design cells (five per test, so that each test ends within a
+    minute), at the bar of the smaller cases (1e-6; the paper reports better
+    than four digits for its own adjoint, Sec. 3.2).  Observed: 5e-9 at
+    worst, the FP64 rounding of F (~1e-13 of F, over 2h) in the differences
+    of the cells with small gradients."""
+    w, pre = c3_autograd
+    fd_check(tg, w, 500, verbose=True, pre=pre, part=part)
 
 
 def test_backward_after_an_intervening_forward(tg):
