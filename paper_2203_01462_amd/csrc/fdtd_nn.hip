@@ -137,7 +137,7 @@ constexpr int XST = 40;                 // LDS stride between staged pixels (80 
 constexpr int WST = 40;                 // LDS stride between staged (tap, co) weight rows
 constexpr int TT = 16, HT = TT + 2;     // output tile side, halo tile side
 
-template <int MT>
+template <int MT, bool NHWC>
 __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, int h, int w,
                                                           const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ wt,
@@ -170,17 +170,25 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
       const int r = pos / HT, q = pos - r * HT;
       const int iy = y0 - 1 + r, ix = x0 - 1 + q;
       const bool ok = iy >= 0 && iy < h && ix >= 0 && ix < w;
-      const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
+      if constexpr (NHWC) {
+        // channel-last copy: the pixel's 32 channels are 64 contiguous bytes
+        const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
 #pragma unroll
-      for (int c8 = 0; c8 < CC; c8 += 8) {
-        uint32_t pk[4];
+        for (int c8 = 0; c8 < CC / 8; ++c8)
+          *(uint4 *)(Xs + pos * XST + 8 * c8) = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
+      } else {
+        const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t lo = ok ? src[(size_t)(c8 + 2 * j) * cs] : 0u;
-          const uint32_t hi = ok ? src[(size_t)(c8 + 2 * j + 1) * cs] : 0u;
-          pk[j] = lo | (hi << 16);
+        for (int c8 = 0; c8 < CC; c8 += 8) {
+          uint32_t pk[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t lo = ok ? src[(size_t)(c8 + 2 * j) * cs] : 0u;
+            const uint32_t hi = ok ? src[(size_t)(c8 + 2 * j + 1) * cs] : 0u;
+            pk[j] = lo | (hi << 16);
+          }
+          *(uint4 *)(Xs + pos * XST + c8) = uint4{pk[0], pk[1], pk[2], pk[3]};
         }
-        *(uint4 *)(Xs + pos * XST + c8) = uint4{pk[0], pk[1], pk[2], pk[3]};
       }
     }
     __syncthreads();
@@ -218,7 +226,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
 // The same with the staging software-pipelined (see above): faster on the
 // deep layers with a few pixel tiles and several channel chunks, slower on
 // the wide ones (its prefetch registers leave one wavefront per SIMD).
-template <int MT>
+template <int MT, bool NHWC>
 __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cout, int h, int w,
                                                                const uint16_t *__restrict__ x,
                                                                const uint16_t *__restrict__ wt,
@@ -248,12 +256,24 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
       const int r = pos / HT, q = pos - r * HT;
       const int iy = y0 - 1 + r, ix = x0 - 1 + q;
       const bool ok = pos < HT * HT && iy >= 0 && iy < h && ix >= 0 && ix < w;
-      const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
+      if constexpr (NHWC) {
+        const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
 #pragma unroll
-      for (int j = 0; j < CC / 2; ++j) {
-        const uint32_t lo = ok ? src[(size_t)(2 * j) * cs] : 0u;
-        const uint32_t hi = ok ? src[(size_t)(2 * j + 1) * cs] : 0u;
-        xr[k][j] = lo | (hi << 16);
+        for (int c8 = 0; c8 < CC / 8; ++c8) {
+          const uint4 v = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
+          xr[k][4 * c8] = v.x;
+          xr[k][4 * c8 + 1] = v.y;
+          xr[k][4 * c8 + 2] = v.z;
+          xr[k][4 * c8 + 3] = v.w;
+        }
+      } else {
+        const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
+#pragma unroll
+        for (int j = 0; j < CC / 2; ++j) {
+          const uint32_t lo = ok ? src[(size_t)(2 * j) * cs] : 0u;
+          const uint32_t hi = ok ? src[(size_t)(2 * j + 1) * cs] : 0u;
+          xr[k][j] = lo | (hi << 16);
+        }
       }
     }
   };
@@ -339,23 +359,80 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
   }
 }
 
+// Channel-last copy of a [c][n][hw] BF16 tensor: y[(img hw + p) c + ch].
+// grid (hw / 64, c / 32, n): a workgroup moves 64 pixels x 32 channels
+// through LDS, reading rows of pixels and writing 64-byte channel runs.
+__global__ void __launch_bounds__(BS) to_nhwc_kernel(int c, int hw, const uint16_t *__restrict__ x,
+                                                     uint16_t *__restrict__ y) {
+  __shared__ uint16_t tile[32][64 + 2];
+  const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 32, img = blockIdx.z, nimg = gridDim.z;
+  const int t = threadIdx.x;
+  const size_t cs = (size_t)nimg * hw;
+  {
+    const int p = t & 63, g = t >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int ch = g * 8 + k;
+      tile[ch][p] = x[(size_t)(c0 + ch) * cs + (size_t)img * hw + p0 + p];
+    }
+  }
+  __syncthreads();
+  const int p = t >> 2, part = t & 3;
+  uint32_t pk[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    pk[j] = (uint32_t)tile[part * 8 + 2 * j][p] | ((uint32_t)tile[part * 8 + 2 * j + 1][p] << 16);
+  *(uint4 *)(y + ((size_t)img * hw + p0 + p) * c + c0 + part * 8) = uint4{pk[0], pk[1], pk[2], pk[3]};
+}
+
+// Device buffer for the channel-last copy of a convolution input, one per
+// (device, stream) so that convolutions on different streams never share it;
+// kept until the process ends, grown (after the device has drained the work
+// that may still read it) to the largest request.
+uint16_t *nhwc_buffer(size_t elems, hipStream_t s) {
+  int dev = 0;
+  FDTD_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> bufs;
+  std::lock_guard<std::mutex> lock(mu);
+  auto &b = bufs[{dev, s}];
+  if (b.second < elems) {
+    if (b.first) {
+      FDTD_HIP(hipDeviceSynchronize());
+      FDTD_HIP(hipFree(b.first));
+    }
+    b.first = nullptr;
+    b.second = 0;
+    FDTD_HIP(hipMalloc(&b.first, elems * sizeof(uint16_t)));
+    b.second = elems;
+  }
+  return static_cast<uint16_t *>(b.first);
+}
+
 // One forward convolution launch: the LDS-tiled kernel where the shape and
-// the weight alignment allow it, else the generic one.
+// the weight alignment allow it (its input staged from a channel-last copy,
+// 16-byte loads of a pixel's channels), else the generic one.
 void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, const uint16_t *wt, const float *bias,
                  float *z, uint16_t *a, hipStream_t s) {
   if (cin % CC == 0 && h % TT == 0 && w % TT == 0 && ((uintptr_t)wt & 15) == 0) {
     const int tiles = (h / TT) * (w / TT), cot = cout <= 32 ? (cout + 31) / 32 : (cout + 63) / 64;
+    uint16_t *xh = nhwc_buffer((size_t)n * cin * h * w, s);
+    hipLaunchKernelGGL(to_nhwc_kernel, dim3(h * w / 64, cin / 32, n), dim3(BS), 0, s, cin, h * w, x, xh);
     if (tiles <= 4 && cin > CC) {  // deep layers: pipelined staging, one tile per workgroup (measured)
       const dim3 g(tiles, cot, n);
       if (cout <= 32)
-        hipLaunchKernelGGL(conv_fwd_mfma_pipe_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a, 1);
+        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
+                           a, 1);
       else
-        hipLaunchKernelGGL(conv_fwd_mfma_pipe_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a, 1);
+        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
+                           a, 1);
       return;
     }
     const dim3 g(tiles, cot, n);
-    if (cout <= 32) hipLaunchKernelGGL(conv_fwd_mfma_kernel<2>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
-    else hipLaunchKernelGGL(conv_fwd_mfma_kernel<4>, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+    if (cout <= 32)
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a);
+    else
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a);
     return;
   }
   const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
