@@ -10,7 +10,8 @@
  *                          implicit GEMM on BF16 matrix cores with FP32
  *                          accumulation: z = w * x + b
  *   fdtd_nn_conv3x3_dgrad  dL/dx of the same convolution (the forward GEMM with
- *                          the weights turned by 180 degrees and transposed)
+ *                          the weights turned by 180 degrees and transposed);
+ *                          _dgrad_relu fuses the ReLU backward of the layer below
  *   fdtd_nn_conv3x3_wgrad  dL/dw and dL/db (GEMM over all pixels of the batch)
  *   fdtd_nn_relu_bf16      a = bf16(max(z, 0)) and its backward
  *   fdtd_nn_pool2 / up2    2x2 average pooling and 2x nearest upsampling (and
@@ -54,6 +55,16 @@ fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int
  * wrot: caller workspace of cout*cin*9 BF16 values. */
 fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
                                   const uint16_t *wt, uint16_t *wrot, float *dx, void *stream);
+
+/* The data gradient fused with the backward of the ReLU whose BF16 output a
+ * ([cin][n][h][w], the convolution's input) fed this layer:
+ * dza = bf16(dx * (a > 0)) with dx as fdtd_nn_conv3x3_dgrad computes it --
+ * the same BF16 values as fdtd_nn_conv3x3_dgrad followed by
+ * fdtd_nn_relu_bf16_backward(a, dx), without the FP32 dx in memory.
+ * dza must not overlap dz or a. */
+fdtd_status fdtd_nn_conv3x3_dgrad_relu(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
+                                       const uint16_t *wt, uint16_t *wrot, const uint16_t *a, uint16_t *dza,
+                                       void *stream);
 
 /* dw[co][ky][kx][ci] = sum_{n,y,x} dz[co][n][y][x] x[ci][n][y+ky-1][x+kx-1];
  * db[co] = sum_{n,y,x} dz; work: caller workspace of fdtd_nn_wgrad_work(...)

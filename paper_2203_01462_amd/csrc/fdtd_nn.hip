@@ -37,6 +37,48 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// The BF16 output of a convolution: relu(v) in the forward pass; with a mask
+// (the BF16 output of the ReLU that produced this convolution's input, in a
+// data-gradient pass) the pre-activation gradient v * (mask > 0), the same
+// value as the separate ReLU backward of the FP32 v.
+__device__ __forceinline__ uint16_t store_a(float v, const uint16_t *__restrict__ mask, size_t o) {
+  return mask ? f2bf(bf2f(mask[o]) > 0.f ? v : 0.f) : f2bf(fmaxf(v, 0.f));
+}
+
+// Mask values of one 16-channel block of a tiled kernel's outputs: rows
+// `row0 + s` (s < 4, pix0 = the first row's pixel offset) at the lane's
+// column, channels co0 + 4 kq + j.
+__device__ __forceinline__ void load_mask16(uint16_t (&mk)[4][4], int co0, int cout, int kq, size_t pix0, int w,
+                                            size_t cs, const uint16_t *__restrict__ mask) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co0 + 4 * kq + j;
+      mk[s][j] = co < cout ? mask[(size_t)co * cs + pix0 + (size_t)s * w] : (uint16_t)0;
+    }
+}
+
+// Output of that block: z = v (FP32) and/or a = relu(v) (BF16), or with a
+// mask (mk loaded by load_mask16) a = v * (mask > 0) (BF16).
+__device__ __forceinline__ void tile_out16(const f4 (&acc)[4], const uint16_t (&mk)[4][4], bool masked, int co0,
+                                           int cout, int kq, size_t pix0, int w, size_t cs,
+                                           const float *__restrict__ bias, float *__restrict__ z,
+                                           uint16_t *__restrict__ a) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co0 + 4 * kq + j;
+      if (co < cout) {
+        const float v = acc[s][j] + (bias ? bias[co] : 0.f);
+        const size_t o = (size_t)co * cs + pix0 + (size_t)s * w;
+        if (z) z[o] = v;
+        if (a) a[o] = masked ? f2bf(bf2f(mk[s][j]) > 0.f ? v : 0.f) : f2bf(fmaxf(v, 0.f));
+      }
+    }
+}
+
 __device__ __forceinline__ double block_sum(double v, double *lds) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
@@ -69,7 +111,8 @@ __device__ __forceinline__ void mfma_step(const uint16_t (*As)[TK + PAD], const 
 // a = bf16(max(z, 0)).  grid (ceil(HW/64), ceil(cout/64), n).
 __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, int w, const uint16_t *__restrict__ x,
                                                      const uint16_t *__restrict__ wt, const float *__restrict__ bias,
-                                                     float *__restrict__ z, uint16_t *__restrict__ a) {
+                                                     float *__restrict__ z, uint16_t *__restrict__ a,
+                                                     const uint16_t *__restrict__ mask) {
   __shared__ uint16_t As[TM][TK + PAD];
   __shared__ uint16_t Bs[TK][TN + PAD];
   const int n = blockIdx.z, nimg = gridDim.z, HW = h * w, K = cin * 9;
@@ -116,7 +159,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, 
         const float v = acc[s][j] + (bias ? bias[co] : 0.f);
         const size_t o = (size_t)co * cs + (size_t)n * HW + p;
         if (z) z[o] = v;
-        if (a) a[o] = f2bf(fmaxf(v, 0.f));
+        if (a) a[o] = store_a(v, mask, o);
       }
     }
 }
@@ -142,7 +185,8 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
                                                           const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ wt,
                                                           const float *__restrict__ bias, float *__restrict__ z,
-                                                          uint16_t *__restrict__ a) {
+                                                          uint16_t *__restrict__ a,
+                                                          const uint16_t *__restrict__ mask) {
   __shared__ __attribute__((aligned(16))) uint16_t Xs[HT * HT * XST];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * 16 * MT * WST];
   const int n = blockIdx.z, nimg = gridDim.z, HW = h * w;
@@ -157,6 +201,15 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
+  // a data-gradient pass's mask values, loaded first so that they arrive
+  // while the tile is staged and multiplied
+  const size_t pix0 = (size_t)n * HW + (size_t)(y0 + 4 * wave) * w + x0 + l16;
+  const bool masked = a && mask;
+  uint16_t mk[MT][4][4];
+  if (masked) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) load_mask16(mk[m], co0 + 16 * m, cout, kq, pix0, w, cs, mask);
+  }
   for (int c0 = 0; c0 < cin; c0 += CC) {
     for (int v = t; v < 9 * 16 * MT * 4; v += BS) {
       const int part = v & 3, row = v >> 2;
@@ -208,19 +261,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
     __syncthreads();
   }
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int co = co0 + 16 * m + 4 * kq + j;
-        if (co < cout) {
-          const float v = acc[m][s][j] + (bias ? bias[co] : 0.f);
-          const size_t o = (size_t)co * cs + (size_t)n * HW + (size_t)(y0 + 4 * wave + s) * w + x0 + l16;
-          if (z) z[o] = v;
-          if (a) a[o] = f2bf(fmaxf(v, 0.f));
-        }
-      }
+  for (int m = 0; m < MT; ++m) tile_out16(acc[m], mk[m], masked, co0 + 16 * m, cout, kq, pix0, w, cs, bias, z, a);
 }
 
 // The same with the staging software-pipelined (see above): faster on the
@@ -232,7 +273,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
                                                                const uint16_t *__restrict__ wt,
                                                                const float *__restrict__ bias,
                                                                float *__restrict__ z, uint16_t *__restrict__ a,
-                                                               const int tpw) {
+                                                               const uint16_t *__restrict__ mask, const int tpw) {
   __shared__ __attribute__((aligned(16))) uint16_t Xs[HT * HT * XST];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * 16 * MT * WST];
   constexpr int NXP = (HT * HT + BS - 1) / BS;           // halo pixels per thread (2)
@@ -338,22 +379,15 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
     }
     if (ch == nch - 1) {  // the tile's last chunk: write it out
       const int y0 = (tile / tilesx) * TT, x0 = (tile % tilesx) * TT;
+      const size_t pix0 = (size_t)n * HW + (size_t)(y0 + 4 * wave) * w + x0 + l16;
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MT; ++m) {
+        uint16_t mk[4][4];
+        if (a && mask) load_mask16(mk, co0 + 16 * m, cout, kq, pix0, w, cs, mask);
+        tile_out16(acc[m], mk, a && mask, co0 + 16 * m, cout, kq, pix0, w, cs, bias, z, a);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int co = co0 + 16 * m + 4 * kq + j;
-            if (co < cout) {
-              const float v = acc[m][s][j] + (bias ? bias[co] : 0.f);
-              const size_t o = (size_t)co * cs + (size_t)n * HW + (size_t)(y0 + 4 * wave + s) * w + x0 + l16;
-              if (z) z[o] = v;
-              if (a) a[o] = f2bf(fmaxf(v, 0.f));
-            }
-          }
-          acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int s = 0; s < 4; ++s) acc[m][s] = f4{0.f, 0.f, 0.f, 0.f};
+      }
     }
     __syncthreads();
   }
@@ -413,7 +447,7 @@ uint16_t *nhwc_buffer(size_t elems, hipStream_t s) {
 // the weight alignment allow it (its input staged from a channel-last copy,
 // 16-byte loads of a pixel's channels), else the generic one.
 void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, const uint16_t *wt, const float *bias,
-                 float *z, uint16_t *a, hipStream_t s) {
+                 float *z, uint16_t *a, const uint16_t *mask, hipStream_t s) {
   if (cin % CC == 0 && h % TT == 0 && w % TT == 0 && ((uintptr_t)wt & 15) == 0) {
     const int tiles = (h / TT) * (w / TT), cot = cout <= 32 ? (cout + 31) / 32 : (cout + 63) / 64;
     uint16_t *xh = nhwc_buffer((size_t)n * cin * h * w, s);
@@ -422,21 +456,21 @@ void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, cons
       const dim3 g(tiles, cot, n);
       if (cout <= 32)
         hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
-                           a, 1);
+                           a, mask, 1);
       else
         hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
-                           a, 1);
+                           a, mask, 1);
       return;
     }
     const dim3 g(tiles, cot, n);
     if (cout <= 32)
-      hipLaunchKernelGGL((conv_fwd_mfma_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a);
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
     else
-      hipLaunchKernelGGL((conv_fwd_mfma_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a);
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
     return;
   }
   const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
-  hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a);
+  hipLaunchKernelGGL(conv_fwd_kernel, g, dim3(BS), 0, s, cin, cout, h, w, x, wt, bias, z, a, mask);
 }
 
 // Partial weight gradients over one range of pixels q = (n, p) of the batch:
@@ -499,66 +533,110 @@ __global__ void __launch_bounds__(BS) conv_wgrad_kernel(int nimg, int cin, int c
 // Weight gradient, LDS-tiled for cin % 32 == 0, h % 8 == 0, w % 16 == 0 and
 // 16-byte aligned x and dz:
 // part[split][co][tap][ci] = sum over the split's pixel tiles of
-// dz[co][q] x[ci][q shifted by tap].  A workgroup owns 64 output channels x 32
-// input channels x 9 taps and walks 8 x 16 pixel tiles; the reduction runs
-// over pixels (32 per matrix instruction), so both operands are staged
-// pixel-contiguous: dz rows as they are, and the input tile three times,
-// shifted by kx = 0, 1, 2, so every 16-byte fragment read stays aligned.
-// Wavefront w owns output channels 16w..16w+15 (2 x 9 accumulator tiles).
-// grid (ceil(cout/64), cin/32, splits).
+// dz[co][q] x[ci][q shifted by tap] (rows `stride` floats apart).  A
+// workgroup owns CT (64 or 32) output channels x 32 input channels x 9 taps
+// and walks 8 x 16 pixel tiles; the reduction runs over pixels (32 per
+// matrix instruction), so both operands are staged pixel-contiguous: dz rows
+// as they are, and the input tile three times, shifted by kx = 0, 1, 2, so
+// every 16-byte fragment read stays aligned.  CT = 64: wavefront w owns
+// output channels 16w..16w+15 and both 16-channel halves of the input chunk
+// (2 x 9 accumulator tiles); CT = 32 (layers with at most 32 output
+// channels): output channels 16(w & 1).. and input half w >> 1 (1 x 9).
+// With bpart, the workgroups of the first input chunk also write the
+// split's bias partial sums bpart[split * stride + co] = sum of dz[co][q]
+// over its tiles.  grid (ceil(cout/CT), cin/32, splits).
 constexpr int GY = 8, GX = 16, GP = GY * GX;  // pixel tile
 constexpr int DST = GP + 8;                   // LDS stride of staged dz rows
 constexpr int XCI = (GY + 2) * GX + 8;        // LDS stride per input channel of a shifted copy
 
+template <int CT>
 __global__ void __launch_bounds__(BS) conv_wgrad_mfma_kernel(int nimg, int cin, int cout, int h, int w,
                                                             const uint16_t *__restrict__ x,
                                                             const uint16_t *__restrict__ dz,
-                                                            float *__restrict__ part, int tiles_per_split) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ds[64 * DST];
+                                                            float *__restrict__ part, int64_t stride,
+                                                            int tiles_per_split, float *__restrict__ bpart) {
+  constexpr int NT = CT / 32;           // 16-channel input halves per wavefront
+  constexpr int DV = CT * GY * 2 / BS;  // 16-byte dz vectors per thread and tile
+  __shared__ __attribute__((aligned(16))) uint16_t Ds[CT * DST];
   __shared__ __attribute__((aligned(16))) uint16_t Xs[3 * 32 * XCI];
   const int HW = h * w;
   const size_t P = (size_t)nimg * HW;
-  const int co0 = blockIdx.x * 64, ci0 = blockIdx.y * 32, split = blockIdx.z;
+  const int co0 = blockIdx.x * CT, ci0 = blockIdx.y * 32, split = blockIdx.z;
   const int tx_n = w / GX, tiles_img = (h / GY) * tx_n, tiles = nimg * tiles_img;
   const int T0 = split * tiles_per_split, T1 = min(tiles, T0 + tiles_per_split);
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
-  f4 acc[2][9];
+  const int cw = CT == 64 ? wave : (wave & 1), nb = CT == 64 ? 0 : (wave >> 1);
+  const bool with_bias = bpart != nullptr && blockIdx.y == 0;
+  f4 acc[NT][9];
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt)
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp) acc[nt][tp] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int T = T0; T < T1; ++T) {
+  float bacc[DV];
+#pragma unroll
+  for (int k = 0; k < DV; ++k) bacc[k] = 0.f;
+  // A tile's global loads, issued together into registers: the dz rows (CT
+  // channels x 8 rows x 16 pixels as 16-byte vectors) and the input halo
+  // rows y0-1 .. y0+8 of the 32 channels (one row per thread and pass: the
+  // 16 interior pixels as two 16-byte vectors plus the two halo pixels).
+  // The next tile's loads fly while the current tile's matrix instructions run.
+  constexpr int XR = (32 * (GY + 2) + BS - 1) / BS;
+  uint4 dv[DV], xa[XR], xb[XR];
+  uint32_t xl[XR], xr[XR];
+  auto load_tile = [&](int T) {
     const int n = T / tiles_img, rem = T - n * tiles_img;
     const int y0 = (rem / tx_n) * GY, x0 = (rem % tx_n) * GX;
-    // dz rows: 64 channels x 8 rows x 16 pixels as 16-byte vectors
-    for (int v = t; v < 64 * GY * 2; v += BS) {
-      const int half = v & 1, r = (v >> 1) & (GY - 1), c = v >> 4, co = co0 + c;
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (co < cout) val = *(const uint4 *)(dz + (size_t)co * P + (size_t)n * HW + (size_t)(y0 + r) * w + x0 + 8 * half);
-      *(uint4 *)(Ds + c * DST + r * GX + 8 * half) = val;
+#pragma unroll
+    for (int k = 0; k < DV; ++k) {
+      const int v = t + k * BS;
+      const int half = v & 1, r = (v >> 1) & (GY - 1), co = co0 + (v >> 4);
+      dv[k] = uint4{0u, 0u, 0u, 0u};
+      if (co < cout) dv[k] = *(const uint4 *)(dz + (size_t)co * P + (size_t)n * HW + (size_t)(y0 + r) * w + x0 + 8 * half);
     }
-    // input halo rows y0-1 .. y0+8 (one per thread and channel): the 16
-    // interior pixels as two 16-byte loads plus the two halo pixels, stored as
-    // three copies shifted by kx (copy kx, pixel q = input column x0 - 1 + q + kx)
-    for (int rr = t; rr < 32 * (GY + 2); rr += BS) {
-      const int c = rr / (GY + 2), r = rr - c * (GY + 2);
-      const int iy = y0 - 1 + r;
-      uint32_t W[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}, hl = 0u, hr = 0u;
-      if (iy >= 0 && iy < h) {
+#pragma unroll
+    for (int q = 0; q < XR; ++q) {
+      const int rr = t + q * BS;
+      xa[q] = xb[q] = uint4{0u, 0u, 0u, 0u};
+      xl[q] = xr[q] = 0u;
+      const int c = rr / (GY + 2), r = rr - c * (GY + 2), iy = y0 - 1 + r;
+      if (rr < 32 * (GY + 2) && iy >= 0 && iy < h) {
         const uint16_t *row = x + (size_t)(ci0 + c) * P + (size_t)n * HW + (size_t)iy * w;
-        const uint4 a0 = *(const uint4 *)(row + x0), a1 = *(const uint4 *)(row + x0 + 8);
-        W[0] = a0.x; W[1] = a0.y; W[2] = a0.z; W[3] = a0.w;
-        W[4] = a1.x; W[5] = a1.y; W[6] = a1.z; W[7] = a1.w;
-        if (x0 > 0) hl = row[x0 - 1];
-        if (x0 + GX < w) hr = row[x0 + GX];
+        xa[q] = *(const uint4 *)(row + x0);
+        xb[q] = *(const uint4 *)(row + x0 + 8);
+        if (x0 > 0) xl[q] = row[x0 - 1];
+        if (x0 + GX < w) xr[q] = row[x0 + GX];
       }
+    }
+  };
+  // ... and their LDS copies: dz rows as they are, the input rows three
+  // times, shifted by kx (copy kx, pixel q = input column x0 - 1 + q + kx)
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int k = 0; k < DV; ++k) {
+      const int v = t + k * BS;
+      const int half = v & 1, r = (v >> 1) & (GY - 1), c = v >> 4;
+      *(uint4 *)(Ds + c * DST + r * GX + 8 * half) = dv[k];
+      if (with_bias) {
+        const uint32_t u[4] = {dv[k].x, dv[k].y, dv[k].z, dv[k].w};
+        float s8 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s8 += bf2f((uint16_t)(u[j] & 0xffffu)) + bf2f((uint16_t)(u[j] >> 16));
+        bacc[k] += s8;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < XR; ++q) {
+      const int rr = t + q * BS;
+      if (rr >= 32 * (GY + 2)) continue;
+      const int c = rr / (GY + 2), r = rr - c * (GY + 2);
+      const uint32_t W[8] = {xa[q].x, xa[q].y, xa[q].z, xa[q].w, xb[q].x, xb[q].y, xb[q].z, xb[q].w};
       uint32_t S0[8], S2[8];
-      S0[0] = hl | (W[0] << 16);
+      S0[0] = xl[q] | (W[0] << 16);
 #pragma unroll
       for (int k = 1; k < 8; ++k) S0[k] = (W[k - 1] >> 16) | (W[k] << 16);
 #pragma unroll
       for (int k = 0; k < 7; ++k) S2[k] = (W[k] >> 16) | (W[k + 1] << 16);
-      S2[7] = (W[7] >> 16) | (hr << 16);
+      S2[7] = (W[7] >> 16) | (xr[q] << 16);
       uint16_t *d0 = Xs + (0 * 32 + c) * XCI + r * GX;
       uint16_t *d1 = Xs + (1 * 32 + c) * XCI + r * GX;
       uint16_t *d2 = Xs + (2 * 32 + c) * XCI + r * GX;
@@ -569,17 +647,22 @@ __global__ void __launch_bounds__(BS) conv_wgrad_mfma_kernel(int nimg, int cin, 
       *(uint4 *)d2 = uint4{S2[0], S2[1], S2[2], S2[3]};
       *(uint4 *)(d2 + 8) = uint4{S2[4], S2[5], S2[6], S2[7]};
     }
+  };
+  if (T0 < T1) load_tile(T0);
+  for (int T = T0; T < T1; ++T) {
+    store_tile();
     __syncthreads();
+    if (T + 1 < T1) load_tile(T + 1);
 #pragma unroll
     for (int ks = 0; ks < GP / 32; ++ks) {
       const int py = 2 * ks + (kq >> 1), px = 8 * (kq & 1);
-      const bf8 av = *(const bf8 *)(Ds + (16 * wave + l16) * DST + 32 * ks + 8 * kq);
+      const bf8 av = *(const bf8 *)(Ds + (16 * cw + l16) * DST + 32 * ks + 8 * kq);
 #pragma unroll
       for (int tp = 0; tp < 9; ++tp) {
         const int ky = tp / 3, kx = tp - 3 * ky;
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const bf8 bv = *(const bf8 *)(Xs + (kx * 32 + 16 * nt + l16) * XCI + (py + ky) * GX + px);
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf8 bv = *(const bf8 *)(Xs + (kx * 32 + 16 * (nb + nt) + l16) * XCI + (py + ky) * GX + px);
           acc[nt][tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt][tp], 0, 0, 0);
         }
       }
@@ -587,14 +670,26 @@ __global__ void __launch_bounds__(BS) conv_wgrad_mfma_kernel(int nimg, int cin, 
     __syncthreads();
   }
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt)
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int co = co0 + 16 * wave + 4 * kq + j, ci = ci0 + 16 * nt + l16;
-        if (co < cout) part[(((size_t)split * cout + co) * 9 + tp) * cin + ci] = acc[nt][tp][j];
+        const int co = co0 + 16 * cw + 4 * kq + j, ci = ci0 + 16 * (nb + nt) + l16;
+        if (co < cout) part[(size_t)split * stride + ((size_t)co * 9 + tp) * cin + ci] = acc[nt][tp][j];
       }
+  if (with_bias) {
+    // the 16 consecutive lanes that staged one channel's rows, summed in a
+    // fixed butterfly order
+#pragma unroll
+    for (int k = 0; k < DV; ++k) {
+      float v = bacc[k];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+      const int co = co0 + (t >> 4) + 16 * k;
+      if ((t & 15) == 0 && co < cout) bpart[(size_t)split * stride + co] = v;
+    }
+  }
 }
 
 // Split plan of the weight gradient: which kernel, how many partial sums,
@@ -604,12 +699,16 @@ struct WgradPlan {
   int splits, chunk;
 };
 
+// Output-channel tile of the tiled weight gradient.
+inline int wgrad_ct(int cout) { return cout <= 32 ? 32 : 64; }
+
 // About 768 workgroups in flight (three per CU), at least two pixel tiles
 // per tiled workgroup so the partial sums stay few.
 WgradPlan wgrad_plan(int n, int cin, int cout, int h, int w) {
   WgradPlan pl{};
   if (cin % 32 == 0 && h % GY == 0 && w % GX == 0) {
-    const int groups = ((cout + 63) / 64) * (cin / 32);
+    const int ct = wgrad_ct(cout);
+    const int groups = ((cout + ct - 1) / ct) * (cin / 32);
     const int tiles = n * (h / GY) * (w / GX);
     const int want = std::max(1, (768 + groups - 1) / groups);
     const int per = std::max(std::min(2, tiles), (tiles + want - 1) / want);
@@ -630,19 +729,49 @@ WgradPlan wgrad_plan(int n, int cin, int cout, int h, int w) {
   return pl;
 }
 
-// Pixel ranges of the bias-gradient reduction.
+// Pixel ranges of the bias-gradient reduction of the generic kernel.
 int64_t bias_ranges(int64_t P) { return std::min<int64_t>(64, std::max<int64_t>(1, (P + 16383) / 16384)); }
 
-// dw[i] = sum over splits, in split order (the unrolled loads are issued
-// ahead; the additions keep their order).
-__global__ void __launch_bounds__(BS) split_sum_kernel(const float *__restrict__ part, int splits, int64_t m,
-                                                      float *__restrict__ dw) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= m) return;
+// out[i] = sum over k < splits of part[k * stride + i], i < m.  G groups of
+// consecutive splits per output, each summed in split order (the unrolled
+// loads are issued ahead; the additions keep their order), then the G group
+// sums in group order: a fixed order for a given split count, with G
+// wavefronts' loads in flight per output row when the splits are many.
+// grid ceil(m / 64), 64 G threads.
+template <int G>
+__global__ void __launch_bounds__(64 * G) split_sum_kernel(const float *__restrict__ part, int splits, int64_t stride,
+                                                          int64_t m, float *__restrict__ out) {
+  __shared__ float red[G][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  const int k0 = (int)((int64_t)splits * g / G), k1 = (int)((int64_t)splits * (g + 1) / G);
   float s = 0.f;
+  if (i < m) {
 #pragma unroll 8
-  for (int k = 0; k < splits; ++k) s += part[(size_t)k * m + i];
-  dw[i] = s;
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k * stride + i];
+  }
+  if constexpr (G == 1) {
+    if (i < m) out[i] = s;
+  } else {
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < m) {
+      float r = red[0][o];
+#pragma unroll
+      for (int q = 1; q < G; ++q) r += red[q][o];
+      out[i] = r;
+    }
+  }
+}
+
+void launch_split_sum(const float *part, int splits, int64_t stride, int64_t m, float *out, hipStream_t s) {
+  const dim3 g((unsigned)((m + 63) / 64));
+  if (splits >= 64)
+    hipLaunchKernelGGL(split_sum_kernel<16>, g, dim3(64 * 16), 0, s, part, splits, stride, m, out);
+  else if (splits >= 16)
+    hipLaunchKernelGGL(split_sum_kernel<4>, g, dim3(64 * 4), 0, s, part, splits, stride, m, out);
+  else
+    hipLaunchKernelGGL(split_sum_kernel<1>, g, dim3(64), 0, s, part, splits, stride, m, out);
 }
 
 // Partial bias gradients: part[b][co] = sum of dz[co][q] over pixel range b
@@ -679,6 +808,25 @@ __global__ void __launch_bounds__(BS) relu_back_kernel(int64_t n, const uint16_t
                                                       const float *__restrict__ da, uint16_t *__restrict__ dz) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) dz[i] = f2bf(bf2f(a[i]) > 0.f ? da[i] : 0.f);
+}
+
+// The same on eight elements per thread (count % 8 == 0, 16-byte aligned).
+__global__ void __launch_bounds__(BS) relu_back8_kernel(int64_t n8, const uint4 *__restrict__ a,
+                                                       const float4 *__restrict__ da, uint4 *__restrict__ dz) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n8) return;
+  const uint4 av = a[i];
+  const float4 d0 = da[2 * i], d1 = da[2 * i + 1];
+  const uint32_t aw[4] = {av.x, av.y, av.z, av.w};
+  const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint16_t lo = f2bf(bf2f((uint16_t)(aw[k] & 0xffffu)) > 0.f ? dv[2 * k] : 0.f);
+    const uint16_t hi = f2bf(bf2f((uint16_t)(aw[k] >> 16)) > 0.f ? dv[2 * k + 1] : 0.f);
+    o[k] = (uint32_t)lo | ((uint32_t)hi << 16);
+  }
+  dz[i] = uint4{o[0], o[1], o[2], o[3]};
 }
 
 __global__ void __launch_bounds__(BS) to_bf16_kernel(int64_t n, const float *__restrict__ x, uint16_t *__restrict__ y) {
@@ -722,6 +870,51 @@ __global__ void __launch_bounds__(BS) up2_kernel(int64_t planes, int h, int w, c
   y[i] = x[(size_t)pl * h * w + (size_t)(yi / 2) * w + xi / 2];
 }
 
+// Vector forms for w % 4 == 0: pool2_back writes four outputs of each of
+// two rows from two gradients; up2 copies four inputs to eight outputs of
+// each of two rows (16-byte stores).
+__global__ void __launch_bounds__(BS) pool2_back4_kernel(int64_t planes, int h, int w, const float *__restrict__ dy,
+                                                        float *__restrict__ dx) {
+  const int wq = w / 4, ho = h / 2;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * ho * wq) return;
+  const int64_t pl = i / ((int64_t)ho * wq);
+  const int r = (int)(i % ((int64_t)ho * wq)), yo = r / wq, xq = r - yo * wq;
+  const float2 g = *(const float2 *)(dy + (size_t)pl * ho * (w / 2) + (size_t)yo * (w / 2) + 2 * xq);
+  const float4 v = {0.25f * g.x, 0.25f * g.x, 0.25f * g.y, 0.25f * g.y};
+  float *b = dx + (size_t)pl * h * w + (size_t)(2 * yo) * w + 4 * xq;
+  *(float4 *)b = v;
+  *(float4 *)(b + w) = v;
+}
+
+__global__ void __launch_bounds__(BS) up2x4_kernel(int64_t planes, int h, int w, const uint16_t *__restrict__ x,
+                                                  uint16_t *__restrict__ y) {
+  const int wq = w / 4;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * h * wq) return;
+  const int64_t pl = i / ((int64_t)h * wq);
+  const int r = (int)(i % ((int64_t)h * wq)), yi = r / wq, xq = r - yi * wq;
+  const uint2 v = *(const uint2 *)(x + (size_t)pl * h * w + (size_t)yi * w + 4 * xq);
+  const uint32_t e[4] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16};
+  const uint4 o = {e[0] | (e[0] << 16), e[1] | (e[1] << 16), e[2] | (e[2] << 16), e[3] | (e[3] << 16)};
+  uint16_t *b = y + (size_t)pl * 4 * h * w + (size_t)(2 * yi) * (2 * w) + 8 * xq;
+  *(uint4 *)b = o;
+  *(uint4 *)(b + 2 * w) = o;
+}
+
+// up2_back on two outputs per thread (w % 2 == 0): two 16-byte row reads.
+__global__ void __launch_bounds__(BS) up2_back2_kernel(int64_t planes, int h, int w, const float *__restrict__ dy,
+                                                      float *__restrict__ dx) {
+  const int wh = w / 2;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= planes * h * wh) return;
+  const int64_t pl = i / ((int64_t)h * wh);
+  const int r = (int)(i % ((int64_t)h * wh)), yi = r / wh, xh = r - yi * wh;
+  const float *b = dy + (size_t)pl * 4 * h * w + (size_t)(2 * yi) * (2 * w) + 4 * xh;
+  const float4 u = *(const float4 *)b, d = *(const float4 *)(b + 2 * w);
+  *(float2 *)(dx + (size_t)pl * h * w + (size_t)yi * w + 2 * xh) = float2{u.x + u.y + d.x + d.y, u.z + u.w + d.z + d.w};
+}
+
 __global__ void __launch_bounds__(BS) up2_back_kernel(int64_t planes, int h, int w, const float *__restrict__ dy,
                                                      float *__restrict__ dx) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -751,6 +944,19 @@ __global__ void __launch_bounds__(BS) adam_kernel(int64_t n, float *__restrict__
 __global__ void __launch_bounds__(BS) axpy_kernel(int64_t n, float a, const float *__restrict__ x, float *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) y[i] += a * x[i];
+}
+
+__global__ void __launch_bounds__(BS) axpy4_kernel(int64_t n4, float a, const float4 *__restrict__ x,
+                                                  float4 *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n4) return;
+  const float4 u = x[i];
+  float4 v = y[i];
+  v.x += a * u.x;
+  v.y += a * u.y;
+  v.z += a * u.z;
+  v.w += a * u.w;
+  y[i] = v;
 }
 
 // grad = 2 (pred - target) * scale; partial sums of (pred - target)^2
@@ -823,6 +1029,7 @@ __global__ void __launch_bounds__(BS) gap_linear_back_w_kernel(int nimg, int c, 
 }
 
 int nb_of(int64_t n) { return (int)((n + BS - 1) / BS); }
+bool aligned(const void *p, uintptr_t b) { return ((uintptr_t)p & (b - 1)) == 0; }
 
 thread_local std::string g_err;
 
@@ -853,7 +1060,7 @@ fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int
                             const uint16_t *wt, const float *bias, float *z, uint16_t *a, void *stream) {
   return nguard([&] {
     need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && x && wt && (z || a));
-    launch_conv(n, cin, cout, h, w, x, wt, bias, z, a, (hipStream_t)stream);
+    launch_conv(n, cin, cout, h, w, x, wt, bias, z, a, nullptr, (hipStream_t)stream);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -864,15 +1071,29 @@ fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t 
     need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && dx);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
-    launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr, s);
+    launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr, nullptr, s);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_conv3x3_dgrad_relu(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
+                                       const uint16_t *wt, uint16_t *wrot, const uint16_t *a, uint16_t *dza,
+                                       void *stream) {
+  return nguard([&] {
+    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && a && dza);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
+    launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, nullptr, dza, a, s);
     FDTD_HIP(hipGetLastError());
   });
 }
 
 int64_t fdtd_nn_wgrad_work(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w) {
   if (n <= 0 || cin <= 0 || cout <= 0 || h <= 0 || w <= 0) return 0;
-  const int64_t P = (int64_t)n * h * w;
-  return (int64_t)wgrad_plan(n, cin, cout, h, w).splits * cout * cin * 9 + bias_ranges(P) * cout;
+  const int64_t P = (int64_t)n * h * w, splits = wgrad_plan(n, cin, cout, h, w).splits;
+  // tiled: splits rows of cout * cin * 9 weight and cout bias sums; generic:
+  // the weight rows, then bias_ranges(P) rows of cout bias sums
+  return splits * cout * cin * 9 + std::max(splits, bias_ranges(P)) * cout;
 }
 
 }  // extern "C"
@@ -895,24 +1116,38 @@ void wgrad_run(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const
     const int64_t P = (int64_t)n * h * w;
     const WgradPlan pl = wgrad_plan(n, cin, cout, h, w);
     const int64_t m = (int64_t)cout * K;
-    int S = pl.splits;
     if (pl.tiled && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0) {
-      const dim3 g((cout + 63) / 64, cin / 32, pl.splits);
-      hipLaunchKernelGGL(conv_wgrad_mfma_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, pl.chunk);
+      // partial rows [split][m weight sums | cout bias sums]
+      const int64_t stride = m + cout;
+      const int ct = wgrad_ct(cout);
+      const dim3 g((cout + ct - 1) / ct, cin / 32, pl.splits);
+      float *bp = db ? work + m : nullptr;
+      if (ct == 32)
+        hipLaunchKernelGGL(conv_wgrad_mfma_kernel<32>, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, stride,
+                           pl.chunk, bp);
+      else
+        hipLaunchKernelGGL(conv_wgrad_mfma_kernel<64>, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, stride,
+                           pl.chunk, bp);
+      if (db && db == dw + m) {  // contiguous weight and bias gradients: one reduction
+        launch_split_sum(work, pl.splits, stride, m + cout, dw, s);
+      } else {
+        launch_split_sum(work, pl.splits, stride, m, dw, s);
+        if (db) launch_split_sum(work + m, pl.splits, stride, cout, db, s);
+      }
     } else {
       // generic kernel, at most as many pixel ranges as the plan has partial sums
       int64_t chunk = (P + pl.splits - 1) / pl.splits;
       chunk = (chunk + TK - 1) / TK * TK;
-      S = (int)((P + chunk - 1) / chunk);
+      const int S = (int)((P + chunk - 1) / chunk);
       const dim3 g((K + TN - 1) / TN, (cout + TM - 1) / TM, S);
       hipLaunchKernelGGL(conv_wgrad_kernel, g, dim3(BS), 0, s, n, cin, cout, h, w, x, dz, work, (int)chunk);
-    }
-    hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(m)), dim3(BS), 0, s, work, S, m, dw);
-    if (db) {
-      float *pb = work + (size_t)pl.splits * m;
-      const int64_t nr = bias_ranges(P), chunk = (P + nr - 1) / nr;
-      hipLaunchKernelGGL(bias_grad_kernel, dim3(cout, (unsigned)nr), dim3(BS), 0, s, P, chunk, dz, pb);
-      hipLaunchKernelGGL(split_sum_kernel, dim3(nb_of(cout)), dim3(BS), 0, s, pb, (int)nr, (int64_t)cout, db);
+      launch_split_sum(work, S, m, m, dw, s);
+      if (db) {
+        float *pb = work + (size_t)pl.splits * m;
+        const int64_t nr = bias_ranges(P), bchunk = (P + nr - 1) / nr;
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(cout, (unsigned)nr), dim3(BS), 0, s, P, bchunk, dz, pb);
+        launch_split_sum(pb, (int)nr, cout, cout, db, s);
+      }
     }
     FDTD_HIP(hipGetLastError());
 }
@@ -973,7 +1208,11 @@ fdtd_status fdtd_nn_relu_bf16_backward(int64_t count, const uint16_t *a, const f
                                        void *stream) {
   return nguard([&] {
     need(count > 0 && a && da && dz);
-    hipLaunchKernelGGL(relu_back_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, da, dz);
+    if (count % 8 == 0 && aligned(a, 16) && aligned(da, 16) && aligned(dz, 16))
+      hipLaunchKernelGGL(relu_back8_kernel, dim3(nb_of(count / 8)), dim3(BS), 0, (hipStream_t)stream, count / 8,
+                         (const uint4 *)a, (const float4 *)da, (uint4 *)dz);
+    else
+      hipLaunchKernelGGL(relu_back_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, da, dz);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -1006,8 +1245,12 @@ fdtd_status fdtd_nn_pool2(int64_t planes, int32_t h, int32_t w, const uint16_t *
 fdtd_status fdtd_nn_pool2_backward(int64_t planes, int32_t h, int32_t w, const float *dy, float *dx, void *stream) {
   return nguard([&] {
     need(planes > 0 && h > 1 && w > 1 && h % 2 == 0 && w % 2 == 0 && dy && dx);
-    hipLaunchKernelGGL(pool2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h,
-                       w, dy, dx);
+    if (w % 4 == 0 && aligned(dy, 8) && aligned(dx, 16))
+      hipLaunchKernelGGL(pool2_back4_kernel, dim3(nb_of(planes * (h / 2) * (w / 4))), dim3(BS), 0,
+                         (hipStream_t)stream, planes, h, w, dy, dx);
+    else
+      hipLaunchKernelGGL(pool2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h,
+                         w, dy, dx);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -1015,8 +1258,12 @@ fdtd_status fdtd_nn_pool2_backward(int64_t planes, int32_t h, int32_t w, const f
 fdtd_status fdtd_nn_up2(int64_t planes, int32_t h, int32_t w, const uint16_t *x, uint16_t *y, void *stream) {
   return nguard([&] {
     need(planes > 0 && h > 0 && w > 0 && x && y);
-    hipLaunchKernelGGL(up2_kernel, dim3(nb_of(planes * 4 * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h, w,
-                       x, y);
+    if (w % 4 == 0 && aligned(x, 8) && aligned(y, 16))
+      hipLaunchKernelGGL(up2x4_kernel, dim3(nb_of(planes * h * (w / 4))), dim3(BS), 0, (hipStream_t)stream, planes, h,
+                         w, x, y);
+    else
+      hipLaunchKernelGGL(up2_kernel, dim3(nb_of(planes * 4 * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h, w,
+                         x, y);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -1024,8 +1271,12 @@ fdtd_status fdtd_nn_up2(int64_t planes, int32_t h, int32_t w, const uint16_t *x,
 fdtd_status fdtd_nn_up2_backward(int64_t planes, int32_t h, int32_t w, const float *dy, float *dx, void *stream) {
   return nguard([&] {
     need(planes > 0 && h > 0 && w > 0 && dy && dx);
-    hipLaunchKernelGGL(up2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h, w,
-                       dy, dx);
+    if (w % 2 == 0 && aligned(dy, 16) && aligned(dx, 8))
+      hipLaunchKernelGGL(up2_back2_kernel, dim3(nb_of(planes * h * (w / 2))), dim3(BS), 0, (hipStream_t)stream,
+                         planes, h, w, dy, dx);
+    else
+      hipLaunchKernelGGL(up2_back_kernel, dim3(nb_of(planes * h * w)), dim3(BS), 0, (hipStream_t)stream, planes, h,
+                         w, dy, dx);
     FDTD_HIP(hipGetLastError());
   });
 }
@@ -1044,7 +1295,11 @@ fdtd_status fdtd_nn_adam(int64_t count, float *p, float *m, float *v, const floa
 fdtd_status fdtd_nn_axpy(int64_t count, float a, const float *x, float *y, void *stream) {
   return nguard([&] {
     need(count > 0 && x && y);
-    hipLaunchKernelGGL(axpy_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, x, y);
+    if (count % 4 == 0 && aligned(x, 16) && aligned(y, 16))
+      hipLaunchKernelGGL(axpy4_kernel, dim3(nb_of(count / 4)), dim3(BS), 0, (hipStream_t)stream, count / 4, a,
+                         (const float4 *)x, (float4 *)y);
+    else
+      hipLaunchKernelGGL(axpy_kernel, dim3(nb_of(count)), dim3(BS), 0, (hipStream_t)stream, count, a, x, y);
     FDTD_HIP(hipGetLastError());
   });
 }

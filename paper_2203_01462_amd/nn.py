@@ -58,6 +58,13 @@ def conv3x3_dgrad(dz, wt, wrot, dx, n, cin, cout, h, w, stream=None):
                                                 _p(dx), _s(stream)))
 
 
+def conv3x3_dgrad_relu(dz, wt, wrot, a, dza, n, cin, cout, h, w, stream=None):
+    """The data gradient with the ReLU backward of the layer below fused in:
+    dza = bf16(dx * (a > 0)), a the BF16 activation that is this layer's input."""
+    _check(load_library().fdtd_nn_conv3x3_dgrad_relu(n, cin, cout, h, w, _p(_u16(dz)), _p(_u16(wt)), _p(_u16(wrot)),
+                                                     _p(_u16(a)), _p(_u16(dza)), _s(stream)))
+
+
 def wgrad_work(n, cin, cout, h, w):
     return int(load_library().fdtd_nn_wgrad_work(n, cin, cout, h, w))
 
@@ -236,6 +243,9 @@ class UNet:
         # gradient of each decoder concat buffer; its skip half is consumed by the encoder pass
         self.gcat = [torch.empty((ch[l + 1] + ch[l]) * n * sz[l] ** 2, **f32) for l in range(L - 1)]
         self.gz = torch.empty(max(big, n * s * s), **bf)
+        # BF16 pre-activation gradient written by a data gradient with the
+        # ReLU backward of the layer below fused in
+        self.gz2 = torch.empty(big, **bf)
         self.dF = torch.empty(n, **f32)
         self.dS = torch.empty(n * s * s, **f32)
         self.wrot = torch.empty(max(ci * co * 9 for ci, co, _ in self.plan), **bf)
@@ -281,21 +291,31 @@ class UNet:
         conv3x3(y, self.w(li), self.b(li), n, ch[0], 1, s, s, z=self.S, stream=st)
         return self.F, self.S.view(n, s, s)
 
-    def _conv_back(self, li, x, a_out, ga, gx, h):
+    def _conv_back(self, li, x, a_out, ga, gx, h, gz=None, fuse=False):
         """Backward of conv li (input x, BF16 output a_out = relu(z), or the
-        head when a_out is None) given the FP32 gradient ga of its output;
-        writes the FP32 input gradient into gx unless gx is None."""
+        head when a_out is None) given the FP32 gradient ga of its output, or
+        its BF16 pre-activation gradient gz when the layer above formed it.
+        Writes the FP32 input gradient into gx unless gx is None; with fuse
+        (x is the ReLU output of the layer below, whose backward comes next)
+        writes that layer's BF16 pre-activation gradient into self.gz2 instead
+        and returns it."""
         cin, cout, _ = self.plan[li]
         n, st = self.n, self.stream
         cnt = cout * n * h * h
-        gz = self.gz[:cnt]
-        if a_out is None:
-            to_bf16(ga[:cnt], gz, stream=st)
-        else:
-            relu_bf16_backward(a_out, ga[:cnt], gz, stream=st)
+        if gz is None:
+            gz = self.gz[:cnt]
+            if a_out is None:
+                to_bf16(ga[:cnt], gz, stream=st)
+            else:
+                relu_bf16_backward(a_out, ga[:cnt], gz, stream=st)
         conv3x3_wgrad(x, gz, self.dw(li), self.db(li), self.work, n, cin, cout, h, h, stream=st)
+        if fuse:
+            out = self.gz2[:cin * n * h * h]
+            conv3x3_dgrad_relu(gz, self.w(li), self.wrot, x, out, n, cin, cout, h, h, stream=st)
+            return out
         if gx is not None:
             conv3x3_dgrad(gz, self.w(li), self.wrot, gx[:cin * n * h * h], n, cin, cout, h, h, stream=st)
+        return None
 
     def backward(self, dF, dS):
         """dF: device FP32 [n] = dL/dF_hat; dS: device FP32 [n*side*side] = dL/dS_hat."""
@@ -308,9 +328,9 @@ class UNet:
         for l in range(L - 1):
             sz = s >> l
             li -= 1
-            self._conv_back(li, self.d1[l], self.d2[l], ga, gb, sz)
+            gz = self._conv_back(li, self.d1[l], self.d2[l], ga, None, sz, fuse=True)
             li -= 1
-            self._conv_back(li, self.cat[l], self.d1[l], gb, self.gcat[l], sz)
+            self._conv_back(li, self.cat[l], self.d1[l], None, self.gcat[l], sz, gz=gz)
             # up half of the concat gradient -> gradient of the level below's output
             up_cnt = ch[l + 1] * n * sz * sz
             up2_backward(self.gcat[l][:up_cnt], ga[:up_cnt // 4], ch[l + 1] * n, sz // 2, sz // 2, stream=st)
@@ -332,9 +352,9 @@ class UNet:
                 up_cnt = ch[l + 1] * n * sz * sz
                 axpy(1.0, self.gcat[l][up_cnt:], gb[:ch[l] * n * sz * sz], stream=st)
                 ga, gb = gb, ga
-            self._conv_back(li, self.e1[l], self._skip(l), ga, gb, sz)
+            gz = self._conv_back(li, self.e1[l], self._skip(l), ga, None, sz, fuse=True)
             x = self.x0 if l == 0 else self.pooled[l - 1]
-            self._conv_back(li - 1, x, self.e1[l], gb, None if l == 0 else ga, sz)
+            self._conv_back(li - 1, x, self.e1[l], None, None if l == 0 else ga, sz, gz=gz)
 
     def loss_grad(self, F_t, S_t, wF=1.0, wS=1.0):
         """L = wF mean (F_hat - F_t)^2 + wS mean (S_hat - S_t)^2 on the last

@@ -134,6 +134,55 @@ def test_conv_backward(nn, n, cin, cout, h, w):
     assert np.allclose(db.cpu().double().numpy(), bd.grad.numpy(), rtol=1e-6, atol=1e-5)
 
 
+@pytest.mark.parametrize("n,cin,cout,h,w", [
+    # (the data gradient is a convolution from cout to cin channels)
+    (3, 5, 70, 13, 11),     # generic kernel
+    (2, 32, 64, 64, 64),    # tiled, 32-channel output tile
+    (2, 96, 64, 32, 64),    # tiled, 64-channel output tiles, a ragged one
+    (2, 32, 128, 32, 32),   # pipelined deep-layer variant, 32-channel tile
+    (2, 256, 256, 16, 16),  # pipelined deep-layer variant
+])
+def test_dgrad_relu_fused_bit_exact(nn, n, cin, cout, h, w):
+    """The data gradient with the ReLU backward of the layer below fused in
+    gives the BF16 values of the two separate calls, bit for bit."""
+    g = torch.Generator().manual_seed(31 + cin)
+    wt = bf16_round(torch.randn(cout, cin, 3, 3, generator=g) / math.sqrt(cin * 9))
+    dz = bf16_round(torch.randn(n, cout, h, w, generator=g))
+    act = torch.relu(torch.randn(n, cin, h, w, generator=g))
+    ab, dzb, wb = bits(to_cn(act)), bits(to_cn(dz)), bits(to_krsc(wt))
+    wrot = torch.empty(cout * cin * 9, dtype=torch.int16, device="cuda")
+    dx = torch.empty(cin * n * h * w, device="cuda")
+    sep = torch.empty(cin * n * h * w, dtype=torch.int16, device="cuda")
+    fused = torch.full_like(sep, 0x7fff)
+    nn.conv3x3_dgrad(dzb, wb, wrot, dx, n, cin, cout, h, w)
+    nn.relu_bf16_backward(ab, dx, sep)
+    nn.conv3x3_dgrad_relu(dzb, wb, wrot, ab, fused, n, cin, cout, h, w)
+    torch.cuda.synchronize()
+    assert torch.equal(fused.cpu(), sep.cpu())
+    assert (sep.cpu() == 0).float().mean().item() > 0.3  # the mask did zero entries
+
+
+@pytest.mark.parametrize("n,cin,cout,h,w", [(4, 32, 32, 32, 32), (2, 64, 96, 16, 32), (7, 32, 16, 8, 16)])
+def test_wgrad_contiguous_bias_single_reduction(nn, n, cin, cout, h, w):
+    """Weight and bias gradients in one buffer ([dw | db], the network's
+    parameter layout) take one reduction over both; the values equal those
+    written to separate buffers, bit for bit."""
+    g = torch.Generator().manual_seed(41 + cout)
+    x = bits(to_cn(bf16_round(torch.randn(n, cin, h, w, generator=g))))
+    dz = bits(to_cn(bf16_round(torch.randn(n, cout, h, w, generator=g))))
+    m = cout * cin * 9
+    work = torch.empty(nn.wgrad_work(n, cin, cout, h, w), device="cuda")
+    both = torch.full((m + cout,), float("nan"), device="cuda")
+    dw = torch.empty(m, device="cuda")
+    db = torch.empty(cout, device="cuda")
+    nn.conv3x3_wgrad(x, dz, both[:m], both[m:], work, n, cin, cout, h, w)
+    nn.conv3x3_wgrad(x, dz, dw, db, work, n, cin, cout, h, w)
+    torch.cuda.synchronize()
+    assert torch.equal(both[:m].cpu(), dw.cpu()) and torch.equal(both[m:].cpu(), db.cpu())
+    ref = dz.cpu().view(torch.bfloat16).double().view(cout, -1).sum(1)
+    assert np.allclose(db.cpu().double().numpy(), ref.numpy(), rtol=1e-6, atol=1e-4)
+
+
 @pytest.mark.parametrize("n,cin,cout,h,w,shift", [
     (9, 3, 5, 40, 40, 0),     # generic kernel, several pixel ranges, a ragged last one
     (5, 32, 16, 32, 32, 0),   # tiled kernel, one pixel tile per partial sum
@@ -203,11 +252,12 @@ def test_bf16_conversions_bit_exact(nn):
     assert torch.equal(back.cpu(), x.to(torch.bfloat16).to(torch.float32))
 
 
-def test_relu_and_backward(nn):
+@pytest.mark.parametrize("count", [5000, 4999])  # eight per thread; one per thread
+def test_relu_and_backward(nn, count):
     g = torch.Generator().manual_seed(5)
-    z = torch.randn(5000, generator=g)
-    da = torch.randn(5000, generator=g)
-    a = torch.empty(5000, dtype=torch.int16, device="cuda")
+    z = torch.randn(count, generator=g)
+    da = torch.randn(count, generator=g)
+    a = torch.empty(count, dtype=torch.int16, device="cuda")
     dz = torch.empty_like(a)
     nn.relu_bf16(z.cuda(), a)
     nn.relu_bf16_backward(a, da.cuda(), dz)
@@ -218,9 +268,11 @@ def test_relu_and_backward(nn):
     assert torch.equal(dz.cpu(), ref.to(torch.bfloat16).view(torch.int16))
 
 
-def test_pool_and_upsample(nn):
+# w = 14: one element per thread; 12: the vector forms; 6: up2_backward's
+# vector form only
+@pytest.mark.parametrize("planes,h,w", [(6, 10, 14), (5, 8, 12), (3, 6, 6)])
+def test_pool_and_upsample(nn, planes, h, w):
     g = torch.Generator().manual_seed(9)
-    planes, h, w = 6, 10, 14
     x = bf16_round(torch.randn(planes, h, w, generator=g))
     y = torch.empty(planes * (h // 2) * (w // 2), dtype=torch.int16, device="cuda")
     nn.pool2(bits(x), y, planes, h, w)
@@ -244,9 +296,9 @@ def test_pool_and_upsample(nn):
     assert torch.allclose(dxu.cpu().view(planes, h, w), ref_du, rtol=1e-6, atol=1e-6)
 
 
-def test_adam_axpy(nn):
+@pytest.mark.parametrize("n", [3001, 3000])  # axpy: one, then four elements per thread
+def test_adam_axpy(nn, n):
     g = torch.Generator().manual_seed(4)
-    n = 3001
     p, m, v, gr = (torch.randn(n, generator=g) for _ in range(4))
     v = v.abs()
     pd, md, vd, gd = p.cuda(), m.cuda(), v.cuda(), gr.cuda()
