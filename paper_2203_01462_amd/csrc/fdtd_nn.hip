@@ -419,6 +419,42 @@ __global__ void __launch_bounds__(BS) to_nhwc_kernel(int c, int hw, const uint16
   *(uint4 *)(y + ((size_t)img * hw + p0 + p) * c + c0 + part * 8) = uint4{pk[0], pk[1], pk[2], pk[3]};
 }
 
+// The convolution of a one-channel input (cout <= 64): a workgroup of 64 x 4
+// pixels stages its 66 x 6 input halo and the weights in LDS; each thread
+// forms its pixel's cout outputs as FP32 sums over the taps in order (plus
+// the bias), written as z and/or a (store_a).  grid (ceil(w/64), ceil(h/4), n).
+__global__ void __launch_bounds__(BS) conv1_fwd_kernel(int cout, int h, int w, const uint16_t *__restrict__ x,
+                                                      const uint16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                      float *__restrict__ z, uint16_t *__restrict__ a,
+                                                      const uint16_t *__restrict__ mask) {
+  __shared__ float xs[6][66];
+  __shared__ float ws[64 * 9];
+  const int n = blockIdx.z, nimg = gridDim.z, HW = h * w;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
+  const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+  for (int i = t; i < 6 * 66; i += BS) {
+    const int r = i / 66, q = i - r * 66, iy = y0 - 1 + r, ix = x0 - 1 + q;
+    xs[r][q] = (iy >= 0 && iy < h && ix >= 0 && ix < w) ? bf2f(x[(size_t)n * HW + (size_t)iy * w + ix]) : 0.f;
+  }
+  for (int i = t; i < cout * 9; i += BS) ws[i] = bf2f(wt[i]);
+  __syncthreads();
+  const int xx = x0 + lx, yy = y0 + ly;
+  if (xx >= w || yy >= h) return;
+  float xn[9];
+#pragma unroll
+  for (int tp = 0; tp < 9; ++tp) xn[tp] = xs[ly + tp / 3][lx + tp % 3];
+  const size_t cs = (size_t)nimg * HW, pix = (size_t)n * HW + (size_t)yy * w + xx;
+  for (int co = 0; co < cout; ++co) {
+    float v = 0.f;
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) v = fmaf(ws[co * 9 + tp], xn[tp], v);
+    v += bias ? bias[co] : 0.f;
+    const size_t o = (size_t)co * cs + pix;
+    if (z) z[o] = v;
+    if (a) a[o] = store_a(v, mask, o);
+  }
+}
+
 // Device buffer for the channel-last copy of a convolution input, one per
 // (device, stream) so that convolutions on different streams never share it;
 // kept until the process ends, grown (after the device has drained the work
@@ -448,6 +484,11 @@ uint16_t *nhwc_buffer(size_t elems, hipStream_t s) {
 // 16-byte loads of a pixel's channels), else the generic one.
 void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, const uint16_t *wt, const float *bias,
                  float *z, uint16_t *a, const uint16_t *mask, hipStream_t s) {
+  if (cin == 1 && cout <= 64) {
+    hipLaunchKernelGGL(conv1_fwd_kernel, dim3((w + 63) / 64, (h + 3) / 4, n), dim3(BS), 0, s, cout, h, w, x, wt, bias,
+                       z, a, mask);
+    return;
+  }
   if (cin % CC == 0 && h % TT == 0 && w % TT == 0 && ((uintptr_t)wt & 15) == 0) {
     const int tiles = (h / TT) * (w / TT), cot = cout <= 32 ? (cout + 31) / 32 : (cout + 63) / 64;
     uint16_t *xh = nhwc_buffer((size_t)n * cin * h * w, s);
@@ -692,10 +733,76 @@ __global__ void __launch_bounds__(BS) conv_wgrad_mfma_kernel(int nimg, int cin, 
   }
 }
 
+// Weight gradient of a layer with one input channel and at most 32 output
+// channels (the network's first layer), h % 8 == 0, w % 64 == 0:
+// part[split * stride + co * 9 + tap] = sum over the split's 8 x 64 pixel
+// tiles of dz[co][q] x[q shifted by tap], bpart[split * stride + co] = the
+// sum of dz[co][q] (FP32).  Wavefront wv owns channels 8 wv .. 8 wv + 7, its
+// lanes the tile's columns; a fixed butterfly combines the lanes' sums.
+// grid (splits).
+constexpr int C1Y = 8;
+__global__ void __launch_bounds__(BS) conv1_wgrad_kernel(int nimg, int cout, int h, int w,
+                                                        const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
+                                                        float *__restrict__ part, int64_t stride, int tiles_per_split,
+                                                        float *__restrict__ bpart) {
+  __shared__ float xs[C1Y + 2][66];
+  const int HW = h * w;
+  const size_t P = (size_t)nimg * HW;
+  const int tx = w / 64, tiles_img = (h / C1Y) * tx, tiles = nimg * tiles_img;
+  const int split = blockIdx.x, T0 = split * tiles_per_split, T1 = min(tiles, T0 + tiles_per_split);
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  float acc[8][9], bacc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    bacc[c] = 0.f;
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) acc[c][tp] = 0.f;
+  }
+  for (int T = T0; T < T1; ++T) {
+    const int n = T / tiles_img, rem = T - n * tiles_img;
+    const int y0 = (rem / tx) * C1Y, x0 = (rem % tx) * 64;
+    __syncthreads();  // the previous tile's rows are read
+    for (int i = t; i < (C1Y + 2) * 66; i += BS) {
+      const int r = i / 66, q = i - r * 66, iy = y0 - 1 + r, ix = x0 - 1 + q;
+      xs[r][q] = (iy >= 0 && iy < h && ix >= 0 && ix < w) ? bf2f(x[(size_t)n * HW + (size_t)iy * w + ix]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int r = 0; r < C1Y; ++r) {
+      float xn[9];
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) xn[tp] = xs[r + tp / 3][lane + tp % 3];
+      const size_t pix = (size_t)n * HW + (size_t)(y0 + r) * w + x0 + lane;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int co = 8 * wv + c;
+        const float d = co < cout ? bf2f(dz[(size_t)co * P + pix]) : 0.f;
+        bacc[c] += d;
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) acc[c][tp] = fmaf(d, xn[tp], acc[c][tp]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int co = 8 * wv + c;
+#pragma unroll
+    for (int tp = 0; tp < 10; ++tp) {
+      float v = tp < 9 ? acc[c][tp] : bacc[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0 && co < cout) {
+        if (tp < 9) part[(size_t)split * stride + co * 9 + tp] = v;
+        else if (bpart) bpart[(size_t)split * stride + co] = v;
+      }
+    }
+  }
+}
+
 // Split plan of the weight gradient: which kernel, how many partial sums,
 // pixels (generic) or pixel tiles (tiled) per split.
 struct WgradPlan {
-  bool tiled;
+  bool tiled, c1;  // LDS-tiled matrix-core kernel; one-input-channel kernel
   int splits, chunk;
 };
 
@@ -706,6 +813,13 @@ inline int wgrad_ct(int cout) { return cout <= 32 ? 32 : 64; }
 // per tiled workgroup so the partial sums stay few.
 WgradPlan wgrad_plan(int n, int cin, int cout, int h, int w) {
   WgradPlan pl{};
+  if (cin == 1 && cout <= 32 && h % C1Y == 0 && w % 64 == 0) {
+    const int tiles = n * (h / C1Y) * (w / 64);
+    pl.c1 = true;
+    pl.chunk = std::min(2, tiles);
+    pl.splits = (tiles + pl.chunk - 1) / pl.chunk;
+    return pl;
+  }
   if (cin % 32 == 0 && h % GY == 0 && w % GX == 0) {
     const int ct = wgrad_ct(cout);
     const int groups = ((cout + ct - 1) / ct) * (cin / 32);
@@ -1009,6 +1123,32 @@ __global__ void __launch_bounds__(BS) gap_linear_back_a_kernel(int nimg, int c, 
 }
 
 // dwl[c] = sum_n dout[n] mean_p a[c][n][p]; dbl = sum_n dout[n].  One workgroup per channel (+1 for the bias).
+// The same for hw % 64 == 0: one 1024-thread workgroup per image, wavefront
+// wv takes channels wv, wv + 16, ..., its lanes pixels lane + 64 k (FP64
+// sums, a fixed order).
+__global__ void __launch_bounds__(1024) gap_linear64_kernel(int nimg, int c, int hw, const uint16_t *__restrict__ a,
+                                                           const float *__restrict__ wl, const float *__restrict__ bl,
+                                                           float *__restrict__ out) {
+  __shared__ double lds[16];
+  const int n = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double v = 0;
+  for (int ch = wv; ch < c; ch += 16) {
+    const uint16_t *row = a + ((size_t)ch * nimg + n) * hw;
+    double sp = 0;
+#pragma unroll 4
+    for (int p = lane; p < hw; p += 64) sp += bf2f(row[p]);
+    v += (double)wl[ch] * sp;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int k = 0; k < 16; ++k) s += lds[k];
+    out[n] = (float)(s / hw + bl[0]);
+  }
+}
+
 __global__ void __launch_bounds__(BS) gap_linear_back_w_kernel(int nimg, int c, int hw, const uint16_t *__restrict__ a,
                                                               const float *__restrict__ dout, float *__restrict__ dwl,
                                                               float *__restrict__ dbl) {
@@ -1116,7 +1256,18 @@ void wgrad_run(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const
     const int64_t P = (int64_t)n * h * w;
     const WgradPlan pl = wgrad_plan(n, cin, cout, h, w);
     const int64_t m = (int64_t)cout * K;
-    if (pl.tiled && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0) {
+    if (pl.c1) {
+      // partial rows [split][m weight sums | cout bias sums]
+      const int64_t stride = m + cout;
+      hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(pl.splits), dim3(BS), 0, s, n, cout, h, w, x, dz, work, stride,
+                         pl.chunk, db ? work + m : nullptr);
+      if (db && db == dw + m) {
+        launch_split_sum(work, pl.splits, stride, m + cout, dw, s);
+      } else {
+        launch_split_sum(work, pl.splits, stride, m, dw, s);
+        if (db) launch_split_sum(work + m, pl.splits, stride, cout, db, s);
+      }
+    } else if (pl.tiled && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0) {
       // partial rows [split][m weight sums | cout bias sums]
       const int64_t stride = m + cout;
       const int ct = wgrad_ct(cout);
@@ -1322,7 +1473,10 @@ fdtd_status fdtd_nn_gap_linear(int32_t n, int32_t c, int32_t hw, const uint16_t 
                                float *out, void *stream) {
   return nguard([&] {
     need(n > 0 && c > 0 && hw > 0 && a && wl && bl && out);
-    hipLaunchKernelGGL(gap_linear_kernel, dim3(n), dim3(BS), 0, (hipStream_t)stream, n, c, hw, a, wl, bl, out);
+    if (hw % 64 == 0)
+      hipLaunchKernelGGL(gap_linear64_kernel, dim3(n), dim3(1024), 0, (hipStream_t)stream, n, c, hw, a, wl, bl, out);
+    else
+      hipLaunchKernelGGL(gap_linear_kernel, dim3(n), dim3(BS), 0, (hipStream_t)stream, n, c, hw, a, wl, bl, out);
     FDTD_HIP(hipGetLastError());
   });
 }

@@ -70,6 +70,12 @@ CONV_CASES = [
     (2, 96, 32, 16, 48),
     (1, 32, 20, 16, 16),
     (2, 256, 256, 16, 16),
+    # one input channel (the network's first layer): the direct forward kernel;
+    # the weight gradient's one-channel kernel (h % 8, w % 64, cout <= 32,
+    # a ragged last group of eight channels) or the generic one
+    (2, 1, 32, 16, 64),
+    (3, 1, 20, 8, 128),
+    (1, 1, 48, 9, 70),
 ]
 
 
@@ -162,7 +168,8 @@ def test_dgrad_relu_fused_bit_exact(nn, n, cin, cout, h, w):
     assert (sep.cpu() == 0).float().mean().item() > 0.3  # the mask did zero entries
 
 
-@pytest.mark.parametrize("n,cin,cout,h,w", [(4, 32, 32, 32, 32), (2, 64, 96, 16, 32), (7, 32, 16, 8, 16)])
+@pytest.mark.parametrize("n,cin,cout,h,w", [(4, 32, 32, 32, 32), (2, 64, 96, 16, 32), (7, 32, 16, 8, 16),
+                                             (4, 1, 32, 16, 128)])
 def test_wgrad_contiguous_bias_single_reduction(nn, n, cin, cout, h, w):
     """Weight and bias gradients in one buffer ([dw | db], the network's
     parameter layout) take one reduction over both; the values equal those
@@ -322,9 +329,10 @@ def test_adam_axpy(nn, n):
     assert np.allclose(yd.cpu().double(), y.double() - 0.5 * G, rtol=1e-6, atol=1e-7)
 
 
-def test_head_and_loss(nn):
+@pytest.mark.parametrize("c,hw", [(24, 49), (40, 128)])  # one-pass and 64-pixel-row forms of the head
+def test_head_and_loss(nn, c, hw):
     g = torch.Generator().manual_seed(12)
-    n, c, hw = 5, 24, 49
+    n = 5
     a = bf16_round(torch.relu(torch.randn(c, n, hw, generator=g)))
     wl = torch.randn(c, generator=g)
     bl = torch.randn(1, generator=g)
