@@ -38,18 +38,23 @@ HBM_PEAK_GBS = 8000.0
 # the summaries live in profiles/.
 SRC_2D = ["paper_2203_01462_amd/csrc/fdtd_2d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 SRC_3D = ["paper_2203_01462_amd/csrc/fdtd_3d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
+SRC_TE = ["paper_2203_01462_amd/csrc/fdtd_te.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "770ae89153743a60",
+    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "ef97cdd071e768d8",
                         "fwd": 77.2e6, "adj": 81.5e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step of all 64 instances = one step2d_batch_mix_kernel launch
-    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "770ae89153743a60",
+    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "ef97cdd071e768d8",
                          "fwd": 500.0e6, "adj": 521.3e6,
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = step3d_general (three launches) + step3d_plain
-    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "3a4145ecc7565a2c",
-                       "fwd": 1301.7e6, "adj": 1337.2e6,
+    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "79ccde80b8f7f326",
+                       "fwd": 1301.2e6, "adj": 1336.7e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
+    # one time step = one step_te_fwd / step_te_adj launch
+    "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "4e9ee27581bb2579",
+                       "fwd": 147.8e6, "adj": 157.2e6,
+                       "profile": "profiles/step_te_te2d_2048_fp32.md"},
 }
 
 
