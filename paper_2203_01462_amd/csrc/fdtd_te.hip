@@ -16,13 +16,17 @@
 // transpose), driven by the gap source, and accumulates the per-edge
 // sensitivity of eq. (25) folded with eq. (27) into one FP64 sum.
 //
-// One thread per node (i, j): it updates H_z(i, j), E_x(i, j) and E_y(i, j),
-// recomputing the new H_z of its lower and left neighbours from the read
-// copy (every array a halo reads has a read and a write copy).  Workgroups
-// of 64 x 4 nodes.  This polarization's workloads are small (the paper's 2D
-// designs), so the step is a plain per-step kernel without temporal
-// blocking.
-//
+// One lane per column: a wavefront covers 64 columns, lane 0 the halo
+// column left of the 63 it updates, and walks a segment of TER rows; at node
+// (i, j) a lane updates H_z(i, j), E_x(i, j) and E_y(i, j).  The lower
+// neighbour's new H_z is the lane's own from the previous row (the segment's
+// first row recomputes it from the read copy), the left neighbour's comes
+// from lane - 1 by a cross-lane shuffle; the next row's field values are
+// loaded before the current row's arithmetic.  Every array a halo reads has
+// a read and a write copy.  This polarization's workloads are small (the
+// paper's 2D designs), so the step is a plain per-step kernel without
+// temporal blocking.
+
 // Design layout (per edge): the design box of dnx x dny cells holds its E_x
 // edges [dny+1][dnx] (density indices 0 .. ndx-1) followed by its E_y edges
 // [dny][dnx+1]; the gap box's edges likewise give the monitor order.
@@ -31,7 +35,15 @@
 namespace fdtd {
 namespace {
 
-constexpr int TEX = 64, TEY = 4;
+#ifndef FDTD_TE_ROWS
+#define FDTD_TE_ROWS 4
+#endif
+#ifndef FDTD_TE_WAVES
+#define FDTD_TE_WAVES 4
+#endif
+// lanes (= columns, the first a halo) per wavefront, wavefronts per
+// workgroup, rows per wavefront
+constexpr int TEX = 64, TEW = FDTD_TE_WAVES, TER = FDTD_TE_ROWS, TEC = TEX - 1;
 
 __device__ __forceinline__ bool te_pml_e(int i, int n, int P) { return P > 0 && (i < P || i > n - 1 - P); }
 __device__ __forceinline__ bool te_pml_h(int i, int n, int P) { return P > 0 && (i < P || i >= n - 1 - P); }
@@ -91,11 +103,14 @@ __device__ __forceinline__ T te_e(const Step2D<T> &p, int n, int comp, int i, in
 // Forward.  Copy 0 read, copy 1 written.  Memories: pex = H_z's x
 // difference, pey = H_z's y difference, phx = E_x's (y), phy = E_y's (x).
 template <typename T>
-__global__ void __launch_bounds__(TEX * TEY) step_te_fwd(const Step2D<T> p, int n) {
-  const int i = blockIdx.x * TEX + (threadIdx.x % TEX), j = blockIdx.y * TEY + (threadIdx.x / TEX);
+__global__ void __launch_bounds__(TEX * TEW) step_te_fwd(const Step2D<T> p, int n) {
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = (int)blockIdx.x * TEC + lane - 1, j0 = (blockIdx.y * TEW + wv) * TER;
   const int nx = p.nx, ny = p.ny, P = p.P;
-  if (i >= nx || j >= ny) return;
-  const size_t pitch = p.pitch, q = (size_t)j * pitch + i;
+  // rows with an H_z cell or an E edge to update: 0 .. ny-2
+  if (j0 > ny - 2) return;  // whole wavefront
+  const int j1 = min(j0 + TER, ny - 1);
+  const size_t pitch = p.pitch;
   const T *__restrict__ Ex = p.ez[0];
   const T *__restrict__ Ey = p.hx[0];
   const T *__restrict__ Hz = p.hy[0];
@@ -103,76 +118,120 @@ __global__ void __launch_bounds__(TEX * TEY) step_te_fwd(const Step2D<T> p, int 
   const T *__restrict__ mhy = p.pey[0];
   const T *__restrict__ mex = p.phx[0];
   const T *__restrict__ mey = p.phy[0];
+  T *__restrict__ Exw = p.ez[1];
+  T *__restrict__ Eyw = p.hx[1];
+  T *__restrict__ Hzw = p.hy[1];
+  T *__restrict__ mhxw = p.pex[1];
+  T *__restrict__ mhyw = p.pey[1];
+  T *__restrict__ mexw = p.phx[1];
+  T *__restrict__ meyw = p.phy[1];
   const T *ei = p.einc + (size_t)n * p.L, *hi = p.hinc + (size_t)n * p.L;
-  // new H_z at cell (a, b) (a <= nx-2, b <= ny-2) and its memories
-  auto hz_new = [&](int a, int b, T &sx, T &sy) {
-    const size_t r = (size_t)b * pitch + a;
-    const T dEy = Ey[r + 1] - Ey[r];
-    const T dEx = Ex[r + pitch] - Ex[r];
-    T tx = dEy * p.ikxh[a], ty = dEx * p.ikyh[b];
+  const bool hcol = i >= 0 && i <= nx - 2;  // the column holds H_z cells and E_x edges
+  const bool own = lane > 0 && hcol;        // ... and is updated by this lane
+  const bool ecol = own && i >= 1;          // ... with E_y edges
+  const bool pmh = hcol && te_pml_h(i, nx, P), pme = ecol && te_pml_e(i, nx, P);
+  const T kxh = hcol ? p.ikxh[i] : T(0), kxe = ecol ? p.ikxe[i] : T(0);
+  const bool tfx = p.tf_on && i >= p.ia && i <= p.ib - 1;
+  // new H_z at cell (i, b) from its five inputs (and its memories)
+  auto hz_of = [&](int b, T eyc, T eyr, T exc, T exn, T hzc, T &sx, T &sy) {
+    const size_t r = (size_t)b * pitch + i;
+    const T dEy = eyr - eyc;
+    const T dEx = exn - exc;
+    T tx = dEy * kxh, ty = dEx * p.ikyh[b];
     sx = T(0);
     sy = T(0);
-    if (te_pml_h(a, nx, P)) { sx = p.bxh[a] * mhx[r] + p.axh[a] * dEy; tx += sx; }
+    if (pmh) { sx = p.bxh[i] * mhx[r] + p.axh[i] * dEy; tx += sx; }
     if (te_pml_h(b, ny, P)) { sy = p.byh[b] * mhy[r] + p.ayh[b] * dEx; ty += sy; }
-    T h = Hz[r] - p.chx * (tx - ty);
+    T h = hzc - p.chx * (tx - ty);
     // the H_z rows just outside the box read E_x on its lower and upper lines
-    if (p.tf_on && a >= p.ia && a <= p.ib - 1) {
+    if (tfx) {
       if (b == p.ja - 1) h -= p.chx * ei[p.ja - p.jref];
       if (b == p.jb) h += p.chx * ei[p.jb - p.jref];
     }
     return h;
   };
-  const bool hin = i <= nx - 2 && j <= ny - 2;
-  T h00 = T(0), sx, sy;
-  if (hin) {
-    h00 = hz_new(i, j, sx, sy);
-    p.hy[1][q] = h00;
-    if (te_pml_h(i, nx, P)) p.pex[1][q] = sx;
-    if (te_pml_h(j, ny, P)) p.pey[1][q] = sy;
+  // the lane's column, row j: E_y(i), E_y(i+1), E_x(j), E_x(j+1), H_z
+  T eyc = T(0), eyr = T(0), exc = T(0), exn = T(0), hzc = T(0);
+  auto load_row = [&](int j, T &a, T &b, T &c, T &d, T &e) {
+    const size_t r = (size_t)j * pitch + i;
+    a = Ey[r];
+    b = Ey[r + 1];
+    c = Ex[r];
+    d = Ex[r + pitch];
+    e = Hz[r];
+  };
+  // new H_z of the row below the segment
+  T hb = T(0);
+  if (hcol && j0 >= 1) {
+    T a, b, c, d, e, t0, t1;
+    load_row(j0 - 1, a, b, c, d, e);
+    hb = hz_of(j0 - 1, a, b, c, d, e, t0, t1);
   }
-  // E_x(i, j): curl = dH_z/dy; incident H_z = -(the line's transverse H)
-  if (i <= nx - 2 && j >= 1 && j <= ny - 2) {
-    T t0, t1;
-    const T d = h00 - hz_new(i, j - 1, t0, t1);
-    T c = d * p.ikye[j];
-    if (te_pml_e(j, ny, P)) {
-      const T s = p.bye[j] * mex[q] + p.aye[j] * d;
-      p.phx[1][q] = s;
-      c += s;
+  if (hcol) load_row(j0, eyc, eyr, exc, exn, hzc);
+  for (int j = j0; j < j1; ++j) {
+    const size_t q = (size_t)j * pitch + i;
+    // the next row's values, in flight during this row's arithmetic
+    T eyc2 = T(0), eyr2 = T(0), exc2 = T(0), exn2 = T(0), hzc2 = T(0);
+    if (hcol && j + 1 < j1) load_row(j + 1, eyc2, eyr2, exc2, exn2, hzc2);
+    T h00 = T(0), sx = T(0), sy = T(0);
+    if (hcol) h00 = hz_of(j, eyc, eyr, exc, exn, hzc, sx, sy);
+    // the left neighbour's new H_z
+    const T hl = __shfl_up(h00, 1, 64);
+    if (own) {
+      Hzw[q] = h00;
+      if (pmh) mhxw[q] = sx;
+      if (te_pml_h(j, ny, P)) mhyw[q] = sy;
+      // E_x(i, j): curl = dH_z/dy; incident H_z = -(the line's transverse H)
+      if (j >= 1) {
+        const T d = h00 - hb;
+        T c = d * p.ikye[j];
+        if (te_pml_e(j, ny, P)) {
+          const T s = p.bye[j] * mex[q] + p.aye[j] * d;
+          mexw[q] = s;
+          c += s;
+        }
+        if (tfx) {
+          if (j == p.ja) c += hi[p.ja - 1 - p.jref];
+          if (j == p.jb) c -= hi[p.jb - p.jref];
+        }
+        Exw[q] = te_e<T, false>(p, n, 0, i, j, exc, c);
+      }
+      // E_y(i, j): curl = -dH_z/dx
+      if (ecol) {
+        const T d = h00 - hl;
+        T g = d * kxe;
+        if (pme) {
+          const T s = p.bxe[i] * mey[q] + p.axe[i] * d;
+          meyw[q] = s;
+          g += s;
+        }
+        T c = -g;
+        if (p.tf_on && j >= p.ja && j <= p.jb - 1) {
+          if (i == p.ia) c -= hi[j - p.jref];
+          if (i == p.ib) c += hi[j - p.jref];
+        }
+        Eyw[q] = te_e<T, false>(p, n, 1, i, j, eyc, c);
+      }
     }
-    if (p.tf_on && i >= p.ia && i <= p.ib - 1) {
-      if (j == p.ja) c += hi[p.ja - 1 - p.jref];
-      if (j == p.jb) c -= hi[p.jb - p.jref];
-    }
-    p.ez[1][q] = te_e<T, false>(p, n, 0, i, j, Ex[q], c);
-  }
-  // E_y(i, j): curl = -dH_z/dx
-  if (i >= 1 && i <= nx - 2 && j <= ny - 2) {
-    T t0, t1;
-    const T d = h00 - hz_new(i - 1, j, t0, t1);
-    T g = d * p.ikxe[i];
-    if (te_pml_e(i, nx, P)) {
-      const T s = p.bxe[i] * mey[q] + p.axe[i] * d;
-      p.phy[1][q] = s;
-      g += s;
-    }
-    T c = -g;
-    if (p.tf_on && j >= p.ja && j <= p.jb - 1) {
-      if (i == p.ia) c -= hi[j - p.jref];
-      if (i == p.ib) c += hi[j - p.jref];
-    }
-    p.hx[1][q] = te_e<T, false>(p, n, 1, i, j, Ey[q], c);
+    hb = h00;
+    eyc = eyc2;
+    eyr = eyr2;
+    exc = exc2;
+    exn = exn2;
+    hzc = hzc2;
   }
 }
 
 // Adjoint step m = n: copy 0 holds E*^{m+1/2}, H_z*^{m+1} and the memories
 // (nu), copy 1 receives E*^{m-1/2}, H_z*^m.
 template <typename T>
-__global__ void __launch_bounds__(TEX * TEY) step_te_adj(const Step2D<T> p, int n) {
-  const int i = blockIdx.x * TEX + (threadIdx.x % TEX), j = blockIdx.y * TEY + (threadIdx.x / TEX);
+__global__ void __launch_bounds__(TEX * TEW) step_te_adj(const Step2D<T> p, int n) {
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = (int)blockIdx.x * TEC + lane - 1, j0 = (blockIdx.y * TEW + wv) * TER;
   const int nx = p.nx, ny = p.ny, P = p.P;
-  if (i >= nx || j >= ny) return;
-  const size_t pitch = p.pitch, q = (size_t)j * pitch + i;
+  if (j0 > ny - 2) return;  // whole wavefront
+  const int j1 = min(j0 + TER, ny - 1);
+  const size_t pitch = p.pitch;
   const T *__restrict__ Ex = p.ez[0];
   const T *__restrict__ Ey = p.hx[0];
   const T *__restrict__ Hz = p.hy[0];
@@ -180,49 +239,84 @@ __global__ void __launch_bounds__(TEX * TEY) step_te_adj(const Step2D<T> p, int 
   const T *__restrict__ mhy = p.pey[0];
   const T *__restrict__ mex = p.phx[0];
   const T *__restrict__ mey = p.phy[0];
+  T *__restrict__ Exw = p.ez[1];
+  T *__restrict__ Eyw = p.hx[1];
+  T *__restrict__ Hzw = p.hy[1];
+  T *__restrict__ mhxw = p.pex[1];
+  T *__restrict__ mhyw = p.pey[1];
+  T *__restrict__ mexw = p.phx[1];
+  T *__restrict__ meyw = p.phy[1];
+  const bool hcol = i >= 0 && i <= nx - 2;
+  const bool own = lane > 0 && hcol;
+  const bool ecol = own && i >= 1;
+  const bool pmh = hcol && te_pml_h(i, nx, P);
   // E* graded by the E update's absorber profile (new memory from E* itself);
-  // zero on the walls and the unused slots
-  auto gx = [&](int a, int b) {
-    if (a > nx - 2 || b < 1 || b > ny - 2) return T(0);
-    const size_t r = (size_t)b * pitch + a;
-    const T e = Ex[r];
-    return e * p.ikye[b] + (te_pml_e(b, ny, P) ? p.bye[b] * mex[r] + p.aye[b] * e : T(0));
+  // zero on the walls and the unused slots.  gx: E_x* at (i, b), value e;
+  // gy: E_y* at (a, b) in this row, value e.
+  auto gx = [&](int b, T e) {
+    if (!hcol || b < 1 || b > ny - 2) return T(0);
+    return e * p.ikye[b] + (te_pml_e(b, ny, P) ? p.bye[b] * mex[(size_t)b * pitch + i] + p.aye[b] * e : T(0));
   };
-  auto gy = [&](int a, int b) {
-    if (a < 1 || a > nx - 2 || b > ny - 2) return T(0);
-    const size_t r = (size_t)b * pitch + a;
-    const T e = Ey[r];
-    return e * p.ikxe[a] + (te_pml_e(a, nx, P) ? p.bxe[a] * mey[r] + p.axe[a] * e : T(0));
+  auto gy = [&](int a, int b, T e) {
+    if (a < 1 || a > nx - 2) return T(0);
+    return e * p.ikxe[a] + (te_pml_e(a, nx, P) ? p.bxe[a] * mey[(size_t)b * pitch + a] + p.axe[a] * e : T(0));
   };
-  // new H_z* at cell (a, b): the forward curl-E update on the graded E*
-  auto hz_new = [&](int a, int b) {
-    const size_t r = (size_t)b * pitch + a;
-    return Hz[r] - p.chx * ((gy(a + 1, b) - gy(a, b)) - (gx(a, b + 1) - gx(a, b)));
+  // new H_z* at cell (i, b): the forward curl-E update on the graded E*
+  auto hz_of = [&](int b, T eyc, T eyr, T exc, T exn, T hzc) {
+    return hzc - p.chx * ((gy(i + 1, b, eyr) - gy(i, b, eyc)) - (gx(b + 1, exn) - gx(b, exc)));
   };
   // H_z* graded by the H update's profile along x (for dH/dx) and y (dH/dy)
-  auto hxg = [&](int a, int b, T h) {
-    return h * p.ikxh[a] + (te_pml_h(a, nx, P) ? p.bxh[a] * mhx[(size_t)b * pitch + a] + p.axh[a] * h : T(0));
+  auto hxg = [&](int b, T h) {
+    return h * p.ikxh[i] + (pmh ? p.bxh[i] * mhx[(size_t)b * pitch + i] + p.axh[i] * h : T(0));
   };
-  auto hyg = [&](int a, int b, T h) {
-    return h * p.ikyh[b] + (te_pml_h(b, ny, P) ? p.byh[b] * mhy[(size_t)b * pitch + a] + p.ayh[b] * h : T(0));
+  auto hyg = [&](int b, T h) {
+    return h * p.ikyh[b] + (te_pml_h(b, ny, P) ? p.byh[b] * mhy[(size_t)b * pitch + i] + p.ayh[b] * h : T(0));
   };
-  // own memories of E* (driven by E* of copy 0)
-  if (i <= nx - 2 && j >= 1 && j <= ny - 2 && te_pml_e(j, ny, P)) p.phx[1][q] = p.bye[j] * mex[q] + p.aye[j] * Ex[q];
-  if (i >= 1 && i <= nx - 2 && j <= ny - 2 && te_pml_e(i, nx, P)) p.phy[1][q] = p.bxe[i] * mey[q] + p.axe[i] * Ey[q];
-  T h00 = T(0);
-  if (i <= nx - 2 && j <= ny - 2) {
-    h00 = hz_new(i, j);
-    p.hy[1][q] = h00;
-    if (te_pml_h(i, nx, P)) p.pex[1][q] = p.bxh[i] * mhx[q] + p.axh[i] * h00;
-    if (te_pml_h(j, ny, P)) p.pey[1][q] = p.byh[j] * mhy[q] + p.ayh[j] * h00;
+  T eyc = T(0), eyr = T(0), exc = T(0), exn = T(0), hzc = T(0);
+  auto load_row = [&](int j, T &a, T &b, T &c, T &d, T &e) {
+    const size_t r = (size_t)j * pitch + i;
+    a = Ey[r];
+    b = Ey[r + 1];
+    c = Ex[r];
+    d = Ex[r + pitch];
+    e = Hz[r];
+  };
+  // y-graded new H_z* of the row below the segment
+  T gb = T(0);
+  if (hcol && j0 >= 1) {
+    T a, b, c, d, e;
+    load_row(j0 - 1, a, b, c, d, e);
+    gb = hyg(j0 - 1, hz_of(j0 - 1, a, b, c, d, e));
   }
-  if (i <= nx - 2 && j >= 1 && j <= ny - 2) {
-    const T c = hyg(i, j, h00) - hyg(i, j - 1, hz_new(i, j - 1));
-    p.ez[1][q] = te_e<T, true>(p, n, 0, i, j, Ex[q], c);
-  }
-  if (i >= 1 && i <= nx - 2 && j <= ny - 2) {
-    const T c = -(hxg(i, j, h00) - hxg(i - 1, j, hz_new(i - 1, j)));
-    p.hx[1][q] = te_e<T, true>(p, n, 1, i, j, Ey[q], c);
+  if (hcol) load_row(j0, eyc, eyr, exc, exn, hzc);
+  for (int j = j0; j < j1; ++j) {
+    const size_t q = (size_t)j * pitch + i;
+    T eyc2 = T(0), eyr2 = T(0), exc2 = T(0), exn2 = T(0), hzc2 = T(0);
+    if (hcol && j + 1 < j1) load_row(j + 1, eyc2, eyr2, exc2, exn2, hzc2);
+    T h00 = T(0), gyo = T(0), gxo = T(0);
+    if (hcol) {
+      h00 = hz_of(j, eyc, eyr, exc, exn, hzc);
+      gyo = hyg(j, h00);
+      gxo = hxg(j, h00);
+    }
+    // the left neighbour's x-graded new H_z*
+    const T gl = __shfl_up(gxo, 1, 64);
+    if (own) {
+      // own memories of E* (driven by E* of copy 0)
+      if (j >= 1 && te_pml_e(j, ny, P)) mexw[q] = p.bye[j] * mex[q] + p.aye[j] * exc;
+      if (ecol && te_pml_e(i, nx, P)) meyw[q] = p.bxe[i] * mey[q] + p.axe[i] * eyc;
+      Hzw[q] = h00;
+      if (pmh) mhxw[q] = p.bxh[i] * mhx[q] + p.axh[i] * h00;
+      if (te_pml_h(j, ny, P)) mhyw[q] = p.byh[j] * mhy[q] + p.ayh[j] * h00;
+      if (j >= 1) Exw[q] = te_e<T, true>(p, n, 0, i, j, exc, gyo - gb);
+      if (ecol) Eyw[q] = te_e<T, true>(p, n, 1, i, j, eyc, -(gxo - gl));
+    }
+    gb = gyo;
+    eyc = eyc2;
+    eyr = eyr2;
+    exc = exc2;
+    exn = exn2;
+    hzc = hzc2;
   }
 }
 
@@ -230,9 +324,9 @@ __global__ void __launch_bounds__(TEX * TEY) step_te_adj(const Step2D<T> p, int 
 
 template <typename T>
 void launch_step_te(const Step2D<T> &p, int n, bool adjoint, hipStream_t s) {
-  const dim3 grid((unsigned)((p.nx + TEX - 1) / TEX), (unsigned)((p.ny + TEY - 1) / TEY));
-  if (adjoint) hipLaunchKernelGGL(step_te_adj<T>, grid, dim3(TEX * TEY), 0, s, p, n);
-  else hipLaunchKernelGGL(step_te_fwd<T>, grid, dim3(TEX * TEY), 0, s, p, n);
+  const dim3 grid((unsigned)((p.nx + TEC - 1) / TEC), (unsigned)((p.ny + TEW * TER - 1) / (TEW * TER)));
+  if (adjoint) hipLaunchKernelGGL(step_te_adj<T>, grid, dim3(TEX * TEW), 0, s, p, n);
+  else hipLaunchKernelGGL(step_te_fwd<T>, grid, dim3(TEX * TEW), 0, s, p, n);
 }
 
 template void launch_step_te<float>(const Step2D<float> &, int, bool, hipStream_t);
