@@ -124,7 +124,7 @@ def test_c2_full_directional_derivative(gpu):
                    strict=False)
 def test_c2_full_fp32_against_fp64(gpu):
     """The FP32 build at the full 2048^2 x 20000-step size against the FP64
-    build, at the spec bars 1e-4 (F) and 1e-3 (gradient).  Measured:
+    build, at the FP32 bars 1e-4 (F) and 1e-3 (gradient).  Measured:
     1.5e-4 and 2.5e-2 -- the gap field is below FP32's resolution of the
     background field; FP32 parity on the 512^2 grids is ~1e-6 / ~2e-4."""
     w = W.c2()
