@@ -32,6 +32,14 @@
  * never abort; EINVAL for non-positive sizes or missing pointers.  Sums over
  * the batch (weight and bias gradients, the head, the loss) are taken in a
  * fixed order, so results do not depend on scheduling.
+ *
+ * Device memory: the convolutions (forward and data gradient) on their
+ * matrix-core path stage the input through a channel-last copy held by the
+ * library, one buffer per (device, stream), allocated on first use and grown
+ * (after a device synchronisation) when a larger input arrives; it is kept
+ * until the process ends.  Calls on one stream are ordered, so they share
+ * it safely; calls on different streams use different buffers.  Only
+ * fdtd_nn_conv3x3_wgrad_noalloc allocates nothing.
  */
 #ifndef FDTD_NN_H
 #define FDTD_NN_H
