@@ -60,23 +60,40 @@ __device__ __forceinline__ void load_mask16(uint16_t (&mk)[4][4], int co0, int c
 }
 
 // Output of that block: z = v (FP32) and/or a = relu(v) (BF16), or with a
-// mask (mk loaded by load_mask16) a = v * (mask > 0) (BF16).
+// mask (mk loaded by load_mask16) a = v * (mask > 0) (BF16).  The values are
+// formed first and stored back to back (a store between loads and arithmetic
+// that reuse its registers would wait for it to complete).
 __device__ __forceinline__ void tile_out16(const f4 (&acc)[4], const uint16_t (&mk)[4][4], bool masked, int co0,
                                            int cout, int kq, size_t pix0, int w, size_t cs,
                                            const float *__restrict__ bias, float *__restrict__ z,
                                            uint16_t *__restrict__ a) {
+  // the lane's four biases, loaded together ahead of the stores
+  float bv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bv[j] = (bias && co0 + 4 * kq + j < cout) ? bias[co0 + 4 * kq + j] : 0.f;
+  float v[4][4];
+  uint16_t b[4][4];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int co = co0 + 4 * kq + j;
-      if (co < cout) {
-        const float v = acc[s][j] + (bias ? bias[co] : 0.f);
-        const size_t o = (size_t)co * cs + pix0 + (size_t)s * w;
-        if (z) z[o] = v;
-        if (a) a[o] = masked ? f2bf(bf2f(mk[s][j]) > 0.f ? v : 0.f) : f2bf(fmaxf(v, 0.f));
-      }
+      v[s][j] = acc[s][j] + bv[j];
+      b[s][j] = masked ? f2bf(bf2f(mk[s][j]) > 0.f ? v[s][j] : 0.f) : f2bf(fmaxf(v[s][j], 0.f));
     }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int co = co0 + 4 * kq + j;
+    if (co >= cout) continue;
+    const size_t o = (size_t)co * cs + pix0;
+    if (z) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) z[o + (size_t)s * w] = v[s][j];
+    }
+    if (a) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[o + (size_t)s * w] = b[s][j];
+    }
+  }
 }
 
 __device__ __forceinline__ double block_sum(double v, double *lds) {
