@@ -800,18 +800,24 @@ __global__ void __launch_bounds__(BS) conv1_wgrad_kernel(int nimg, int cout, int
       }
     }
   }
+  // reduce all 80 sums first, then store them back to back
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    const int co = 8 * wv + c;
 #pragma unroll
-    for (int tp = 0; tp < 10; ++tp) {
-      float v = tp < 9 ? acc[c][tp] : bacc[c];
+    for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0 && co < cout) {
-        if (tp < 9) part[(size_t)split * stride + co * 9 + tp] = v;
-        else if (bpart) bpart[(size_t)split * stride + co] = v;
-      }
+      for (int o = 32; o > 0; o >>= 1) acc[c][tp] += __shfl_xor(acc[c][tp], o, 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bacc[c] += __shfl_xor(bacc[c], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int co = 8 * wv + c;
+      if (co >= cout) continue;
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) part[(size_t)split * stride + co * 9 + tp] = acc[c][tp];
+      if (bpart) bpart[(size_t)split * stride + co] = bacc[c];
     }
   }
 }
