@@ -69,10 +69,31 @@ __device__ __forceinline__ void tile_of(int bid, int nbx, int nby, int &tx, int 
   ty = t / nbx;
 }
 
+// Every array a step touches is device memory.  The batched kernels copy
+// their parameter blocks from device memory, which leaves the compiler
+// unable to tell where the pointers point: it would reach the arrays with
+// flat instructions, which also count against the LDS wait counter.  With
+// G their update code addresses the arrays through global-space pointers.
+// (The single-context kernels get their pointers as kernel arguments, which
+// the compiler already knows to be global; there the casts only add scalar
+// register pressure.)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <bool G, typename T>
+__device__ __forceinline__ auto gp(T *q) {
+  if constexpr (G) return (gptr<T>)q;
+  else return q;
+}
+
 // Branch-free predicated load: reads base[q] when `on`, else base[0] (always
 // a valid address) and returns 0.
 template <typename T>
 __device__ __forceinline__ T ldp(const T *__restrict__ base, size_t q, bool on) {
+  const T v = base[on ? q : 0];
+  return on ? v : T(0);
+}
+template <typename T>
+__device__ __forceinline__ T ldp(const gptr<const T> __restrict__ base, size_t q, bool on) {
   const T v = base[on ? q : 0];
   return on ? v : T(0);
 }
@@ -103,15 +124,15 @@ __device__ __forceinline__ bool wave_touches_box(const int i0, const int jb, con
 
 // Tiles that are neither edge tiles nor touch the design or gap box need only
 // the plain dielectric update, identical in the forward and adjoint solves.
-template <typename T, int R>
+template <typename T, int R, bool G>
 __device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, const int i, const int jb) {
   const int pitch = p.pitch;
-  const T *__restrict__ ez = p.ez[par];
-  const T *__restrict__ hxo = p.hx[par];
-  const T *__restrict__ hyo = p.hy[par];
-  T *__restrict__ ezw = p.ez[par ^ 1];
-  T *__restrict__ hxw = p.hx[par ^ 1];
-  T *__restrict__ hyw = p.hy[par ^ 1];
+  auto *__restrict__ ez = gp<G>((const T *)p.ez[par]);
+  auto *__restrict__ hxo = gp<G>((const T *)p.hx[par]);
+  auto *__restrict__ hyo = gp<G>((const T *)p.hy[par]);
+  auto *__restrict__ ezw = gp<G>(p.ez[par ^ 1]);
+  auto *__restrict__ hxw = gp<G>(p.hx[par ^ 1]);
+  auto *__restrict__ hyw = gp<G>(p.hy[par ^ 1]);
   const size_t q0 = (size_t)jb * pitch + i;
   T e[R + 2], er[R], el[R], hx[R + 1], hy[R], hyl[R];
 #pragma unroll
@@ -143,30 +164,30 @@ __device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, con
 
 // Absorber, wall, total-field, design and gap nodes.  EDGE = false compiles
 // the absorber and plane-wave terms out (interior design/gap wavefronts).
-template <typename T, bool ADJ, bool EDGE, int R>
+template <typename T, bool ADJ, bool EDGE, int R, bool G>
 __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, const int par, const int i,
                                              const int jb) {
   const int nx = p.nx, ny = p.ny, pitch = p.pitch, P = EDGE ? p.P : 0;
   if (i >= nx) return;
   const int wr = par ^ 1;
-  const T *__restrict__ ez = p.ez[par];
-  const T *__restrict__ hxo = p.hx[par];
-  const T *__restrict__ hyo = p.hy[par];
-  const T *__restrict__ pexo = p.pex[par];
-  const T *__restrict__ peyo = p.pey[par];
-  const T *__restrict__ phxo = p.phx[par];
-  const T *__restrict__ phyo = p.phy[par];
-  T *__restrict__ ezw = p.ez[wr];
-  T *__restrict__ hxw = p.hx[wr];
-  T *__restrict__ hyw = p.hy[wr];
-  T *__restrict__ pexw = p.pex[wr];
-  T *__restrict__ peyw = p.pey[wr];
-  T *__restrict__ phxw = p.phx[wr];
-  T *__restrict__ phyw = p.phy[wr];
-  const T *__restrict__ rho = p.rho;
-  T *__restrict__ Jc = p.J;
-  T *__restrict__ hist = p.hist;
-  double *__restrict__ grad = p.grad;
+  auto *__restrict__ ez = gp<G>((const T *)p.ez[par]);
+  auto *__restrict__ hxo = gp<G>((const T *)p.hx[par]);
+  auto *__restrict__ hyo = gp<G>((const T *)p.hy[par]);
+  auto *__restrict__ pexo = gp<G>((const T *)p.pex[par]);
+  auto *__restrict__ peyo = gp<G>((const T *)p.pey[par]);
+  auto *__restrict__ phxo = gp<G>((const T *)p.phx[par]);
+  auto *__restrict__ phyo = gp<G>((const T *)p.phy[par]);
+  auto *__restrict__ ezw = gp<G>(p.ez[wr]);
+  auto *__restrict__ hxw = gp<G>(p.hx[wr]);
+  auto *__restrict__ hyw = gp<G>(p.hy[wr]);
+  auto *__restrict__ pexw = gp<G>(p.pex[wr]);
+  auto *__restrict__ peyw = gp<G>(p.pey[wr]);
+  auto *__restrict__ phxw = gp<G>(p.phx[wr]);
+  auto *__restrict__ phyw = gp<G>(p.phy[wr]);
+  auto *__restrict__ rho = gp<G>((const T *)p.rho);
+  auto *__restrict__ Jc = gp<G>(p.J);
+  auto *__restrict__ hist = gp<G>(p.hist);
+  auto *__restrict__ grad = gp<G>(p.grad);
 
   const bool hasl = i >= 1, hasr = i + 1 < nx;
   const bool colx = i >= 1 && i <= nx - 2;       // E node column / H_x column
@@ -222,19 +243,19 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
     const bool gap = gcol && inner && gj >= 0 && gj < p.gny;
     const size_t d = (size_t)(des ? dj * p.dnx + di : 0);
     rr[r] = ldp(rho, d, des);
-    Jo[r] = ldp((const T *)Jc, d, des && !gap);
-    Em[r] = ldp((const T *)hist, (size_t)(n - 1 - p.hist_base) * nd + d, ADJ && des && !gap);
-    gacc[r] = ldp((const double *)grad, d, ADJ && des && !gap);
-    src[r] = ldp(p.asrc, (size_t)n * p.ng + (gap ? gj * p.gnx + gi : 0), ADJ && gap);
+    Jo[r] = ldp(gp<G>((const T *)p.J), d, des && !gap);
+    Em[r] = ldp(gp<G>((const T *)p.hist), (size_t)(n - 1 - p.hist_base) * nd + d, ADJ && des && !gap);
+    gacc[r] = ldp(gp<G>((const double *)p.grad), d, ADJ && des && !gap);
+    src[r] = ldp(gp<G>(p.asrc), (size_t)n * p.ng + (gap ? gj * p.gnx + gi : 0), ADJ && gap);
     const bool tfr = !ADJ && tfy && j >= p.ja && j <= p.jb;
-    einc_r[r] = ldp(p.einc, (size_t)n * p.L + (tfr ? j - p.jref : 0), tfr);
+    einc_r[r] = ldp(gp<G>(p.einc), (size_t)n * p.L + (tfr ? j - p.jref : 0), tfr);
   }
   T eA = T(0), eB = T(0), hA = T(0), hB = T(0);
   if (!ADJ && EDGE && p.tf_on) {
-    eA = p.einc[(size_t)n * p.L + (p.ja - p.jref)];
-    eB = p.einc[(size_t)n * p.L + (p.jb - p.jref)];
-    hA = p.hinc[(size_t)n * p.L + (p.ja - 1 - p.jref)];
-    hB = p.hinc[(size_t)n * p.L + (p.jb - p.jref)];
+    eA = gp<G>(p.einc)[(size_t)n * p.L + (p.ja - p.jref)];
+    eB = gp<G>(p.einc)[(size_t)n * p.L + (p.jb - p.jref)];
+    hA = gp<G>(p.hinc)[(size_t)n * p.L + (p.ja - 1 - p.jref)];
+    hB = gp<G>(p.hinc)[(size_t)n * p.L + (p.jb - p.jref)];
   }
 
   // ---------------------------------------------------------------- H
@@ -250,8 +271,8 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       if (colx && j >= 0 && j <= ny - 2) {
         const T dE = e[r + 1] - e[r];
         if (pml_h(j, ny, P)) {
-          ps = p.byh[j] * phx[r] + p.ayh[j] * dE;
-          h = hx[r] - p.chx * (dE * p.ikyh[j] + ps);
+          ps = gp<G>(p.byh)[j] * phx[r] + gp<G>(p.ayh)[j] * dE;
+          h = hx[r] - p.chx * (dE * gp<G>(p.ikyh)[j] + ps);
         } else {
           h = hx[r] - p.chx * dE;
         }
@@ -271,8 +292,8 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
         if (coly) {
           const T dE = er[r] - e[r + 1];
           if (pxh) {
-            ps = p.bxh[i] * phy[r] + p.axh[i] * dE;
-            h = hy[r] + p.chx * (dE * p.ikxh[i] + ps);
+            ps = gp<G>(p.bxh)[i] * phy[r] + gp<G>(p.axh)[i] * dE;
+            h = hy[r] + p.chx * (dE * gp<G>(p.ikxh)[i] + ps);
           } else {
             h = hy[r] + p.chx * dE;
           }
@@ -282,8 +303,8 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
         if (hasl) {
           const T dE = e[r + 1] - el[r];
           if (pxhl) {
-            const T psl = p.bxh[i - 1] * phyl[r] + p.axh[i - 1] * dE;
-            hl = hyl[r] + p.chx * (dE * p.ikxh[i - 1] + psl);
+            const T psl = gp<G>(p.bxh)[i - 1] * phyl[r] + gp<G>(p.axh)[i - 1] * dE;
+            hl = hyl[r] + p.chx * (dE * gp<G>(p.ikxh)[i - 1] + psl);
           } else {
             hl = hyl[r] + p.chx * dE;
           }
@@ -304,8 +325,8 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       gy[r] = e[r];
       peyn[r] = T(0);
       if (j >= 0 && j < ny && pml_e(j, ny, P)) {
-        peyn[r] = p.bye[j] * pey[r] + p.aye[j] * e[r];
-        gy[r] = e[r] * p.ikye[j] + peyn[r];
+        peyn[r] = gp<G>(p.bye)[j] * pey[r] + gp<G>(p.aye)[j] * e[r];
+        gy[r] = e[r] * gp<G>(p.ikye)[j] + peyn[r];
       }
     }
 #pragma unroll
@@ -313,11 +334,11 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       gx[r] = e[r + 1];
       pexn[r] = T(0);
       if (pxe) {
-        pexn[r] = p.bxe[i] * pex[r] + p.axe[i] * e[r + 1];
-        gx[r] = e[r + 1] * p.ikxe[i] + pexn[r];
+        pexn[r] = gp<G>(p.bxe)[i] * pex[r] + gp<G>(p.axe)[i] * e[r + 1];
+        gx[r] = e[r + 1] * gp<G>(p.ikxe)[i] + pexn[r];
       }
-      gxr[r] = pxer ? er[r] * p.ikxe[i + 1] + (p.bxe[i + 1] * pexr[r] + p.axe[i + 1] * er[r]) : er[r];
-      gxl[r] = pxel ? el[r] * p.ikxe[i - 1] + (p.bxe[i - 1] * pexl[r] + p.axe[i - 1] * el[r]) : el[r];
+      gxr[r] = pxer ? er[r] * gp<G>(p.ikxe)[i + 1] + (gp<G>(p.bxe)[i + 1] * pexr[r] + gp<G>(p.axe)[i + 1] * er[r]) : er[r];
+      gxl[r] = pxel ? el[r] * gp<G>(p.ikxe)[i - 1] + (gp<G>(p.bxe)[i - 1] * pexl[r] + gp<G>(p.axe)[i - 1] * el[r]) : el[r];
     }
 #pragma unroll
     for (int r = 0; r < R + 1; ++r) {
@@ -327,8 +348,8 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
         h = hx[r] - p.chx * (gy[r + 1] - gy[r]);
         g = h;
         if (pml_h(j, ny, P)) {
-          nu = p.byh[j] * phx[r] + p.ayh[j] * h;
-          g = h * p.ikyh[j] + nu;
+          nu = gp<G>(p.byh)[j] * phx[r] + gp<G>(p.ayh)[j] * h;
+          g = h * gp<G>(p.ikyh)[j] + nu;
         }
       }
       hxn[r] = h;
@@ -344,14 +365,14 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
           h = hy[r] + p.chx * (gxr[r] - gx[r]);
           g = h;
           if (pxh) {
-            nu = p.bxh[i] * phy[r] + p.axh[i] * h;
-            g = h * p.ikxh[i] + nu;
+            nu = gp<G>(p.bxh)[i] * phy[r] + gp<G>(p.axh)[i] * h;
+            g = h * gp<G>(p.ikxh)[i] + nu;
           }
         }
         if (hasl) {
           const T hl = hyl[r] + p.chx * (gx[r] - gxl[r]);
           gl = hl;
-          if (pxhl) gl = hl * p.ikxh[i - 1] + (p.bxh[i - 1] * phyl[r] + p.axh[i - 1] * hl);
+          if (pxhl) gl = hl * gp<G>(p.ikxh)[i - 1] + (gp<G>(p.bxh)[i - 1] * phyl[r] + gp<G>(p.axh)[i - 1] * hl);
         }
       }
       hyn[r] = h;
@@ -375,12 +396,12 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
     if (!ADJ) {
       T cx = dHy, cy = dHx;
       if (pxe) {
-        pexf[r] = p.bxe[i] * pex[r] + p.axe[i] * dHy;
-        cx = dHy * p.ikxe[i] + pexf[r];
+        pexf[r] = gp<G>(p.bxe)[i] * pex[r] + gp<G>(p.axe)[i] * dHy;
+        cx = dHy * gp<G>(p.ikxe)[i] + pexf[r];
       }
       if (pml_e(j, ny, P)) {
-        peyf[r] = p.bye[j] * pey[r + 1] + p.aye[j] * dHx;
-        cy = dHx * p.ikye[j] + peyf[r];
+        peyf[r] = gp<G>(p.bye)[j] * pey[r + 1] + gp<G>(p.aye)[j] * dHx;
+        cy = dHx * gp<G>(p.ikye)[j] + peyf[r];
       }
       curl = cx - cy;
       if (tfx && j == p.ja) curl += hA;
@@ -458,19 +479,19 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
       if (ADJ) grad[d] = gnew[r];
     }
     if (!ADJ && des && p.hist_on) hist[(size_t)(n - p.hist_base) * nd + d] = en[r];
-    if (!ADJ && gap) p.gapE[(size_t)(n + 1) * p.ng + gj * p.gnx + gi] = (double)en[r];
+    if (!ADJ && gap) gp<G>(p.gapE)[(size_t)(n + 1) * p.ng + gj * p.gnx + gi] = (double)en[r];
   }
 }
 
 // One workgroup's tile: block `bid` of the grid of one instance.
-template <typename T, bool ADJ, int R>
+template <typename T, bool ADJ, int R, bool G>
 __device__ __forceinline__ void step2d_block(const Step2D<T> &p, const int n, const int par, const int bid) {
   constexpr int TYB = WAVES * R;
   const int nx = p.nx, ny = p.ny, P = p.P;
   const int nbx = (nx + TXW - 1) / TXW, nby = (ny + TYB - 1) / TYB;
   int tx, ty;
   if (p.tlist) {
-    const int t = p.tlist[bid];
+    const int t = gp<G>(p.tlist)[bid];
     tx = t % nbx;
     ty = t / nbx;
   } else {
@@ -485,17 +506,17 @@ __device__ __forceinline__ void step2d_block(const Step2D<T> &p, const int n, co
   if (!wave_is_edge<R>(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
     if (!wave_touches_box<R>(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) &&
         !wave_touches_box<R>(i0, jb, p.gx0, p.gy0, p.gnx, p.gny))
-      step_bulk<T, R>(p, par, i, jb);
+      step_bulk<T, R, G>(p, par, i, jb);
     else
-      step_general<T, ADJ, false, R>(p, n, par, i, jb);
+      step_general<T, ADJ, false, R, G>(p, n, par, i, jb);
     return;
   }
-  step_general<T, ADJ, true, R>(p, n, par, i, jb);
+  step_general<T, ADJ, true, R, G>(p, n, par, i, jb);
 }
 
 template <typename T, bool ADJ, int R>
 __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES) step2d_kernel(const Step2D<T> p, const int n) {
-  step2d_block<T, ADJ, R>(p, n, 0, blockIdx.x);
+  step2d_block<T, ADJ, R, false>(p, n, 0, blockIdx.x);
 }
 
 // Several instances in one launch: instance k owns workgroups
@@ -537,7 +558,7 @@ __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
   p.pey[0] = rd[4]; p.pey[1] = wr[4];
   p.phx[0] = rd[5]; p.phx[1] = wr[5];
   p.phy[0] = rd[6]; p.phy[1] = wr[6];
-  step2d_block<T, ADJ, R>(p, n, 0, b - f[lo]);
+  step2d_block<T, ADJ, R, true>(p, n, 0, b - f[lo]);
 }
 
 // ---------------------------------------------------------------- two-step
@@ -558,7 +579,7 @@ constexpr int TBX = 64, TBY = 16, TBH = 2;
 constexpr int TLX = TBX + 2 * TBH, TLY = TBY + 2 * TBH;  // 68 x 20
 constexpr int TLS = TLX + 1;                               // LDS row stride
 
-template <typename T>
+template <typename T, bool G>
 __device__ __forceinline__ void tb_block(const Step2D<T> &p, const int code, T *ezo, T *hxo, T *hyo, T *E, T *HX,
                                          T *HY) {
   const int nbx = (p.nx + TXW - 1) / TXW;
@@ -566,9 +587,9 @@ __device__ __forceinline__ void tb_block(const Step2D<T> &p, const int code, T *
   const int st = code >> 1, sx = st % nbx, sy = st / nbx;
   const int x0 = sx * TBX - TBH, y0 = sy * TBY - TBH;  // global origin of LDS (0, 0)
   const int pitch = p.pitch;
-  const T *__restrict__ ez = p.ez[0];
-  const T *__restrict__ hx = p.hx[0];
-  const T *__restrict__ hy = p.hy[0];
+  auto *__restrict__ ez = gp<G>((const T *)p.ez[0]);
+  auto *__restrict__ hx = gp<G>((const T *)p.hx[0]);
+  auto *__restrict__ hy = gp<G>((const T *)p.hy[0]);
   const T ch = p.chx, ce = p.ce_s;
   const int t = threadIdx.x;
   // all of a thread's loads in flight before the first LDS store
@@ -609,9 +630,9 @@ __device__ __forceinline__ void tb_block(const Step2D<T> &p, const int code, T *
   }
   __syncthreads();
   if (mid) {  // the intermediate state of the super-tile, for the per-step neighbours
-    T *__restrict__ ezm = p.ez[1];
-    T *__restrict__ hxm = p.hx[1];
-    T *__restrict__ hym = p.hy[1];
+    auto *__restrict__ ezm = gp<G>(p.ez[1]);
+    auto *__restrict__ hxm = gp<G>(p.hx[1]);
+    auto *__restrict__ hym = gp<G>(p.hy[1]);
     for (int e = t; e < TBY * TBX; e += NT) {
       const int r = TBH + e / TBX, c = TBH + e % TBX, k = r * TLS + c;
       const size_t q = (size_t)(y0 + r) * pitch + (x0 + c);
@@ -632,9 +653,9 @@ __device__ __forceinline__ void tb_block(const Step2D<T> &p, const int code, T *
   for (int e = t; e < TBY * TBX; e += NT) {
     const int r = TBH + e / TBX, c = TBH + e % TBX, k = r * TLS + c;
     const size_t q = (size_t)(y0 + r) * pitch + (x0 + c);
-    ezo[q] = E[k] + ce * ((HY[k] - HY[k - 1]) - (HX[k] - HX[k - TLS]));
-    hxo[q] = HX[k];
-    hyo[q] = HY[k];
+    gp<G>(ezo)[q] = E[k] + ce * ((HY[k] - HY[k - 1]) - (HX[k] - HX[k - TLS]));
+    gp<G>(hxo)[q] = HX[k];
+    gp<G>(hyo)[q] = HY[k];
   }
 }
 // One launch of the blocked schedule: workgroups [0, nrest) take one
@@ -649,10 +670,10 @@ __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
   // per-step workgroups first: their slow design and absorber tiles start
   // early and the two-step workgroups fill the machine around them
   if (b < nrest) {
-    step2d_block<T, ADJ, RDEF>(ps, n, 0, b);
+    step2d_block<T, ADJ, RDEF, false>(ps, n, 0, b);
     return;
   }
-  tb_block<T>(pt, tiles[b - nrest], ezo, hxo, hyo, E, HX, HY);
+  tb_block<T, false>(pt, tiles[b - nrest], ezo, hxo, hyo, E, HX, HY);
 }
 
 // Last k with f[k] <= b.
@@ -688,14 +709,14 @@ __global__ void __launch_bounds__(NT, FDTD2D_MIN_WAVES)
     const cptr2<int> src = (cptr2<int>)(&(ds + k)->ps);
 #pragma unroll
     for (int w = 0; w < (int)(sizeof(Step2D<T>) / 4); ++w) dst[w] = src[w];
-    step2d_block<T, ADJ, RDEF>(p, n, 0, lb);
+      step2d_block<T, ADJ, RDEF, true>(p, n, 0, lb);
     return;
   }
   if (lb >= d->ntb) return;
   const cptr2<int> src = (cptr2<int>)(&(ds + k)->pt);
 #pragma unroll
   for (int w = 0; w < (int)(sizeof(Step2D<T>) / 4); ++w) dst[w] = src[w];
-  tb_block<T>(p, d->tiles[lb], d->ezo, d->hxo, d->hyo, E, HX, HY);
+  tb_block<T, true>(p, d->tiles[lb], d->ezo, d->hxo, d->hyo, E, HX, HY);
 }
 
 
