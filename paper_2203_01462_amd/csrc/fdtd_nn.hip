@@ -182,10 +182,12 @@ __global__ void __launch_bounds__(BS) conv_fwd_kernel(int cin, int cout, int h, 
 }
 
 // The same convolution, LDS-tiled for cin % 32 == 0 and h, w multiples of 16,
-// on v_mfma_f32_16x16x32_bf16.  A workgroup owns 16*MT output channels x a
-// 16 x 16 pixel tile of one image; per chunk of 32 input channels it stages
-// the 18 x 18 halo tile channel-last in LDS (eight channels of one pixel are
-// one 16-byte LDS read) and the weights of all nine taps, then each
+// on v_mfma_f32_16x16x32_bf16, reading a channel-last copy of the input
+// (x[n][y][x][cin], to_nhwc_kernel).  A workgroup owns 16*MT output channels
+// x a 16 x 16 pixel tile of one image; per chunk of 32 input channels it
+// stages the 18 x 18 halo tile in LDS (a pixel's 32 channels are four
+// 16-byte loads; eight channels of one pixel are one 16-byte LDS read) and
+// the weights of all nine taps, then each
 // wavefront (four pixel rows) runs nine taps x MT x 4 matrix instructions.
 // grid ((h/16) * (w/16), ceil(cout / (16*MT)), n).
 // Pipelined variant: a workgroup walks `tpw` pixel tiles; the next (tile,
@@ -197,7 +199,7 @@ constexpr int XST = 40;                 // LDS stride between staged pixels (80 
 constexpr int WST = 40;                 // LDS stride between staged (tap, co) weight rows
 constexpr int TT = 16, HT = TT + 2;     // output tile side, halo tile side
 
-template <int MT, bool NHWC>
+template <int MT>
 __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, int h, int w,
                                                           const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ wt,
@@ -212,7 +214,6 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
   const int co0 = blockIdx.y * 16 * MT;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
   const size_t cs = (size_t)nimg * HW;
-  const uint16_t *xn = x + (size_t)n * HW;
   f4 acc[MT][4];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -240,26 +241,11 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
       const int r = pos / HT, q = pos - r * HT;
       const int iy = y0 - 1 + r, ix = x0 - 1 + q;
       const bool ok = iy >= 0 && iy < h && ix >= 0 && ix < w;
-      if constexpr (NHWC) {
-        // channel-last copy: the pixel's 32 channels are 64 contiguous bytes
-        const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
+      // channel-last input: the pixel's 32 channels are 64 contiguous bytes
+      const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
 #pragma unroll
-        for (int c8 = 0; c8 < CC / 8; ++c8)
-          *(uint4 *)(Xs + pos * XST + 8 * c8) = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
-      } else {
-        const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
-#pragma unroll
-        for (int c8 = 0; c8 < CC; c8 += 8) {
-          uint32_t pk[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const uint32_t lo = ok ? src[(size_t)(c8 + 2 * j) * cs] : 0u;
-            const uint32_t hi = ok ? src[(size_t)(c8 + 2 * j + 1) * cs] : 0u;
-            pk[j] = lo | (hi << 16);
-          }
-          *(uint4 *)(Xs + pos * XST + c8) = uint4{pk[0], pk[1], pk[2], pk[3]};
-        }
-      }
+      for (int c8 = 0; c8 < CC / 8; ++c8)
+        *(uint4 *)(Xs + pos * XST + 8 * c8) = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
     }
     __syncthreads();
 #pragma unroll
@@ -284,7 +270,7 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_kernel(int cin, int cout, in
 // The same with the staging software-pipelined (see above): faster on the
 // deep layers with a few pixel tiles and several channel chunks, slower on
 // the wide ones (its prefetch registers leave one wavefront per SIMD).
-template <int MT, bool NHWC>
+template <int MT>
 __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cout, int h, int w,
                                                                const uint16_t *__restrict__ x,
                                                                const uint16_t *__restrict__ wt,
@@ -302,7 +288,6 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
   const int co0 = blockIdx.y * 16 * MT;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, l16 = lane & 15, kq = lane >> 4;
   const size_t cs = (size_t)nimg * HW;
-  const uint16_t *xn = x + (size_t)n * HW;
   uint32_t xr[NXP][CC / 2];
   uint4 wr[NWV];
   // global -> registers for step (tile, c0); registers -> LDS after the barrier
@@ -314,24 +299,14 @@ __global__ void __launch_bounds__(BS) conv_fwd_mfma_pipe_kernel(int cin, int cou
       const int r = pos / HT, q = pos - r * HT;
       const int iy = y0 - 1 + r, ix = x0 - 1 + q;
       const bool ok = pos < HT * HT && iy >= 0 && iy < h && ix >= 0 && ix < w;
-      if constexpr (NHWC) {
-        const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
+      const uint4 *src = (const uint4 *)(x + ((size_t)n * HW + (ok ? iy * w + ix : 0)) * cin + c0);
 #pragma unroll
-        for (int c8 = 0; c8 < CC / 8; ++c8) {
-          const uint4 v = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
-          xr[k][4 * c8] = v.x;
-          xr[k][4 * c8 + 1] = v.y;
-          xr[k][4 * c8 + 2] = v.z;
-          xr[k][4 * c8 + 3] = v.w;
-        }
-      } else {
-        const uint16_t *src = xn + (size_t)c0 * cs + (ok ? iy * w + ix : 0);
-#pragma unroll
-        for (int j = 0; j < CC / 2; ++j) {
-          const uint32_t lo = ok ? src[(size_t)(2 * j) * cs] : 0u;
-          const uint32_t hi = ok ? src[(size_t)(2 * j + 1) * cs] : 0u;
-          xr[k][j] = lo | (hi << 16);
-        }
+      for (int c8 = 0; c8 < CC / 8; ++c8) {
+        const uint4 v = ok ? src[c8] : uint4{0u, 0u, 0u, 0u};
+        xr[k][4 * c8] = v.x;
+        xr[k][4 * c8 + 1] = v.y;
+        xr[k][4 * c8 + 2] = v.z;
+        xr[k][4 * c8 + 3] = v.w;
       }
     }
   };
@@ -513,18 +488,18 @@ void launch_conv(int n, int cin, int cout, int h, int w, const uint16_t *x, cons
     if (tiles <= 4 && cin > CC) {  // deep layers: pipelined staging, one tile per workgroup (measured)
       const dim3 g(tiles, cot, n);
       if (cout <= 32)
-        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
+        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<2>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
                            a, mask, 1);
       else
-        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
+        hipLaunchKernelGGL((conv_fwd_mfma_pipe_kernel<4>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z,
                            a, mask, 1);
       return;
     }
     const dim3 g(tiles, cot, n);
     if (cout <= 32)
-      hipLaunchKernelGGL((conv_fwd_mfma_kernel<2, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<2>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
     else
-      hipLaunchKernelGGL((conv_fwd_mfma_kernel<4, true>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
+      hipLaunchKernelGGL((conv_fwd_mfma_kernel<4>), g, dim3(BS), 0, s, cin, cout, h, w, xh, wt, bias, z, a, mask);
     return;
   }
   const dim3 g((h * w + TN - 1) / TN, (cout + TM - 1) / TM, n);
