@@ -47,9 +47,10 @@ MEASURED_TRAFFIC = {
     "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "ebd9536401a0edad",
                          "fwd": 501.0e6, "adj": 522.5e6,
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
-    # one time step = step3d_general (three launches) + step3d_plain
-    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "79ccde80b8f7f326",
-                       "fwd": 1301.2e6, "adj": 1336.7e6,
+    # one time step = the general update (forward: one step3d_general_fwd
+    # launch; adjoint: three step3d_general launches) + step3d_plain
+    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "94e1bef7dd56bbf5",
+                       "fwd": 1302.5e6, "adj": 1337.3e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
     # one time step = one step_te_fwd / step_te_adj launch
     "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "e46db84b8a373962",
@@ -386,7 +387,8 @@ def main():
                 "measured_frac": round(traffic / step_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "kernel": ("step_te_fwd / step_te_adj (one launch per time step)" if W.is_te(base)
                            else "step2d_mix_kernel (two launches per two time steps)" if base["dims"] == 2
-                           else "step3d_general x3 + step3d_plain (one time step)"),
+                           else "step3d_general_fwd (forward) or step3d_general x3 (adjoint) + step3d_plain"
+                                " (one time step)"),
                 "bytes_per_step_fwd": bf, "bytes_per_step_adj": ba,
                 "avg_step_us_fwd": round(fwd_ms * 1e3 / max(launches_f, 1), 3),
                 "avg_step_us_adj": round(adj_ms * 1e3 / max(launches_a, 1), 3)}

@@ -17,11 +17,12 @@
 // step's values, which the ping-pong copies keep intact.  A tile-plane is
 // "plain" when its whole reach is background dielectric; all others
 // (absorber, walls, injection faces, Drude design edges, gap) are "general".
-// One step is three launches of step3d_general over host-built lists of
-// tile-chunks (one absorber axis or none; several axes; design and gap),
-// the last two on a second stream beside the first, then step3d_plain,
-// which reads back the general launches' new H where a plain plane sits on
-// a general one.  The general path keeps its cost down by
+// One step is the general update over three host-built lists of
+// tile-chunks (one absorber axis or none; several axes; design and gap) --
+// one launch of step3d_general_fwd in the FP32 forward, else three
+// launches of step3d_general, the multi-axis one on a second stream -- then
+// step3d_plain, which reads back the general update's new H where a plain
+// plane sits on a general one.  The general path keeps its cost down by
 // loading each group of absorber memories only in tiles/planes that reach
 // that absorber (uniform branches), by addressing the whole state of a copy
 // through one base pointer with 32-bit offsets, and by CPML tables that are
@@ -606,10 +607,7 @@ constexpr int gen_waves() {
 }
 
 template <typename T, bool ADJ, bool DES, int AX>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(gen_waves<T, ADJ, DES, AX>())))
-step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
-  const int code = ((cptr<int>)list)[blockIdx.x];
-  if (code < 0) return;
+__device__ __forceinline__ void general_body(const Step3D<T> &p, const int n, const int code) {
   const int c = AX == 8 ? code >> 2 : code;
   const int nbx = (p.n[0] + TX - 1) / TX, nby = (p.n[1] + TY - 1) / TY;
   const int bx = c % nbx, by = (c / nbx) % nby, bz = c / (nbx * nby);
@@ -626,6 +624,32 @@ step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
   } else {
     general_chunk<T, ADJ, DES, AX>(p, n, tl);
   }
+}
+
+template <typename T, bool ADJ, bool DES, int AX>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(gen_waves<T, ADJ, DES, AX>())))
+step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
+  const int code = ((cptr<int>)list)[blockIdx.x];
+  if (code < 0) return;
+  general_body<T, ADJ, DES, AX>(p, n, code);
+}
+
+// The FP32 forward's three lists in one launch, in list order (single-axis,
+// multi-axis, design): workgroup b takes entry b, and the body follows the
+// list the entry sits in (a uniform branch).  Each list's length is a
+// multiple of 8, so every entry keeps the XCD slot its list gave it.  At 4
+// waves per SIMD the union of the three bodies spills a few registers;
+// measured on the 256^3 workload it still beats the three launches on two
+// streams, whose fork and join each left the machine idle for ~6 us.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+step3d_general_fwd(const Step3D<float> p, const int n, const int *__restrict__ list) {
+  const int b = blockIdx.x;
+  const int code = ((cptr<int>)list)[b];
+  if (code < 0) return;
+  if (b < p.gS) general_body<float, false, false, 8>(p, n, code);
+  else if (b < p.gS + p.gM) general_body<float, false, false, 7>(p, n, code);
+  else if (p.gAxD) general_body<float, false, true, 7>(p, n, code);
+  else general_body<float, false, true, 0>(p, n, code);
 }
 
 // ---------------------------------------------------------------- plain
@@ -1174,14 +1198,27 @@ std::vector<int> plan3d_super(const Step3D<T> &p, int so[3], int sn[3], std::vec
 #ifndef FDTD3D_AUX
 #define FDTD3D_AUX 1
 #endif
+#ifndef FDTD3D_MERGE
+#define FDTD3D_MERGE 1
+#endif
 
-// The three general launches write disjoint tile-chunks of the write copy
-// and read only the read copy, so the multi-axis and design launches may run
-// on the second stream beside the single-axis one.
+// The three general lists write disjoint tile-chunks of the write copy and
+// read only the read copy, so they may run in any order or side by side.
+// FP32 forward: one launch over all three.  Otherwise three launches: the
+// multi-axis list on the second stream, beside the design list and then the
+// single-axis list on the context stream (the order measured fastest for
+// the FP32 adjoint, whose multi-axis body is the longest).
 template <typename T, bool ADJ>
 static void launch_general(const Step3D<T> &q, int n, hipStream_t s, const Aux3D &aux) {
   const int *L = q.glist;
-  const bool two = FDTD3D_AUX && aux.stream && (q.gM > 0 || q.gD > 0);
+  if constexpr (std::is_same<T, float>::value && !ADJ) {
+    const int tot = q.gS + q.gM + q.gD;
+    if (FDTD3D_MERGE && tot > 0) {
+      hipLaunchKernelGGL(step3d_general_fwd, dim3(tot), dim3(NT), 0, s, q, n, L);
+      return;
+    }
+  }
+  const bool two = FDTD3D_AUX && aux.stream && q.gM > 0;
   hipStream_t s2 = s;
   if (two) {
     FDTD_HIP(hipEventRecord(aux.fork, s));
@@ -1191,9 +1228,9 @@ static void launch_general(const Step3D<T> &q, int n, hipStream_t s, const Aux3D
   if (q.gM > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 7>), dim3(q.gM), dim3(NT), 0, s2, q, n, L + q.gS);
   if (q.gD > 0) {
     if (q.gAxD)
-      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 7>), dim3(q.gD), dim3(NT), 0, s2, q, n, L + q.gS + q.gM);
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 7>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
     else
-      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 0>), dim3(q.gD), dim3(NT), 0, s2, q, n, L + q.gS + q.gM);
+      hipLaunchKernelGGL((step3d_general<T, ADJ, true, 0>), dim3(q.gD), dim3(NT), 0, s, q, n, L + q.gS + q.gM);
   }
   if (q.gS > 0) hipLaunchKernelGGL((step3d_general<T, ADJ, false, 8>), dim3(q.gS), dim3(NT), 0, s, q, n, L);
   if (two) {
