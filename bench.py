@@ -53,8 +53,8 @@ MEASURED_TRAFFIC = {
                        "fwd": 1302.5e6, "adj": 1337.3e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
     # one time step = one step_te_fwd / step_te_adj launch
-    "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "e46db84b8a373962",
-                       "fwd": 165.8e6, "adj": 172.3e6,
+    "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "9a8855a23ae314cd",
+                       "fwd": 161.8e6, "adj": 168.4e6,
                        "profile": "profiles/step_te_te2d_2048_fp32.md"},
 }
 
