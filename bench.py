@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {
                        "fwd": 1302.5e6, "adj": 1337.3e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
     # one time step = one step_te_fwd / step_te_adj launch
-    "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "9a8855a23ae314cd",
+    "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "7894ca2a1bac6bae",
                        "fwd": 161.8e6, "adj": 168.4e6,
                        "profile": "profiles/step_te_te2d_2048_fp32.md"},
 }

@@ -391,8 +391,6 @@ __global__ void __launch_bounds__(TEX * TEW) step_te_adj(const Step2D<T> p, int 
   else if (kind == 0) te_adj_body<T, false, TER>(p, n, bx, j0);
 }
 
-}  // namespace
-
 // The blocks whose updated nodes (i, j) reach the design box's edges (i in
 // dx0 .. dx0+dnx, j in dy0 .. dy0+dny) or the gap box's; empty if neither
 // box is.
@@ -412,6 +410,8 @@ TeRect te_rect(const Step2D<T> &p) {
   const int rows = TEW * TER;
   return TeRect{ilo / TEC, ihi / TEC + 1, jlo / rows, jhi / rows + 1};
 }
+
+}  // namespace
 
 template <typename T>
 void launch_step_te(const Step2D<T> &p, int n, bool adjoint, hipStream_t s) {
