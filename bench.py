@@ -40,12 +40,12 @@ SRC_2D = ["paper_2203_01462_amd/csrc/fdtd_2d.hip", "paper_2203_01462_amd/csrc/fd
 SRC_3D = ["paper_2203_01462_amd/csrc/fdtd_3d.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 SRC_TE = ["paper_2203_01462_amd/csrc/fdtd_te.hip", "paper_2203_01462_amd/csrc/fdtd_api.hip"]
 MEASURED_TRAFFIC = {
-    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "ebd9536401a0edad",
+    "tmz2d_2048_fp32": {"sources": SRC_2D, "sha256_16": "57cf56d54ce24ece",
                         "fwd": 77.2e6, "adj": 81.5e6,
                         "profile": "profiles/step2d_mix_kernel_tmz2d_2048_fp32.md"},
     # one time step of all 64 instances = one step2d_batch_mix_kernel launch
-    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "ebd9536401a0edad",
-                         "fwd": 501.0e6, "adj": 522.5e6,
+    "tmz2d_batch64_c4": {"sources": SRC_2D, "sha256_16": "57cf56d54ce24ece",
+                         "fwd": 500.0e6, "adj": 521.7e6,
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = the general update (forward: one step3d_general_fwd
     # launch; adjoint: three step3d_general launches) + step3d_plain

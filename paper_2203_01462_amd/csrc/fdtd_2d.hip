@@ -163,8 +163,10 @@ __device__ __forceinline__ void step_bulk(const Step2D<T> &p, const int par, con
 }
 
 // Absorber, wall, total-field, design and gap nodes.  EDGE = false compiles
-// the absorber and plane-wave terms out (interior design/gap wavefronts).
-template <typename T, bool ADJ, bool EDGE, int R, bool G>
+// the absorber and plane-wave terms out (interior design/gap wavefronts),
+// DES = false the design and gap terms (edge wavefronts away from both
+// boxes: their loads, arithmetic and stores).
+template <typename T, bool ADJ, bool EDGE, int R, bool G, bool DES = true>
 __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, const int par, const int i,
                                              const int jb) {
   const int nx = p.nx, ny = p.ny, pitch = p.pitch, P = EDGE ? p.P : 0;
@@ -197,7 +199,7 @@ __device__ __forceinline__ void step_general(const Step2D<T> &p, const int n, co
   const bool pxel = hasl && pml_e(i - 1, nx, P), pxer = hasr && pml_e(i + 1, nx, P);
   const int nd = p.dnx * p.dny;
   const int di = i - p.dx0, gi = i - p.gx0;
-  const bool dcol = colx && di >= 0 && di < p.dnx, gcol = colx && gi >= 0 && gi < p.gnx;
+  const bool dcol = DES && colx && di >= 0 && di < p.dnx, gcol = DES && colx && gi >= 0 && gi < p.gnx;
   const bool tfx = (EDGE && p.tf_on) && i >= p.ia && i <= p.ib;
   const bool tfy = (EDGE && p.tf_on) && (i == p.ia - 1 || i == p.ia || i == p.ib || i == p.ib + 1);
 
@@ -503,6 +505,25 @@ __device__ __forceinline__ void step2d_block(const Step2D<T> &p, const int n, co
   const int jb = ty * TYB + wave * R;
   if (jb >= ny) return;  // no barriers in these kernels
   const int ia = p.tf_on ? p.ia : -8, ib = p.tf_on ? p.ib : -8, ja = p.tf_on ? p.ja : -8, jbt = p.tf_on ? p.jb : -8;
+  if constexpr (G && ADJ) {
+    // The batched adjoint's edge wavefronts away from the design and gap
+    // boxes skip their terms (measured on 64 uneven instances: 158 -> 146 us
+    // per adjoint step; in the forward and in the single-context kernels the
+    // extra body measured slower).
+    const bool box = wave_touches_box<R>(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) ||
+                     wave_touches_box<R>(i0, jb, p.gx0, p.gy0, p.gnx, p.gny);
+    if (!wave_is_edge<R>(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
+      if (!box)
+        step_bulk<T, R, G>(p, par, i, jb);
+      else
+        step_general<T, ADJ, false, R, G>(p, n, par, i, jb);
+    } else if (!box) {
+      step_general<T, ADJ, true, R, G, false>(p, n, par, i, jb);
+    } else {
+      step_general<T, ADJ, true, R, G>(p, n, par, i, jb);
+    }
+    return;
+  }
   if (!wave_is_edge<R>(nx, ny, P, i0, jb, ia, ib, ja, jbt)) {
     if (!wave_touches_box<R>(i0, jb, p.dx0, p.dy0, p.dnx, p.dny) &&
         !wave_touches_box<R>(i0, jb, p.gx0, p.gy0, p.gnx, p.gny))
