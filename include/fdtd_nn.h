@@ -11,7 +11,8 @@
  *                          accumulation: z = w * x + b
  *   fdtd_nn_conv3x3_dgrad  dL/dx of the same convolution (the forward GEMM with
  *                          the weights turned by 180 degrees and transposed);
- *                          _dgrad_relu fuses the ReLU backward of the layer below
+ *                          _dgrad_relu fuses the ReLU backward of the layer below;
+ *                          fdtd_nn_rot_weights turns many layers' weights at once
  *   fdtd_nn_conv3x3_wgrad  dL/dw and dL/db (GEMM over all pixels of the batch)
  *   fdtd_nn_relu_bf16      a = bf16(max(z, 0)) and its backward
  *   fdtd_nn_pool2 / up2    2x2 average pooling and 2x nearest upsampling (and
@@ -60,7 +61,9 @@ fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int
                             const uint16_t *wt, const float *bias, float *z, uint16_t *a, void *stream);
 
 /* dx[ci][n][y][x] = sum_{co,ky,kx} w[co][ky][kx][ci] dz[co][n][y-ky+1][x-kx+1];
- * wrot: caller workspace of cout*cin*9 BF16 values. */
+ * wrot: caller workspace of cout*cin*9 BF16 values, into which the weights
+ * wt are turned first -- or, with wt = NULL, the turned weights themselves,
+ * as fdtd_nn_rot_weights writes them (then nothing is written to wrot). */
 fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
                                   const uint16_t *wt, uint16_t *wrot, float *dx, void *stream);
 
@@ -68,11 +71,23 @@ fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t 
  * ([cin][n][h][w], the convolution's input) fed this layer:
  * dza = bf16(dx * (a > 0)) with dx as fdtd_nn_conv3x3_dgrad computes it --
  * the same BF16 values as fdtd_nn_conv3x3_dgrad followed by
- * fdtd_nn_relu_bf16_backward(a, dx), without the FP32 dx in memory.
- * dza must not overlap dz or a. */
+ * fdtd_nn_relu_bf16_backward(a, dx), without the FP32 dx in memory (wt and
+ * wrot as there, wt = NULL included).  dza must not overlap dz or a. */
 fdtd_status fdtd_nn_conv3x3_dgrad_relu(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
                                        const uint16_t *wt, uint16_t *wrot, const uint16_t *a, uint16_t *dza,
                                        void *stream);
+
+/* The turned weights of several layers in one launch, for data gradients
+ * called with wt = NULL (e.g. once per optimizer step instead of once per
+ * data gradient).  Layer l (0 <= l < nlayers <= 32; cin, cout, off are host
+ * arrays of nlayers entries) has its weights at w + off[l], layout
+ * [cout[l]][3][3][cin[l]]; its turned weights go to wrot + off[l], layout
+ * [cin[l]][3][3][cout[l]] with the taps turned by 180 degrees: wrot[off +
+ * (ci*9 + 8 - tap)*cout + co] = w[off + (co*9 + tap)*cin + ci].  The layers'
+ * ranges must not overlap, and wrot must not overlap w.  EINVAL on a bad
+ * count, size or offset. */
+fdtd_status fdtd_nn_rot_weights(int32_t nlayers, const int32_t *cin, const int32_t *cout, const int64_t *off,
+                                const uint16_t *w, uint16_t *wrot, void *stream);
 
 /* dw[co][ky][kx][ci] = sum_{n,y,x} dz[co][n][y][x] x[ci][n][y+ky-1][x+kx-1];
  * db[co] = sum_{n,y,x} dz; work: caller workspace of fdtd_nn_wgrad_work(...)

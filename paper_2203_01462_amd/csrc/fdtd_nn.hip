@@ -911,6 +911,30 @@ __global__ void __launch_bounds__(BS) rot_kernel(int cin, int cout, const uint16
   wrot[((size_t)ci * 9 + (8 - tap)) * cout + co] = w[i];
 }
 
+// Every layer of a table in one launch: the turned, transposed layout of
+// rot_kernel at wrot + off[l] from layer l's weights at w + off[l] (layout
+// [cout][3][3][cin]).  Thread i writes element k of layer l's output (so the
+// stores are contiguous and the scattered accesses are the reads); it finds
+// its layer by scanning the prefix counts (at most kRotLayers entries).
+constexpr int kRotLayers = 32;
+struct RotTable {
+  int n;
+  int cin[kRotLayers], cout[kRotLayers];
+  int64_t off[kRotLayers], first[kRotLayers + 1];
+};
+
+__global__ void __launch_bounds__(BS) rot_all_kernel(const RotTable t, const uint16_t *__restrict__ w,
+                                                    uint16_t *__restrict__ wrot) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= t.first[t.n]) return;
+  int l = 0;
+  while (l + 1 < t.n && i >= t.first[l + 1]) ++l;
+  const int64_t k = i - t.first[l];
+  const int cin = t.cin[l], cout = t.cout[l];
+  const int co = (int)(k % cout), rtap = (int)((k / cout) % 9), ci = (int)(k / (9 * (int64_t)cout));
+  wrot[t.off[l] + k] = w[t.off[l] + ((int64_t)co * 9 + (8 - rtap)) * cin + ci];
+}
+
 __global__ void __launch_bounds__(BS) relu_kernel(int64_t n, const float *__restrict__ z, uint16_t *__restrict__ a) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) a[i] = f2bf(fmaxf(z[i], 0.f));
@@ -1206,9 +1230,9 @@ fdtd_status fdtd_nn_conv3x3(int32_t n, int32_t cin, int32_t cout, int32_t h, int
 fdtd_status fdtd_nn_conv3x3_dgrad(int32_t n, int32_t cin, int32_t cout, int32_t h, int32_t w, const uint16_t *dz,
                                   const uint16_t *wt, uint16_t *wrot, float *dx, void *stream) {
   return nguard([&] {
-    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && dx);
+    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wrot && dx);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
+    if (wt) hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
     launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, dx, nullptr, nullptr, s);
     FDTD_HIP(hipGetLastError());
   });
@@ -1218,10 +1242,30 @@ fdtd_status fdtd_nn_conv3x3_dgrad_relu(int32_t n, int32_t cin, int32_t cout, int
                                        const uint16_t *wt, uint16_t *wrot, const uint16_t *a, uint16_t *dza,
                                        void *stream) {
   return nguard([&] {
-    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wt && wrot && a && dza);
+    need(n > 0 && n <= 65535 && cin > 0 && cout > 0 && h > 0 && w > 0 && dz && wrot && a && dza);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
+    if (wt) hipLaunchKernelGGL(rot_kernel, dim3(nb_of((int64_t)cin * cout * 9)), dim3(BS), 0, s, cin, cout, wt, wrot);
     launch_conv(n, cout, cin, h, w, dz, wrot, nullptr, nullptr, dza, a, s);
+    FDTD_HIP(hipGetLastError());
+  });
+}
+
+fdtd_status fdtd_nn_rot_weights(int32_t nlayers, const int32_t *cin, const int32_t *cout, const int64_t *off,
+                                const uint16_t *w, uint16_t *wrot, void *stream) {
+  return nguard([&] {
+    need(nlayers >= 1 && nlayers <= kRotLayers && cin && cout && off && w && wrot);
+    RotTable t{};
+    t.n = nlayers;
+    t.first[0] = 0;
+    for (int l = 0; l < nlayers; ++l) {
+      need(cin[l] > 0 && cout[l] > 0 && off[l] >= 0);
+      t.cin[l] = cin[l];
+      t.cout[l] = cout[l];
+      t.off[l] = off[l];
+      t.first[l + 1] = t.first[l] + (int64_t)cin[l] * cout[l] * 9;
+    }
+    need(t.first[nlayers] <= (int64_t)INT32_MAX * BS);
+    hipLaunchKernelGGL(rot_all_kernel, dim3(nb_of(t.first[nlayers])), dim3(BS), 0, (hipStream_t)stream, t, w, wrot);
     FDTD_HIP(hipGetLastError());
   });
 }

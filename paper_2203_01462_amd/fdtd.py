@@ -76,7 +76,8 @@ EXPORTS = ["fdtd_abi_version", "fdtd_create", "fdtd_set_density", "fdtd_forward"
            "fdtd_mma_create", "fdtd_mma_begin", "fdtd_mma_solve", "fdtd_mma_accept", "fdtd_mma_destroy",
            "fdtd_design_stats", "fdtd_design_last_error",
            # include/fdtd_nn.h
-           "fdtd_nn_conv3x3", "fdtd_nn_conv3x3_dgrad", "fdtd_nn_conv3x3_dgrad_relu", "fdtd_nn_wgrad_work",
+           "fdtd_nn_conv3x3", "fdtd_nn_conv3x3_dgrad", "fdtd_nn_conv3x3_dgrad_relu", "fdtd_nn_rot_weights",
+           "fdtd_nn_wgrad_work",
            "fdtd_nn_conv3x3_wgrad", "fdtd_nn_conv3x3_wgrad_noalloc",
            "fdtd_nn_relu_bf16", "fdtd_nn_relu_bf16_backward", "fdtd_nn_to_bf16", "fdtd_nn_from_bf16",
            "fdtd_nn_pool2", "fdtd_nn_pool2_backward", "fdtd_nn_up2", "fdtd_nn_up2_backward", "fdtd_nn_adam",
@@ -144,6 +145,7 @@ def load_library(path=LIB_PATH):
         "fdtd_nn_conv3x3": [I32, I32, I32, I32, I32, P, P, P, P, P, P],
         "fdtd_nn_conv3x3_dgrad": [I32, I32, I32, I32, I32, P, P, P, P, P],
         "fdtd_nn_conv3x3_dgrad_relu": [I32, I32, I32, I32, I32, P, P, P, P, P, P],
+        "fdtd_nn_rot_weights": [I32, P, P, P, P, P, P],
         "fdtd_nn_conv3x3_wgrad": [I32, I32, I32, I32, I32, P, P, P, P, P, P],
         "fdtd_nn_conv3x3_wgrad_noalloc": [I32, I32, I32, I32, I32, P, P, P, P, P],
         "fdtd_nn_relu_bf16": [I64, P, P, P],

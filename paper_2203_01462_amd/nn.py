@@ -53,16 +53,31 @@ def conv3x3(x, wt, bias, n, cin, cout, h, w, z=None, a=None, stream=None):
                                           _s(stream)))
 
 
+def _u16n(t):
+    return None if t is None else _u16(t)
+
+
 def conv3x3_dgrad(dz, wt, wrot, dx, n, cin, cout, h, w, stream=None):
-    _check(load_library().fdtd_nn_conv3x3_dgrad(n, cin, cout, h, w, _p(_u16(dz)), _p(_u16(wt)), _p(_u16(wrot)),
+    """wt None: wrot already holds the turned weights (rot_weights)."""
+    _check(load_library().fdtd_nn_conv3x3_dgrad(n, cin, cout, h, w, _p(_u16(dz)), _p(_u16n(wt)), _p(_u16(wrot)),
                                                 _p(dx), _s(stream)))
 
 
 def conv3x3_dgrad_relu(dz, wt, wrot, a, dza, n, cin, cout, h, w, stream=None):
     """The data gradient with the ReLU backward of the layer below fused in:
     dza = bf16(dx * (a > 0)), a the BF16 activation that is this layer's input."""
-    _check(load_library().fdtd_nn_conv3x3_dgrad_relu(n, cin, cout, h, w, _p(_u16(dz)), _p(_u16(wt)), _p(_u16(wrot)),
+    _check(load_library().fdtd_nn_conv3x3_dgrad_relu(n, cin, cout, h, w, _p(_u16(dz)), _p(_u16n(wt)), _p(_u16(wrot)),
                                                      _p(_u16(a)), _p(_u16(dza)), _s(stream)))
+
+
+def rot_weights(layers, w, wrot, stream=None):
+    """Turned weights of every (cin, cout, offset) layer of the flat BF16
+    array w into wrot at the same offsets, in one launch."""
+    k = len(layers)
+    cin = (C.c_int32 * k)(*[ci for ci, _, _ in layers])
+    cout = (C.c_int32 * k)(*[co for _, co, _ in layers])
+    off = (C.c_int64 * k)(*[o for _, _, o in layers])
+    _check(load_library().fdtd_nn_rot_weights(k, cin, cout, off, _p(_u16(w)), _p(_u16(wrot)), _s(stream)))
 
 
 def wgrad_work(n, cin, cout, h, w):
@@ -199,6 +214,11 @@ class UNet:
         self.v = torch.zeros_like(self.p)
         self.g = torch.zeros_like(self.p)
         self.pb = to_bf16(self.p, stream=self.stream)
+        # every conv layer's turned weights for the data gradients, at the
+        # layer's own offset; refreshed in one launch at the first backward
+        # after the BF16 weights change
+        self.wrot = torch.empty_like(self.pb)
+        self._rot_ok = False
         self.t = 0
         self._alloc(batch)
 
@@ -210,6 +230,10 @@ class UNet:
     def b(self, i):
         ow, ob = self.offs[i]
         return self.p[ob:ob + self.plan[i][1]]
+
+    def wrot_of(self, i):
+        ow, ob = self.offs[i]
+        return self.wrot[ow:ob]
 
     def dw(self, i):
         ow, ob = self.offs[i]
@@ -248,7 +272,6 @@ class UNet:
         self.gz2 = torch.empty(big, **bf)
         self.dF = torch.empty(n, **f32)
         self.dS = torch.empty(n * s * s, **f32)
-        self.wrot = torch.empty(max(ci * co * 9 for ci, co, _ in self.plan), **bf)
         self.work = torch.empty(max(wgrad_work(n, ci, co, sz[l], sz[l]) for ci, co, l in self.plan), **f32)
         self.msew = torch.empty(max(mse_work(n * s * s), 1), dtype=torch.float64, device=d)
         self.loss = torch.zeros(2, dtype=torch.float64, device=d)
@@ -311,10 +334,10 @@ class UNet:
         conv3x3_wgrad(x, gz, self.dw(li), self.db(li), self.work, n, cin, cout, h, h, stream=st)
         if fuse:
             out = self.gz2[:cin * n * h * h]
-            conv3x3_dgrad_relu(gz, self.w(li), self.wrot, x, out, n, cin, cout, h, h, stream=st)
+            conv3x3_dgrad_relu(gz, None, self.wrot_of(li), x, out, n, cin, cout, h, h, stream=st)
             return out
         if gx is not None:
-            conv3x3_dgrad(gz, self.w(li), self.wrot, gx[:cin * n * h * h], n, cin, cout, h, h, stream=st)
+            conv3x3_dgrad(gz, None, self.wrot_of(li), gx[:cin * n * h * h], n, cin, cout, h, h, stream=st)
         return None
 
     def backward(self, dF, dS):
@@ -323,6 +346,10 @@ class UNet:
         L = len(ch)
         li = len(self.plan) - 1
         ga, gb = self.ga, self.gb
+        if not self._rot_ok:
+            rot_weights([(ci, co, ow) for (ci, co, _), (ow, _) in zip(self.plan, self.offs)], self.pb, self.wrot,
+                        stream=st)
+            self._rot_ok = True
         # sensitivity head and decoder, top down
         self._conv_back(li, self.d2[0], None, dS, ga, s)
         for l in range(L - 1):
@@ -367,6 +394,7 @@ class UNet:
     def step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
         adam(self.p, self.m, self.v, self.g, self.pb, lr, self.t, beta1, beta2, eps, stream=self.stream)
+        self._rot_ok = False
 
     def state(self):
         return {"p": self.p.detach().cpu(), "channels": self.ch, "side": self.side}
@@ -374,4 +402,5 @@ class UNet:
     def load(self, p):
         self.p.copy_(p.to(self.dev))
         to_bf16(self.p, self.pb, stream=self.stream)
+        self._rot_ok = False
 

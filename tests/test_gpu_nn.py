@@ -168,6 +168,45 @@ def test_dgrad_relu_fused_bit_exact(nn, n, cin, cout, h, w):
     assert (sep.cpu() == 0).float().mean().item() > 0.3  # the mask did zero entries
 
 
+def test_rot_weights_all_layers_match_per_call_turn(nn):
+    """Several layers' weights turned in one launch (fdtd_nn_rot_weights)
+    land where the per-call turn of each data gradient puts them, so a data
+    gradient given the turned weights (wt = NULL) is the same, bit for bit;
+    entries between the layers are left alone."""
+    g = torch.Generator().manual_seed(53)
+    layers, ws, o = [], [], 0
+    for cin, cout in [(5, 70), (32, 64), (96, 64), (256, 256), (64, 1)]:
+        o = (o + 7) // 8 * 8 + 3 * 8  # gaps between the layers
+        layers.append((cin, cout, o))
+        ws.append(bf16_round(torch.randn(cout, cin, 3, 3, generator=g) / math.sqrt(cin * 9)))
+        o += cout * cin * 9
+    flat = torch.zeros(o, dtype=torch.int16)
+    for (cin, cout, off), wt in zip(layers, ws):
+        flat[off:off + cout * cin * 9] = bits(to_krsc(wt)).reshape(-1).cpu()
+    w = flat.cuda()
+    wrot = torch.full((o,), 0x1234, dtype=torch.int16, device="cuda")
+    nn.rot_weights(layers, w, wrot)
+    used = torch.zeros(o, dtype=torch.bool)
+    for (cin, cout, off), wt in zip(layers, ws):
+        m = cout * cin * 9
+        one = torch.empty(m, dtype=torch.int16, device="cuda")
+        n, h, wd = 2, 16, 24
+        dz = bits(to_cn(bf16_round(torch.randn(n, cout, h, wd, generator=g))))
+        dx1 = torch.empty(cin * n * h * wd, device="cuda")
+        dx2 = torch.empty_like(dx1)
+        nn.conv3x3_dgrad(dz, w[off:off + m], one, dx1, n, cin, cout, h, wd)
+        nn.conv3x3_dgrad(dz, None, wrot[off:off + m], dx2, n, cin, cout, h, wd)
+        torch.cuda.synchronize()
+        assert torch.equal(wrot[off:off + m].cpu(), one.cpu())
+        assert torch.equal(dx1.cpu(), dx2.cpu())
+        used[off:off + m] = True
+    assert bool((wrot.cpu()[~used] == 0x1234).all())
+    with pytest.raises(nn.FDTDError):
+        nn.rot_weights([(0, 4, 0)], w, wrot)
+    with pytest.raises(nn.FDTDError):
+        nn.rot_weights([(1, 1, 0)] * 33, w, wrot)
+
+
 @pytest.mark.parametrize("n,cin,cout,h,w", [(4, 32, 32, 32, 32), (2, 64, 96, 16, 32), (7, 32, 16, 8, 16),
                                              (4, 1, 32, 16, 128)])
 def test_wgrad_contiguous_bias_single_reduction(nn, n, cin, cout, h, w):
