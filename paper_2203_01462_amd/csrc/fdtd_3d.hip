@@ -654,7 +654,7 @@ step3d_general_fwd(const Step3D<float> p, const int n, const int *__restrict__ l
 
 // ---------------------------------------------------------------- plain
 // Background dielectric only, identical for the forward and the adjoint.
-// Launched after step3d_general in the same step, so where plane k-1 was
+// Launched after the general update of the same step, so where plane k-1 was
 // general its new H is read back from the write copy.  Its own tiling
 // (64 x 8 columns, 4-plane chunks) covers the bounding box of the plain
 // tile-planes only; each lane takes the nodes whose general-kernel
@@ -1244,8 +1244,8 @@ void launch_step3d(const Step3D<T> &p, T *rd, T *wr, int n, bool adjoint, hipStr
   Step3D<T> q = p;  // copy 0 is read, copy 1 written
   q.A[0] = rd;
   q.A[1] = wr;
-  // the general tile-chunks (three launches by what they need), then the
-  // plain ones, which read back the new H of a general plane below them
+  // the general tile-chunks (one launch, or three by what they need), then
+  // the plain ones, which read back the new H of a general plane below them
   if (adjoint) launch_general<T, true>(q, n, s, aux);
   else launch_general<T, false>(q, n, s, aux);
   int pbx, pby, pbz;

@@ -129,10 +129,11 @@ std::vector<int> gen3d_plan(const Step3D<T> &p, int &nS, int &nM, int &nD, int &
 template <typename T>
 void plain3d_box(const Step3D<T> &p, int pb[6]);
 
-// A second stream and two events (created without timing) of a context: the
-// general launches over multi-axis and design chunks run on `stream`
-// beside the single-axis launch on the main stream, joined before the plain
-// launch.  A null stream keeps all launches on the main stream.
+// A second stream and two events (created without timing) of a context:
+// where the general update is three launches (the adjoint, FP64), the one
+// over multi-axis chunks runs on `stream` beside the design and single-axis
+// launches on the main stream, joined before the plain launch.  A null
+// stream keeps all launches on the main stream.
 struct Aux3D {
   hipStream_t stream;
   hipEvent_t fork, join;
