@@ -49,8 +49,8 @@ MEASURED_TRAFFIC = {
                          "profile": "profiles/step2d_batch_mix_kernel_tmz2d_batch64_c4.md"},
     # one time step = the general update (forward: one step3d_general_fwd
     # launch; adjoint: three step3d_general launches) + step3d_plain
-    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "7d0660558e7609bc",
-                       "fwd": 1302.4e6, "adj": 1337.2e6,
+    "yee3d_256_fp32": {"sources": SRC_3D, "sha256_16": "fcb7428c015ddb5e",
+                       "fwd": 1302.2e6, "adj": 1337.0e6,
                        "profile": "profiles/step3d_yee3d_256_fp32.md"},
     # one time step = one step_te_fwd / step_te_adj launch
     "te2d_2048_fp32": {"sources": SRC_TE, "sha256_16": "7894ca2a1bac6bae",

@@ -19,10 +19,10 @@
 // (absorber, walls, injection faces, Drude design edges, gap) are "general".
 // One step is the general update over three host-built lists of
 // tile-chunks (one absorber axis or none; several axes; design and gap) --
-// one launch of step3d_general_fwd in the FP32 forward, else three
-// launches of step3d_general, the multi-axis one on a second stream -- then
-// step3d_plain, which reads back the general update's new H where a plain
-// plane sits on a general one.  The general path keeps its cost down by
+// one launch of step3d_general_fwd in the FP32 forward (design box clear of
+// the absorber), else three launches of step3d_general, the multi-axis one
+// on a second stream -- then step3d_plain, which reads back the general
+// update's new H where a plain plane sits on a general one.  The general path keeps its cost down by
 // loading each group of absorber memories only in tiles/planes that reach
 // that absorber (uniform branches), by addressing the whole state of a copy
 // through one base pointer with 32-bit offsets, and by CPML tables that are
@@ -635,12 +635,14 @@ step3d_general(const Step3D<T> p, const int n, const int *__restrict__ list) {
 }
 
 // The FP32 forward's three lists in one launch, in list order (single-axis,
-// multi-axis, design): workgroup b takes entry b, and the body follows the
-// list the entry sits in (a uniform branch).  Each list's length is a
-// multiple of 8, so every entry keeps the XCD slot its list gave it.  At 4
-// waves per SIMD the union of the three bodies spills a few registers;
-// measured on the 256^3 workload it still beats the three launches on two
-// streams, whose fork and join each left the machine idle for ~6 us.
+// multi-axis, design), when no design chunk reaches the absorber (gAxD = 0):
+// workgroup b takes entry b, and the body follows the list the entry sits in
+// (a uniform branch).  Each list's length is a multiple of 8, so every entry
+// keeps the XCD slot its list gave it.  The union of the bodies fits 4 waves
+// per SIMD (119 VGPRs; with the design-with-absorber body as well it needed
+// 137 and spilled at 128).  Measured on the 256^3 workload it beats the
+// three launches on two streams, whose fork and join each left the machine
+// idle for ~6 us.
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 step3d_general_fwd(const Step3D<float> p, const int n, const int *__restrict__ list) {
   const int b = blockIdx.x;
@@ -648,7 +650,6 @@ step3d_general_fwd(const Step3D<float> p, const int n, const int *__restrict__ l
   if (code < 0) return;
   if (b < p.gS) general_body<float, false, false, 8>(p, n, code);
   else if (b < p.gS + p.gM) general_body<float, false, false, 7>(p, n, code);
-  else if (p.gAxD) general_body<float, false, true, 7>(p, n, code);
   else general_body<float, false, true, 0>(p, n, code);
 }
 
@@ -1204,7 +1205,8 @@ std::vector<int> plan3d_super(const Step3D<T> &p, int so[3], int sn[3], std::vec
 
 // The three general lists write disjoint tile-chunks of the write copy and
 // read only the read copy, so they may run in any order or side by side.
-// FP32 forward: one launch over all three.  Otherwise three launches: the
+// FP32 forward with no design chunk in the absorber: one launch over all
+// three.  Otherwise three launches: the
 // multi-axis list on the second stream, beside the design list and then the
 // single-axis list on the context stream (the order measured fastest for
 // the FP32 adjoint, whose multi-axis body is the longest).
@@ -1213,7 +1215,7 @@ static void launch_general(const Step3D<T> &q, int n, hipStream_t s, const Aux3D
   const int *L = q.glist;
   if constexpr (std::is_same<T, float>::value && !ADJ) {
     const int tot = q.gS + q.gM + q.gD;
-    if (FDTD3D_MERGE && tot > 0) {
+    if (FDTD3D_MERGE && tot > 0 && !q.gAxD) {
       hipLaunchKernelGGL(step3d_general_fwd, dim3(tot), dim3(NT), 0, s, q, n, L);
       return;
     }
