@@ -3,7 +3,8 @@ against the per-cell model written out by hand (each array read once and
 written once per step; FP32): 2D 24 B per cell (E_z, H_x, H_y) + 8 B per
 absorber-memory pair over the CPML strips + design-edge bytes; 3D 48 B per
 cell + 8 B per memory pair (4 pairs per slab direction) + design-edge bytes.
-Also the one-GPU contract of the command line."""
+Also the one-GPU contract of the command line, and that the counter-measured
+traffic records belong to the sources as they stand."""
 import os
 import subprocess
 import sys
@@ -38,6 +39,17 @@ def test_c3_bytes_per_step():
     assert bench.algorithmic_bytes(w, True) == adj
     # the figures the 3D bench line and its profile quote
     assert round(fwd / 1e6, 1) == 1027.6 and round(adj / 1e6, 1) == 1052.8
+
+
+def test_measured_traffic_records_match_sources_and_profiles():
+    """Every counter-measured traffic record was taken on the kernel sources
+    as they stand (so bench.py reports it rather than null), and the profile
+    summary it cites names the same source hash."""
+    for name, rec in bench.MEASURED_TRAFFIC.items():
+        assert bench.sources_sha(rec["sources"]) == rec["sha256_16"], name
+        with open(os.path.join(ROOT, rec["profile"])) as f:
+            assert rec["sha256_16"] in f.read(), name
+        assert 0 < rec["fwd"] and 0 < rec["adj"], name
 
 
 def test_bench_refuses_more_than_one_gpu():
